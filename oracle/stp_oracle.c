@@ -1,0 +1,468 @@
+/*
+ * stp_oracle.c -- plain FP64 CPU oracle for the element-local space-time predictor (STP) of the
+ * linear ADER-DG scheme of Gallard, Rannabauer, Reinarz, Bader (arXiv:2003.12787).
+ *
+ * TEST INFRASTRUCTURE. Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark
+ * load this library. The product (the HIP library under paper_2003_12787_amd/) never calls it, includes
+ * nothing from it and shares no code, tables or generators with it. The oracle computes its own
+ * quadrature nodes, derivative matrix and face vectors.
+ *
+ * Every function is written for clarity, not speed: plain loops, FP64, no blocking, no fusion.
+ *
+ * Conventions (readings of the paper, each listed in the design doc):
+ *   - N is the polynomial degree; n = N+1 Gauss-Legendre nodes per axis (Sec. II-A, nodal tensor basis).
+ *   - Reference element [0,1]^3, physical derivative = reference derivative / h.
+ *   - Nodal data u[node][s] with node = (z*n + y)*n + x, the quantity index s fastest (the AoS tensor
+ *     Q[k1][k2][k3][s] of Sec. III-B, k1 = z, k2 = y, k3 = x).
+ *   - D[i][j] = l_j'(xi_i): row = output node, column = input node (Sec. III-B, dF = sum_l D[k3][l] F[..l..]).
+ *   - The PDE is q_t + sum_d (A_d q)_{x_d} + B_d dq/dx_d = 0 (Eq. (1) with the material matrix absorbed
+ *     into B_d and the sign moved to the left-hand side). The volume operator is
+ *         V(u) = sum_d V_d(u),  V_d(u) = -(1/h) [ D x_d (A_d o u) + B_d o (D x_d u) ]
+ *     where "D x_d" contracts spatial axis d and "o" is the nodewise m x m matrix-vector product.
+ *   - Cauchy-Kowalewsky Taylor loop, Eq. (4) and the recursion p_o = V p_{o-1} below it, with N+1 terms
+ *     o = 0..N. The outputs are time AVERAGES: weights dt^o/(o+1)!, i.e. Eq. (4)'s integral divided by dt.
+ *   - Optional point source (Eq. (1) delta term; Fig. 1 first and last statements of the time loop):
+ *         p_0 = Q,  p_{o+1} = V p_o + S_o,  S_o[node][s] = P[node] * a[s] * sigma^(o)(t_n).
+ *   - favg[d] is the time average of V_d(p(t)), accumulated as in Fig. 1 (sum_o w_o V_d(p_o)). The same
+ *     quantity recomputed from q-bar by linearity (Fig. 5, V_d(q-bar)) is returned separately on request.
+ *   - Faces f = x-, x+, y-, y+, z-, z+ (reference coordinate 0 or 1 along the normal); face data
+ *     [f][a][b][s] with (a, b) the two remaining axes, slower first: (z,y), (z,x), (y,x).
+ *   - qface = q-bar extrapolated to each face; fface = (A_{d_f} o q-bar) extrapolated (only if A present).
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+#include <unistd.h>
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ENOMEM (-3)
+
+enum { OR_ACOUSTIC = 0, OR_ELASTIC = 1, OR_GENERIC = 2 };
+
+/* ------------------------------------------------------------------------------------------------ */
+/* 1D basis: Gauss-Legendre nodes on [0,1] (Sec. II-A: nodal Lagrange basis on Gauss-Legendre points). */
+
+/* Legendre polynomial P_n(x) and its derivative by the three-term recurrence
+ * (k+1) P_{k+1} = (2k+1) x P_k - k P_{k-1}. */
+static void legendre_eval(int n, long double x, long double* pn, long double* dpn)
+{
+    long double p0 = 1.0L, p1 = x;
+    if (n == 0) { *pn = 1.0L; *dpn = 0.0L; return; }
+    for (int k = 1; k < n; ++k) {
+        long double p2 = ((2.0L * k + 1.0L) * x * p1 - (long double)k * p0) / (long double)(k + 1);
+        p0 = p1;
+        p1 = p2;
+    }
+    *pn = p1;
+    /* P_n'(x) = n (x P_n - P_{n-1}) / (x^2 - 1); the nodes are interior so x^2 != 1. */
+    *dpn = (long double)n * (x * p1 - p0) / (x * x - 1.0L);
+}
+
+/* n Gauss-Legendre nodes xi[0..n) ascending on [0,1] and their weights w (summing to 1). */
+int oracle_gl_nodes(int n, double* xi, double* w)
+{
+    if (n < 1 || n > 64 || !xi || !w) return OR_EINVAL;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int i = 0; i < n; ++i) {
+        /* Newton from the classical cosine guess; roots of P_n in descending order for i = 0..n-1. */
+        long double x = cosl(pi * ((long double)i + 0.75L) / ((long double)n + 0.5L));
+        long double pn = 0, dpn = 1;
+        for (int it = 0; it < 100; ++it) {
+            legendre_eval(n, x, &pn, &dpn);
+            long double dx = pn / dpn;
+            x -= dx;
+            if (fabsl(dx) < 1e-19L) break;
+        }
+        legendre_eval(n, x, &pn, &dpn);
+        long double wx = 2.0L / ((1.0L - x * x) * dpn * dpn); /* weight on [-1,1] */
+        int j = n - 1 - i;                                    /* ascending order */
+        xi[j] = (double)((1.0L + x) * 0.5L);
+        w[j] = (double)(wx * 0.5L);
+    }
+    return OR_OK;
+}
+
+/* Lagrange basis l_j(x) for the nodes xi, evaluated at x, by the product formula. */
+int oracle_lagrange_at(int n, const double* xi, double x, double* l)
+{
+    if (n < 1 || !xi || !l) return OR_EINVAL;
+    for (int j = 0; j < n; ++j) {
+        long double v = 1.0L;
+        for (int k = 0; k < n; ++k)
+            if (k != j) v *= ((long double)x - xi[k]) / ((long double)xi[j] - xi[k]);
+        l[j] = (double)v;
+    }
+    return OR_OK;
+}
+
+/* Derivative matrix D[i*n+j] = l_j'(xi_i) (Sec. II-A "discrete derivative operator"), by barycentric
+ * weights beta_j = 1/prod_{k!=j}(xi_j - xi_k): off-diagonal (beta_j/beta_i)/(xi_i - xi_j); the diagonal is
+ * minus the off-diagonal row sum (derivative of a constant is zero). */
+int oracle_dmatrix(int n, const double* xi, double* D)
+{
+    if (n < 1 || !xi || !D) return OR_EINVAL;
+    long double beta[64];
+    for (int j = 0; j < n; ++j) {
+        long double prod = 1.0L;
+        for (int k = 0; k < n; ++k)
+            if (k != j) prod *= ((long double)xi[j] - xi[k]);
+        beta[j] = 1.0L / prod;
+    }
+    for (int i = 0; i < n; ++i) {
+        long double diag = 0.0L;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            long double v = (beta[j] / beta[i]) / ((long double)xi[i] - xi[j]);
+            D[i * n + j] = (double)v;
+            diag -= v;
+        }
+        D[i * n + i] = (double)diag;
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------------------------------ */
+/* Tensor contraction along one spatial axis (Sec. III-B): out[..i..][s] = sum_j M[i][j] u[..j..][s],
+ * axis 0 = x (fastest node index), 1 = y, 2 = z. */
+int oracle_contract(int n, int m, const double* M, int axis, const double* u, double* out)
+{
+    if (n < 1 || m < 1 || axis < 0 || axis > 2 || !M || !u || !out) return OR_EINVAL;
+    for (int z = 0; z < n; ++z)
+        for (int y = 0; y < n; ++y)
+            for (int x = 0; x < n; ++x) {
+                int i = axis == 0 ? x : (axis == 1 ? y : z);
+                for (int s = 0; s < m; ++s) {
+                    double acc = 0.0;
+                    for (int j = 0; j < n; ++j) {
+                        int zz = axis == 2 ? j : z, yy = axis == 1 ? j : y, xx = axis == 0 ? j : x;
+                        acc += M[i * n + j] * u[((zz * n + yy) * n + xx) * m + s];
+                    }
+                    out[((z * n + y) * n + x) * m + s] = acc;
+                }
+            }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------------------------------ */
+/* Physics presets: the non-conservative matrices B_d (row = equation, column = differentiated quantity)
+ * of one node, from its material parameters. The paper names the elastic system (Sec. VI) and gives no
+ * matrices; these follow from the textbook first-order systems written as q_t + sum_d B_d q_{x_d} = 0.
+ *   acoustic, q = (p, v_x, v_y, v_z), par = (rho, K):   p_t + K div v = 0,  v_t + grad p / rho = 0.
+ *   elastic,  q = (v_x, v_y, v_z, s_xx, s_yy, s_zz, s_xy, s_yz, s_xz), par = (rho, lambda, mu):
+ *             rho v_t = div sigma,  sigma_t = lambda (div v) I + mu (grad v + grad v^T). */
+static int stress_index(int i, int j)
+{
+    if (i == j) return 3 + i;
+    int a = i < j ? i : j, b = i < j ? j : i;
+    if (a == 0 && b == 1) return 6; /* xy */
+    if (a == 1 && b == 2) return 7; /* yz */
+    return 8;                       /* xz */
+}
+
+int oracle_preset_B(int physics, int m, const double* par, double* B3)
+{
+    if (!par || !B3) return OR_EINVAL;
+    if (physics == OR_ACOUSTIC) {
+        if (m != 4) return OR_EINVAL;
+        double rho = par[0], K = par[1];
+        memset(B3, 0, sizeof(double) * 3 * 16);
+        for (int d = 0; d < 3; ++d) {
+            double* B = B3 + d * 16;
+            B[0 * 4 + (1 + d)] = K;
+            B[(1 + d) * 4 + 0] = 1.0 / rho;
+        }
+        return OR_OK;
+    }
+    if (physics == OR_ELASTIC) {
+        if (m != 9) return OR_EINVAL;
+        double rho = par[0], lam = par[1], mu = par[2];
+        memset(B3, 0, sizeof(double) * 3 * 81);
+        for (int d = 0; d < 3; ++d) {
+            double* B = B3 + d * 81;
+            for (int i = 0; i < 3; ++i) B[i * 9 + stress_index(i, d)] = -1.0 / rho; /* v_i <- d_d s_id */
+            for (int i = 0; i < 3; ++i)
+                B[(3 + i) * 9 + d] = (i == d) ? -(lam + 2.0 * mu) : -lam;           /* s_ii <- d_d v_d */
+            for (int i = 0; i < 3; ++i)
+                if (i != d) B[stress_index(d, i) * 9 + i] = -mu;                     /* s_di <- d_d v_i */
+        }
+        return OR_OK;
+    }
+    return OR_EINVAL;
+}
+
+/* ------------------------------------------------------------------------------------------------ */
+/* The volume operator of one direction, Sec. II-A "volume term":
+ *   V_d(u) = -(1/h) [ D x_d (A_d o u) + B_d o (D x_d u) ]
+ * Ad, Bd: [n^3][m][m] per node (may be NULL for A). work: 2*n^3*m doubles. */
+static void apply_Vd(int n, int m, const double* D, double h, int d, const double* Ad, const double* Bd,
+                     const double* u, double* out, double* work)
+{
+    const int nn = n * n * n;
+    double* flux = work;
+    double* grad = work + (size_t)nn * m;
+    for (int k = 0; k < nn * m; ++k) out[k] = 0.0;
+    if (Ad) {
+        /* conservative flux F_d = A_d u at every node, then its derivative along d */
+        for (int k = 0; k < nn; ++k)
+            for (int s = 0; s < m; ++s) {
+                double acc = 0.0;
+                for (int r = 0; r < m; ++r) acc += Ad[((size_t)k * m + s) * m + r] * u[k * m + r];
+                flux[k * m + s] = acc;
+            }
+        oracle_contract(n, m, D, d, flux, grad);
+        for (int k = 0; k < nn * m; ++k) out[k] -= grad[k] / h;
+    }
+    /* non-conservative product B_d grad_d u */
+    oracle_contract(n, m, D, d, u, grad);
+    for (int k = 0; k < nn; ++k)
+        for (int s = 0; s < m; ++s) {
+            double acc = 0.0;
+            for (int r = 0; r < m; ++r) acc += Bd[((size_t)k * m + s) * m + r] * (grad[k * m + r] / h);
+            out[k * m + s] -= acc;
+        }
+}
+
+/* Exported: V_d(u) for one element with explicit per-node matrices (A may be NULL). out: [n^3][m]. */
+int oracle_apply_Vd(int N, int m, double h, int d, const double* A3, const double* B3, const double* u,
+                    double* out)
+{
+    if (N < 0 || m < 1 || d < 0 || d > 2 || !(h > 0) || !B3 || !u || !out) return OR_EINVAL;
+    const int n = N + 1, nn = n * n * n;
+    double xi[64], w[64];
+    double* D = malloc(sizeof(double) * n * n);
+    double* work = malloc(sizeof(double) * 2 * (size_t)nn * m);
+    if (!D || !work) { free(D); free(work); return OR_ENOMEM; }
+    oracle_gl_nodes(n, xi, w);
+    oracle_dmatrix(n, xi, D);
+    const size_t msz = (size_t)nn * m * m;
+    apply_Vd(n, m, D, h, d, A3 ? A3 + d * msz : NULL, B3 + d * msz, u, out, work);
+    free(D);
+    free(work);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------------------------------ */
+/* Batched STP. */
+
+typedef struct {
+    int N, m, physics;
+    int has_A;            /* generic: conservative-flux matrices A_d present                          */
+    int coef_per_element; /* presets: params [e][np]; generic: A, B [e][3][m][m] (else per node)      */
+    int has_src;          /* point source present                                                     */
+    long nelem;
+    const double* Q;      /* [e][n^3][m]                                                              */
+    const double* params; /* presets: [e][n^3][np] (np = 2 acoustic, 3 elastic) or [e][np]            */
+    const double* A;      /* generic: [e][3][n^3][m][m] or [e][3][m][m]                               */
+    const double* B;      /* generic: same layout as A                                                */
+    const double* src;    /* [e][n^3 + m + N]: P[node], a[s], sigma^(o)(t_n) for o = 0..N-1           */
+    const double* dt;     /* [e]                                                                      */
+    const double* h;      /* [e]                                                                      */
+    double* qavg;         /* [e][n^3][m]                                                              */
+    double* favg;         /* [e][3][n^3][m]  (Fig. 1 accumulation)                                    */
+    double* qface;        /* [e][6][n^2][m]                                                           */
+    double* fface;        /* [e][6][n^2][m]  (only if has_A; may be NULL otherwise)                   */
+    double* favg_fig5;    /* optional [e][3][n^3][m]: V_d(q-bar) (Fig. 5 recompute); may be NULL      */
+    int nthreads;         /* 0 = all online cores                                                     */
+} oracle_args;
+
+typedef struct {
+    const oracle_args* a;
+    long e0, e1;
+    const double* D;
+    const double* e0v;
+    const double* e1v;
+    int status;
+} worker_t;
+
+static int np_of(int physics) { return physics == OR_ACOUSTIC ? 2 : (physics == OR_ELASTIC ? 3 : 0); }
+
+/* Per-element matrices A_d, B_d at every node ([3][n^3][m][m]). */
+static void element_matrices(const oracle_args* a, long e, int nn, double* A3, double* B3)
+{
+    const int m = a->m;
+    const size_t msz = (size_t)m * m;
+    if (a->physics == OR_GENERIC) {
+        for (int d = 0; d < 3; ++d)
+            for (int k = 0; k < nn; ++k) {
+                size_t dst = ((size_t)d * nn + k) * msz;
+                size_t src = a->coef_per_element ? ((size_t)e * 3 + d) * msz
+                                                 : (((size_t)e * 3 + d) * nn + k) * msz;
+                memcpy(B3 + dst, a->B + src, sizeof(double) * msz);
+                if (a->has_A) memcpy(A3 + dst, a->A + src, sizeof(double) * msz);
+            }
+        return;
+    }
+    const int np = np_of(a->physics);
+    double Bn[3 * 81];
+    for (int k = 0; k < nn; ++k) {
+        const double* par = a->coef_per_element ? a->params + (size_t)e * np : a->params + ((size_t)e * nn + k) * np;
+        oracle_preset_B(a->physics, m, par, Bn);
+        for (int d = 0; d < 3; ++d) memcpy(B3 + ((size_t)d * nn + k) * msz, Bn + d * msz, sizeof(double) * msz);
+    }
+}
+
+/* Face extrapolation of nodal data u [n^3][m] into out [6][n^2][m] with vectors e0 = l(0), e1 = l(1). */
+static void extrapolate_faces(int n, int m, const double* e0v, const double* e1v, const double* u, double* out)
+{
+    for (int f = 0; f < 6; ++f) {
+        const int axis = f / 2;
+        const double* ev = (f % 2) ? e1v : e0v;
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b)
+                for (int s = 0; s < m; ++s) {
+                    double acc = 0.0;
+                    for (int j = 0; j < n; ++j) {
+                        int z, y, x;
+                        if (axis == 0) { z = a; y = b; x = j; }
+                        else if (axis == 1) { z = a; y = j; x = b; }
+                        else { z = j; y = a; x = b; }
+                        acc += ev[j] * u[((z * n + y) * n + x) * m + s];
+                    }
+                    out[((size_t)f * n * n + a * n + b) * m + s] = acc;
+                }
+    }
+}
+
+static void* stp_worker(void* arg)
+{
+    worker_t* wk = (worker_t*)arg;
+    const oracle_args* a = wk->a;
+    const int N = a->N, n = N + 1, m = a->m, nn = n * n * n;
+    const size_t vol = (size_t)nn * m, msz = (size_t)m * m;
+    double* p = malloc(sizeof(double) * vol * (size_t)(N + 2));   /* p[o], o = 0..N+1 (Fig. 1)       */
+    double* dF = malloc(sizeof(double) * vol * 3 * (size_t)(N + 1)); /* dF[o][d] = V_d(p[o])          */
+    double* A3 = a->has_A ? malloc(sizeof(double) * 3 * nn * msz) : NULL;
+    double* B3 = malloc(sizeof(double) * 3 * nn * msz);
+    double* work = malloc(sizeof(double) * 2 * vol);
+    double* afl = malloc(sizeof(double) * vol);
+    if (!p || !dF || !B3 || !work || !afl || (a->has_A && !A3)) {
+        wk->status = OR_ENOMEM;
+        goto done;
+    }
+    for (long e = wk->e0; e < wk->e1; ++e) {
+        const double h = a->h[e], dt = a->dt[e];
+        element_matrices(a, e, nn, A3, B3);
+        const double* Q = a->Q + (size_t)e * vol;
+        const double* src = a->has_src ? a->src + (size_t)e * (nn + m + N) : NULL;
+
+        /* Fig. 1: p[0] = q; for each Taylor order, flux derivatives and NCP per direction, then p[o+1]. */
+        memcpy(p, Q, sizeof(double) * vol);
+        for (int o = 0; o <= N; ++o) {
+            for (int d = 0; d < 3; ++d)
+                apply_Vd(n, m, wk->D, h, d, A3 ? A3 + (size_t)d * nn * msz : NULL, B3 + (size_t)d * nn * msz,
+                         p + (size_t)o * vol, dF + ((size_t)o * 3 + d) * vol, work);
+            if (o < N) {
+                double* pn = p + (size_t)(o + 1) * vol;
+                for (size_t k = 0; k < vol; ++k) pn[k] = 0.0;
+                if (src) /* time derivative of order o of the point source, projected on the nodes */
+                    for (int k = 0; k < nn; ++k)
+                        for (int s = 0; s < m; ++s) pn[k * m + s] += src[k] * src[nn + s] * src[nn + m + o];
+                for (int d = 0; d < 3; ++d) {
+                    const double* df = dF + ((size_t)o * 3 + d) * vol;
+                    for (size_t k = 0; k < vol; ++k) pn[k] += df[k];
+                }
+            }
+        }
+
+        /* time averages: weights dt^o / (o+1)!, o = 0..N (Eq. (4) divided by dt) */
+        double* qavg = a->qavg + (size_t)e * vol;
+        double* favg = a->favg + (size_t)e * 3 * vol;
+        for (size_t k = 0; k < vol; ++k) qavg[k] = 0.0;
+        for (size_t k = 0; k < 3 * vol; ++k) favg[k] = 0.0;
+        double wo = 1.0; /* dt^0 / 1! */
+        for (int o = 0; o <= N; ++o) {
+            const double* po = p + (size_t)o * vol;
+            for (size_t k = 0; k < vol; ++k) qavg[k] += wo * po[k];
+            for (int d = 0; d < 3; ++d) {
+                const double* df = dF + ((size_t)o * 3 + d) * vol;
+                for (size_t k = 0; k < vol; ++k) favg[d * vol + k] += wo * df[k];
+            }
+            wo *= dt / (double)(o + 2);
+        }
+
+        /* Fig. 5: the time-averaged fluxes recomputed from q-bar by linearity */
+        if (a->favg_fig5) {
+            double* f5 = a->favg_fig5 + (size_t)e * 3 * vol;
+            for (int d = 0; d < 3; ++d)
+                apply_Vd(n, m, wk->D, h, d, A3 ? A3 + (size_t)d * nn * msz : NULL, B3 + (size_t)d * nn * msz,
+                         qavg, f5 + (size_t)d * vol, work);
+        }
+
+        /* projection onto the six faces (Sec. II-B: one matrix product per face) */
+        extrapolate_faces(n, m, wk->e0v, wk->e1v, qavg, a->qface + (size_t)e * 6 * n * n * m);
+        if (a->has_A && a->fface) {
+            double* ff = a->fface + (size_t)e * 6 * n * n * m;
+            for (int f = 0; f < 6; ++f) {
+                const int d = f / 2;
+                const double* Ad = A3 + (size_t)d * nn * msz;
+                for (int k = 0; k < nn; ++k)
+                    for (int s = 0; s < m; ++s) {
+                        double acc = 0.0;
+                        for (int r = 0; r < m; ++r) acc += Ad[((size_t)k * m + s) * m + r] * qavg[k * m + r];
+                        afl[k * m + s] = acc;
+                    }
+                double tmp_faces[6 * 100 * 16];
+                extrapolate_faces(n, m, wk->e0v, wk->e1v, afl, tmp_faces);
+                memcpy(ff + (size_t)f * n * n * m, tmp_faces + (size_t)f * n * n * m, sizeof(double) * n * n * m);
+            }
+        }
+    }
+done:
+    free(p);
+    free(dF);
+    free(A3);
+    free(B3);
+    free(work);
+    free(afl);
+    return NULL;
+}
+
+int oracle_stp(const oracle_args* a)
+{
+    if (!a || a->N < 0 || a->N > 20 || a->m < 1 || a->m > 16 || a->nelem < 0) return OR_EINVAL;
+    if (a->physics == OR_ACOUSTIC && a->m != 4) return OR_EINVAL;
+    if (a->physics == OR_ELASTIC && a->m != 9) return OR_EINVAL;
+    if (a->physics != OR_GENERIC && a->has_A) return OR_EINVAL;
+    if (a->physics < 0 || a->physics > 2) return OR_EINVAL;
+    if (a->nelem == 0) return OR_OK;
+    if (!a->Q || !a->dt || !a->h || !a->qavg || !a->favg || !a->qface) return OR_EINVAL;
+    if (a->physics == OR_GENERIC ? (!a->B || (a->has_A && (!a->A || !a->fface))) : !a->params) return OR_EINVAL;
+    if (a->has_src && !a->src) return OR_EINVAL;
+    if (a->has_A && (a->N + 1) * (a->N + 1) * a->m > 100 * 16) return OR_EINVAL;
+    for (long e = 0; e < a->nelem; ++e)
+        if (!(a->h[e] > 0) || !(a->dt[e] >= 0)) return OR_EINVAL;
+
+    const int n = a->N + 1;
+    double xi[64], w[64], D[64 * 64], e0v[64], e1v[64];
+    oracle_gl_nodes(n, xi, w);
+    oracle_dmatrix(n, xi, D);
+    oracle_lagrange_at(n, xi, 0.0, e0v);
+    oracle_lagrange_at(n, xi, 1.0, e1v);
+
+    long nt = a->nthreads > 0 ? a->nthreads : sysconf(_SC_NPROCESSORS_ONLN);
+    if (nt < 1) nt = 1;
+    if (nt > a->nelem) nt = a->nelem;
+    if (nt > 256) nt = 256;
+    pthread_t th[256];
+    worker_t wk[256];
+    for (long t = 0; t < nt; ++t) {
+        wk[t].a = a;
+        wk[t].e0 = a->nelem * t / nt;
+        wk[t].e1 = a->nelem * (t + 1) / nt;
+        wk[t].D = D;
+        wk[t].e0v = e0v;
+        wk[t].e1v = e1v;
+        wk[t].status = OR_OK;
+    }
+    for (long t = 1; t < nt; ++t) pthread_create(&th[t], NULL, stp_worker, &wk[t]);
+    stp_worker(&wk[0]);
+    for (long t = 1; t < nt; ++t) pthread_join(th[t], NULL);
+    for (long t = 0; t < nt; ++t)
+        if (wk[t].status != OR_OK) return wk[t].status;
+    return OR_OK;
+}
+
+/* Number of worker threads oracle_stp would use for nelem elements when nthreads == 0. */
+int oracle_default_threads(void) { return (int)sysconf(_SC_NPROCESSORS_ONLN); }

@@ -1,0 +1,182 @@
+"""Seeded synthetic inputs shaped like the paper's workloads (elastic / acoustic waves).
+
+This module holds input recipes only: random materials, random or plane-wave DOFs, element sizes and the
+CFL time-step rule. It contains none of the predictor's arithmetic, and both the oracle tests and the HIP
+path draw their inputs from it. Everything is generated in FP64 with ``numpy.random.default_rng(seed)``;
+reduced-precision runs round these values to the I/O dtype and the oracle is then run on the rounded
+values.
+
+The paper's benchmark (LOH1 on a curvilinear mesh, m = 21) is not available; these inputs stand in for
+it with the same physics (first-order elastic velocity-stress, three material parameters per node).
+
+Quantity order: acoustic (p, v_x, v_y, v_z), params (rho, K); elastic (v_x, v_y, v_z, s_xx, s_yy, s_zz,
+s_xy, s_yz, s_xz), params (rho, lambda, mu). Nodal arrays are [element][z][y][x][quantity].
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+ACOUSTIC, ELASTIC, GENERIC = 0, 1, 2
+NQUANT = {ACOUSTIC: 4, ELASTIC: 9}
+NPARAM = {ACOUSTIC: 2, ELASTIC: 3}
+SEED0 = 2003127870
+
+
+@dataclasses.dataclass
+class Batch:
+    """One uniform-class batch of elements (FP64 host arrays)."""
+    N: int
+    m: int
+    physics: int
+    Q: np.ndarray                    # [E, n^3, m]
+    dt: np.ndarray                   # [E]
+    h: np.ndarray                    # [E]
+    params: np.ndarray | None = None  # presets: [E, n^3, np] or [E, np]
+    A: np.ndarray | None = None       # generic: [E, 3, n^3, m, m] or [E, 3, m, m]
+    B: np.ndarray | None = None       # generic: same layout as A
+    src: np.ndarray | None = None     # [E, n^3 + m + N]
+    coef_per_element: bool = False
+
+    @property
+    def nelem(self) -> int:
+        return self.Q.shape[0]
+
+
+def _node_positions(n: int) -> np.ndarray:
+    """Gauss-Legendre points on [0, 1] from numpy's library routine (used only to sample waves)."""
+    x, _ = np.polynomial.legendre.leggauss(n)
+    return 0.5 * (x + 1.0)
+
+
+def elastic_material(rng, shape):
+    """rho ~ U[2,3], lambda ~ U[1,4], mu ~ U[1,3] (per node or per element)."""
+    rho = rng.uniform(2.0, 3.0, shape)
+    lam = rng.uniform(1.0, 4.0, shape)
+    mu = rng.uniform(1.0, 3.0, shape)
+    return np.stack([rho, lam, mu], axis=-1)
+
+
+def cfl_dt(N: int, h: float, c: float, cfl: float = 0.4) -> float:
+    """dt = cfl * h / ((2N+1) c), the time-step rule of the workloads."""
+    return cfl * h / ((2 * N + 1) * c)
+
+
+def elastic_batch(N: int, nelem: int, seed: int, h: float = 1.0, per_node: bool = True,
+                  q_scale: float = 1.0) -> Batch:
+    """Elastic waves, m = 9: per-node material, Q ~ N(0, 1), dt from the fastest P-wave in the batch."""
+    rng = np.random.default_rng(seed)
+    n3 = (N + 1) ** 3
+    par = elastic_material(rng, (nelem, n3) if per_node else (nelem,))
+    Q = q_scale * rng.standard_normal((nelem, n3, 9))
+    cp = np.sqrt((par[..., 1] + 2 * par[..., 2]) / par[..., 0]).max() if nelem else 1.0
+    dt = np.full(nelem, cfl_dt(N, h, cp))
+    return Batch(N, 9, ELASTIC, Q, dt, np.full(nelem, h), params=par, coef_per_element=not per_node)
+
+
+def acoustic_plane_wave_batch(N: int, nelem: int, seed: int, h: float = 1.0, noise: float = 1e-2,
+                              grid: int | None = None) -> Batch:
+    """Acoustic waves, m = 4: rho = 1, K_e ~ U[1,2] per element; Q is a smooth plane wave
+    p = sin(k.x), v = k_hat p / (rho c_e), k = (2 pi / 8h) (1,2,2)/3, plus N(0, noise^2) per DOF.
+    Elements sit on a cubic grid (grid^3 >= nelem, x fastest)."""
+    rng = np.random.default_rng(seed)
+    n = N + 1
+    if grid is None:
+        grid = max(1, int(round(nelem ** (1.0 / 3.0))))
+        while grid ** 3 < nelem:
+            grid += 1
+    K = rng.uniform(1.0, 2.0, nelem)
+    rho = np.ones(nelem)
+    par = np.stack([rho, K], axis=-1)
+    c = np.sqrt(K / rho)
+    kvec = (2 * math.pi / (8 * h)) * np.array([1.0, 2.0, 2.0]) / 3.0
+    khat = kvec / np.linalg.norm(kvec)
+    xi = _node_positions(n)
+    e = np.arange(nelem)
+    ex, ey, ez = e % grid, (e // grid) % grid, e // (grid * grid)
+    Z, Y, X = np.meshgrid(xi, xi, xi, indexing="ij")  # node (z, y, x)
+    px = (ex[:, None] + X.reshape(1, -1)) * h
+    py = (ey[:, None] + Y.reshape(1, -1)) * h
+    pz = (ez[:, None] + Z.reshape(1, -1)) * h
+    phase = kvec[0] * px + kvec[1] * py + kvec[2] * pz
+    p = np.sin(phase)
+    v = khat[None, None, :] * (p / (rho * c))[:, :, None] if nelem else np.zeros((0, n ** 3, 3))
+    Q = np.concatenate([p[..., None], v], axis=-1)
+    Q = Q + noise * rng.standard_normal(Q.shape)
+    dt = np.full(nelem, cfl_dt(N, h, c.max() if nelem else 1.0))
+    return Batch(N, 4, ACOUSTIC, Q, dt, np.full(nelem, h), params=par, coef_per_element=True)
+
+
+def acoustic_batch(N: int, nelem: int, seed: int, h: float = 1.0, per_node: bool = True) -> Batch:
+    """Acoustic waves with random per-node material rho ~ U[2,3], K ~ U[1,2] and Q ~ N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    n3 = (N + 1) ** 3
+    shape = (nelem, n3) if per_node else (nelem,)
+    par = np.stack([rng.uniform(2.0, 3.0, shape), rng.uniform(1.0, 2.0, shape)], axis=-1)
+    Q = rng.standard_normal((nelem, n3, 4))
+    c = np.sqrt(par[..., 1] / par[..., 0]).max() if nelem else 1.0
+    dt = np.full(nelem, cfl_dt(N, h, c))
+    return Batch(N, 4, ACOUSTIC, Q, dt, np.full(nelem, h), params=par, coef_per_element=not per_node)
+
+
+def generic_batch(N: int, m: int, nelem: int, seed: int, h: float = 1.0, with_A: bool = False,
+                  per_node: bool = True) -> Batch:
+    """Generic linear system: dense B_d (and optionally A_d) with entries ~ N(0, 1/m) per node,
+    Q ~ N(0, 1); dt_e from c_e = max over nodes and directions of the Frobenius norm of B_d."""
+    rng = np.random.default_rng(seed)
+    n3 = (N + 1) ** 3
+    shape = (nelem, 3, n3, m, m) if per_node else (nelem, 3, m, m)
+    B = rng.standard_normal(shape) / math.sqrt(m)
+    A = rng.standard_normal(shape) / math.sqrt(m) if with_A else None
+    Q = rng.standard_normal((nelem, n3, m))
+    axes = tuple(range(1, B.ndim))
+    cB = np.sqrt((B ** 2).sum(axis=(-1, -2)))
+    c = cB.reshape(nelem, -1).max(axis=1) if nelem else np.ones(0)
+    if with_A:
+        cA = np.sqrt((A ** 2).sum(axis=(-1, -2))).reshape(nelem, -1).max(axis=1)
+        c = c + cA
+    del axes
+    dt = np.array([cfl_dt(N, h, ci) for ci in c])
+    return Batch(N, m, GENERIC, Q, dt, np.full(nelem, h), A=A, B=B, coef_per_element=not per_node)
+
+
+def point_source(batch: Batch, seed: int) -> np.ndarray:
+    """A point source per element: nodal projection P ~ U[0,1], amplitude a ~ N(0,1), and the time
+    derivatives sigma^(o)(t_n) ~ N(0,1) for o = 0..N-1. Layout [E, n^3 + m + N]."""
+    rng = np.random.default_rng(seed)
+    n3 = (batch.N + 1) ** 3
+    E = batch.nelem
+    return np.concatenate([rng.uniform(0, 1, (E, n3)), rng.standard_normal((E, batch.m)),
+                           rng.standard_normal((E, batch.N))], axis=1)
+
+
+# ------------------------------------------------------------------------------------------------
+# The named workloads (element counts as in the paper-shaped configurations).
+
+def c1_elastic_n3(seed: int = SEED0 + 0) -> Batch:
+    """Elastic, N=3, 64 elements, h=1, per-node material, FP64."""
+    return elastic_batch(3, 64, seed)
+
+
+def c2_acoustic_n5(nelem: int = 32768, seed: int = SEED0 + 1) -> Batch:
+    """Acoustic, N=5, 32768 = 32^3 elements, plane wave + noise."""
+    return acoustic_plane_wave_batch(5, nelem, seed, grid=32 if nelem == 32768 else None)
+
+
+def c3_elastic_n7(nelem: int = 65536, seed: int = SEED0 + 2) -> Batch:
+    """Elastic, N=7, 65536 elements, per-node material, Q ~ N(0,1)."""
+    return elastic_batch(7, nelem, seed)
+
+
+def c4_classes(nelem: int = 16384, seed: int = SEED0 + 3):
+    """Heterogeneous mix: N_e ~ U{2..9}, m_e ~ U{4, 9} independently. Returns (N[e], m[e])."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(2, 10, nelem), rng.choice(np.array([4, 9]), nelem)
+
+
+def serving_batch_sizes(nbatch: int, seed: int) -> np.ndarray:
+    """Log-uniform batch sizes floor(exp(U[0, ln 4097))) in 1..4096."""
+    rng = np.random.default_rng(seed)
+    return np.minimum(4096, np.floor(np.exp(rng.uniform(0, math.log(4097), nbatch))).astype(np.int64))
