@@ -1,0 +1,187 @@
+/*
+ * stp.h -- C ABI of libstp.so: the element-local space-time predictor (STP) of the linear ADER-DG scheme
+ * (Gallard, Rannabauer, Reinarz, Bader, arXiv:2003.12787) on AMD Instinct MI355X (gfx950).
+ *
+ * What one call computes (Sec. II-A, Eqs. (3)-(4) and the recursion below Eq. (4); Sec. II-B output
+ * contract). For every element e with DOFs Q_e, element size h_e and time step dt_e:
+ *
+ *   PDE        q_t + sum_d (A_d q)_{x_d} + B_d dq/dx_d = 0           (Eq. (1), material absorbed in B_d)
+ *   operator   V(u) = sum_d V_d(u),
+ *              V_d(u) = -(1/h) [ D x_d (A_d o u) + B_d o (D x_d u) ]  (Sec. II-A volume term)
+ *              D[i][j] = l_j'(xi_i) on the n = N+1 Gauss-Legendre nodes of [0,1]; "D x_d" contracts
+ *              spatial axis d; "o" is the nodewise m x m product.
+ *   Taylor     p_0 = Q, p_{o+1} = V p_o (+ S_o), o = 0..N-1          (Cauchy-Kowalewsky, Eq. (4))
+ *   outputs    qavg    = sum_{o=0..N} dt^o/(o+1)! p_o                 time AVERAGE (Eq. (4) / dt)
+ *              favg[d] = V_d(qavg)                                    time-averaged flux divergence + NCP
+ *                                                                     per direction (Fig. 1 favg[d]; computed
+ *                                                                     from qavg by linearity as in Fig. 5)
+ *              qface[f] = qavg extrapolated to face f                 (Sec. II-B: one product per face)
+ *              fface[f] = (A_{d_f} o qavg) extrapolated to face f     (only when A is present)
+ *
+ * Layouts (element-contiguous, no padding; the node index is (z*n + y)*n + x, the quantity index fastest,
+ * i.e. the AoS tensor of Sec. III-A/B):
+ *   Q, qavg           [e][z][y][x][s]                 n^3 * m values per element
+ *   favg              [e][d][z][y][x][s]              3 * n^3 * m  (n^3 * m with STP_FAVG_SUM)
+ *   qface, fface      [e][f][a][b][s]                 6 * n^2 * m; f = x-, x+, y-, y+, z-, z+ (reference
+ *                                                     coordinate 0 / 1 along the normal), (a, b) = the two
+ *                                                     other axes, slower first: (z,y), (z,x), (y,x)
+ *   params (presets)  [e][z][y][x][p] or [e][p] with STP_PARAM_PER_ELEMENT;
+ *                     acoustic p = (rho, K), elastic p = (rho, lambda, mu)
+ *   A, B (generic)    [e][d][z][y][x][row s][col r] or [e][d][s][r] with STP_COEF_PER_ELEMENT
+ *   src (point src)   [e][n^3 + m + N]: nodal projection P[node], amplitude a[s], time derivatives
+ *                     sigma^(o)(t_n), o = 0..N-1; S_o[node][s] = P[node] a[s] sigma^(o)
+ *   dt, h             [e] doubles (device), or host scalars when dt_h_scalar = 1
+ *
+ * Physics presets (quantity order):
+ *   STP_ACOUSTIC  m = 4 (p, v_x, v_y, v_z):   p_t + K div v = 0,  v_t + grad p / rho = 0
+ *   STP_ELASTIC   m = 9 (v_x, v_y, v_z, s_xx, s_yy, s_zz, s_xy, s_yz, s_xz):
+ *                 rho v_t = div sigma,  sigma_t = lambda (div v) I + mu (grad v + grad v^T)
+ *   STP_GENERIC   any 1 <= m <= 16: dense B_d (and optionally A_d) given per node or per element
+ *
+ * Precision: STP_FP64 computes and stores in double. STP_FP32 and STP_BF16X3 read and write float; their
+ * derivative contractions run in FP32 (VALU) or as three BF16 products with FP32 accumulation (MFMA).
+ * Classes whose order is >= acc64_min_order (when > 0) accumulate qavg and the face extrapolation in FP64.
+ *
+ * Ownership: the caller owns every buffer and passes raw pointers; device pointers must be device memory
+ * of the plan's device. The library never frees or retains caller buffers after stp_run returns (after
+ * stp_submit they must stay valid until stp_poll reports completion). The plan owns its constant tables,
+ * streams, events and scratch; it is immutable after creation and stp_run may be called concurrently from
+ * several host threads on different streams.
+ *
+ * Errors: every entry point returns a stp_status and never throws or aborts. Problems detectable on the
+ * host (bad sizes, NULL required pointers, unsupported order/quantity count, h <= 0 or dt < 0 given as host
+ * scalars, outputs aliasing inputs, class ids out of range when checked on the host) return STP_E_INVAL or
+ * STP_E_UNSUPPORTED before any device work is queued. HIP failures return STP_E_DEVICE. A human-readable
+ * message for the last failure on the calling thread is available from stp_last_error().
+ */
+#ifndef STP_H
+#define STP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stp_plan_s* stp_plan_t;
+
+typedef enum {
+    STP_OK = 0,
+    STP_PENDING = 1,          /* stp_poll: the ticket is queued or running                          */
+    STP_E_INVAL = -1,         /* invalid argument                                                   */
+    STP_E_UNSUPPORTED = -2,   /* order / quantity count / physics / precision not supported          */
+    STP_E_NOMEM = -3,         /* allocation failed, or a submitted batch exceeds the serving budget  */
+    STP_E_DEVICE = -4,        /* a HIP runtime call or a kernel launch failed                        */
+    STP_E_BUSY = -5           /* serving queue full                                                  */
+} stp_status;
+
+typedef enum { STP_ACOUSTIC = 0, STP_ELASTIC = 1, STP_GENERIC = 2 } stp_physics;
+typedef enum { STP_FP64 = 0, STP_FP32 = 1, STP_BF16X3 = 2 } stp_prec;
+
+/* stp_class.flags */
+enum {
+    STP_PARAM_PER_ELEMENT = 1u << 0, /* presets: params [e][p] instead of per node                     */
+    STP_A_PRESENT = 1u << 1,         /* generic: conservative flux matrices A_d given; fface written    */
+    STP_COEF_PER_ELEMENT = 1u << 2,  /* generic: A, B given once per element [e][d][s][r]               */
+    STP_FAVG_SUM = 1u << 3,          /* favg holds sum_d favg[d] ([e][n^3][m])                          */
+    STP_SRC_POINT = 1u << 4          /* a point source per element (src array)                          */
+};
+
+/* One element class: polynomial degree N (order; n = N+1 nodes per axis), quantity count m, physics. */
+typedef struct {
+    int order;      /* N, 1..9                                                  */
+    int nquant;     /* m: 4 (acoustic), 9 (elastic), 1..16 (generic)            */
+    int physics;    /* stp_physics                                              */
+    unsigned flags; /* STP_* class flags                                        */
+} stp_class;
+
+typedef struct {
+    int nclass;                /* number of classes, 1..64                                              */
+    const stp_class* classes;  /* host array [nclass], copied by stp_plan                                */
+    int prec;                  /* stp_prec                                                               */
+    int acc64_min_order;       /* FP32/BF16X3: FP64 accumulation of qavg and faces when order >= this;
+                                  0 = never. Ignored for STP_FP64.                                        */
+    int device;                /* HIP device ordinal                                                     */
+    int variant;               /* 0 = autotuned choice; otherwise a kernel variant id (STP_VARIANT_*)  */
+    size_t serve_mem_budget;   /* bytes of in-flight serving memory for stp_submit; 0 disables serving  */
+} stp_plan_desc;
+
+/* Kernel variants selectable through stp_plan_desc.variant (0 = library choice). */
+enum {
+    STP_VARIANT_AUTO = 0,
+    STP_VARIANT_PLAIN = 1,   /* one element per workgroup, one thread per node, LDS-staged             */
+    STP_VARIANT_FUSED = 2,   /* register-blocked lines, LDS transposes (presets, FP32/FP64)           */
+    STP_VARIANT_MFMA = 3     /* split-BF16x3 MFMA contractions with FP32 accumulation (STP_BF16X3)    */
+};
+
+typedef struct {
+    int64_t nelem;               /* number of elements (>= 0; 0 is a no-op)                               */
+    const int32_t* cls;          /* device [nelem] class index per element; NULL when nclass == 1        */
+    const int64_t* off_q;        /* device [nelem] offset (in values) of each element in Q and qavg; favg
+                                    uses 3*off_q (off_q with STP_FAVG_SUM). NULL = contiguous (one class) */
+    const int64_t* off_coef;     /* device [nelem] offset of each element in params or in A and B.
+                                    NULL = contiguous (one class)                                         */
+    const int64_t* off_face;     /* device [nelem] offset in qface / fface. NULL = contiguous (one class)  */
+    const int64_t* off_src;      /* device [nelem] offset in src. NULL = contiguous (one class)            */
+    const double* dt;            /* device [nelem], or host pointer to one value when dt_h_scalar = 1      */
+    const double* h;             /* device [nelem], or host pointer to one value when dt_h_scalar = 1      */
+    int dt_h_scalar;             /* 1: dt[0], h[0] are host scalars shared by all elements                 */
+    const void* Q;               /* device input DOFs                                                      */
+    const void* params;          /* device material parameters (presets)                                   */
+    const void* A;               /* device A_d (generic with STP_A_PRESENT)                               */
+    const void* B;               /* device B_d (generic)                                                  */
+    const void* src;             /* device point sources (STP_SRC_POINT)                                  */
+    void* qavg;                  /* device outputs                                                         */
+    void* favg;
+    void* qface;
+    void* fface;                 /* only written when the class has STP_A_PRESENT                         */
+} stp_batch;
+
+typedef struct {
+    double t_submit;  /* host monotonic seconds when stp_submit accepted the batch   */
+    double t_start;   /* when the dispatcher queued the launch                        */
+    double t_done;    /* when the completion poller observed the end of the launch    */
+    int status;       /* STP_OK, STP_PENDING or an error                              */
+} stp_ticket_info;
+
+/* Build a plan: host tables (Gauss-Legendre nodes, D, face vectors, BF16 hi/lo split of D) in FP64,
+ * uploaded once to the device; kernel choice per class. Returns STP_E_UNSUPPORTED for an order outside
+ * 1..9, a preset with the wrong m, or a generic m outside 1..16. *out is NULL on failure. */
+stp_status stp_plan(const stp_plan_desc* desc, stp_plan_t* out);
+
+/* Release a plan (waits for its outstanding serving work). NULL is a no-op. */
+void stp_plan_free(stp_plan_t plan);
+
+/* Run the predictor on a batch, asynchronously on the HIP stream `hip_stream` (NULL = the null stream).
+ * Returns after the launches are queued. Stream-capturable when batch->dt_h_scalar = 1 or dt/h are
+ * device arrays (no host synchronisation, no allocation). */
+stp_status stp_run(stp_plan_t plan, const stp_batch* batch, void* hip_stream);
+
+/* Serving: enqueue a batch for the plan's dispatcher thread. The batch descriptor is copied; its device
+ * buffers must stay valid until stp_poll reports completion. Admission: the batch's output+scratch bytes
+ * must fit serve_mem_budget (STP_E_NOMEM if it never can); batches wait while the in-flight total would
+ * exceed it. Returns STP_E_BUSY when the queue holds 65536 pending tickets. */
+stp_status stp_submit(stp_plan_t plan, const stp_batch* batch, uint64_t* ticket);
+
+/* Query a ticket. Returns STP_PENDING while queued or running, STP_OK once complete (info filled, the
+ * ticket retired), STP_E_INVAL for an unknown or already retired ticket, STP_E_DEVICE if its launch
+ * failed. info may be NULL. */
+stp_status stp_poll(stp_plan_t plan, uint64_t ticket, stp_ticket_info* info);
+
+/* Wait until every submitted ticket of the plan has completed (completion info stays pollable). */
+stp_status stp_drain(stp_plan_t plan);
+
+/* Algorithmic cost of one element of a class: HBM bytes (inputs read once, outputs written once, in the
+ * plan's I/O precision) and flops (derivatives of only the quantities B_d reads, pointwise terms, time
+ * accumulation, faces). Either pointer may be NULL. */
+stp_status stp_class_cost(stp_plan_t plan, int cls, double* bytes, double* flops);
+
+/* Message of the last failure on the calling thread ("" if none). Valid until the next call. */
+const char* stp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STP_H */

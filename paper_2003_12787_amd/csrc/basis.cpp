@@ -1,0 +1,143 @@
+// basis.cpp -- host-side constant tables of the predictor, built once per plan in FP64/long double:
+// Gauss-Legendre nodes on [0,1] (Sec. II-A nodal Lagrange basis), the derivative matrix D[i][j] = l_j'(xi_i)
+// (Sec. II-A "discrete derivative operator"), the face vectors l_j(0), l_j(1) (Sec. II-B face projection)
+// and the BF16 hi/lo split of D used by the split-BF16x3 contraction.
+//
+// The nodes are the eigenvalues of the symmetric Jacobi matrix of the Legendre recurrence, isolated by
+// Sturm-sequence bisection and polished by Newton steps on the recurrence.
+#include "basis.hpp"
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+namespace stp {
+
+namespace {
+
+// Number of eigenvalues of the n x n Legendre Jacobi matrix (zero diagonal, off-diagonal
+// b_k = k / sqrt(4k^2 - 1)) that are smaller than x (Sturm sequence count).
+int sturm_count(int n, long double x)
+{
+    int count = 0;
+    long double q = -x;  // first pivot: a_0 - x
+    if (q < 0) ++count;
+    for (int k = 1; k < n; ++k) {
+        long double b2 = (long double)k * k / (4.0L * k * k - 1.0L);
+        if (q == 0) q = 1e-30L;
+        q = -x - b2 / q;
+        if (q < 0) ++count;
+    }
+    return count;
+}
+
+// P_n(x) and P_n'(x)
+void legendre(int n, long double x, long double& p, long double& dp)
+{
+    long double a = 1.0L, b = x;
+    if (n == 0) { p = 1; dp = 0; return; }
+    for (int k = 2; k <= n; ++k) {
+        long double c = ((2.0L * k - 1.0L) * x * b - (k - 1.0L) * a) / k;
+        a = b;
+        b = c;
+    }
+    p = b;
+    dp = n * (a - x * b) / (1.0L - x * x);
+}
+
+}  // namespace
+
+void gauss_legendre_01(int n, double* xi, double* w)
+{
+    for (int i = 0; i < n; ++i) {
+        // i-th smallest eigenvalue of the Jacobi matrix in (-1, 1)
+        long double lo = -1.0L, hi = 1.0L;
+        for (int it = 0; it < 80; ++it) {
+            long double mid = 0.5L * (lo + hi);
+            if (sturm_count(n, mid) > i) hi = mid; else lo = mid;
+        }
+        long double x = 0.5L * (lo + hi), p, dp;
+        for (int it = 0; it < 3; ++it) {
+            legendre(n, x, p, dp);
+            x -= p / dp;
+        }
+        legendre(n, x, p, dp);
+        xi[i] = (double)(0.5L * (1.0L + x));
+        w[i] = (double)(1.0L / ((1.0L - x * x) * dp * dp));  // 2/((1-x^2)P'^2) on [-1,1], halved
+    }
+}
+
+void lagrange_values(int n, const double* xi, double x, double* l)
+{
+    for (int j = 0; j < n; ++j) {
+        long double num = 1.0L, den = 1.0L;
+        for (int k = 0; k < n; ++k) {
+            if (k == j) continue;
+            num *= (long double)x - xi[k];
+            den *= (long double)xi[j] - xi[k];
+        }
+        l[j] = (double)(num / den);
+    }
+}
+
+void derivative_matrix(int n, const double* xi, double* D)
+{
+    // l_j'(xi_i) = w_i / (w_j (xi_i - xi_j)) with w_i = prod_{k != i} (xi_i - xi_k)   (i != j)
+    long double pw[kMaxNodes];
+    for (int i = 0; i < n; ++i) {
+        pw[i] = 1.0L;
+        for (int k = 0; k < n; ++k)
+            if (k != i) pw[i] *= (long double)xi[i] - xi[k];
+    }
+    for (int i = 0; i < n; ++i) {
+        long double diag = 0.0L;
+        for (int j = 0; j < n; ++j) {
+            if (i == j) continue;
+            D[i * n + j] = (double)(pw[i] / (pw[j] * ((long double)xi[i] - xi[j])));
+            diag += 1.0L / ((long double)xi[i] - xi[j]);  // l_i'(xi_i) = sum_{k != i} 1/(xi_i - xi_k)
+        }
+        D[i * n + i] = (double)diag;
+    }
+}
+
+void derivative_matrix_f32(int n, const double* D, float* Df)
+{
+    // Off-diagonal entries rounded to FP32; the diagonal is chosen so that every row sums to zero when
+    // accumulated in FP32 order, so constants differentiate to (almost exactly) zero in FP32.
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (i == j) continue;
+            Df[i * n + j] = (float)D[i * n + j];
+            s += (double)Df[i * n + j];
+        }
+        Df[i * n + i] = (float)(-s);
+    }
+}
+
+uint16_t bf16_round(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;  // round to nearest even (inputs are finite)
+    return (uint16_t)(u >> 16);
+}
+
+float bf16_to_float(uint16_t b)
+{
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+void split_bf16(int count, const float* x, uint16_t* hi, uint16_t* lo)
+{
+    for (int i = 0; i < count; ++i) {
+        hi[i] = bf16_round(x[i]);
+        lo[i] = bf16_round(x[i] - bf16_to_float(hi[i]));
+    }
+}
+
+}  // namespace stp

@@ -1,0 +1,23 @@
+// basis.hpp -- host-side 1D basis tables of the predictor (see basis.cpp).
+#pragma once
+#include <cstdint>
+
+namespace stp {
+
+constexpr int kMaxOrder = 9;              // N = 1..9
+constexpr int kMaxNodes = kMaxOrder + 1;  // n = N + 1
+
+// n Gauss-Legendre nodes on [0,1], ascending, and weights summing to 1.
+void gauss_legendre_01(int n, double* xi, double* w);
+// Lagrange basis values l_j(x), j = 0..n-1.
+void lagrange_values(int n, const double* xi, double x, double* l);
+// D[i*n + j] = l_j'(xi_i).
+void derivative_matrix(int n, const double* xi, double* D);
+// FP32 copy of D with zero row sums in FP32.
+void derivative_matrix_f32(int n, const double* D, float* Df);
+// Round-to-nearest-even BF16 and the hi/lo split x ~ hi + lo.
+uint16_t bf16_round(float x);
+float bf16_to_float(uint16_t b);
+void split_bf16(int count, const float* x, uint16_t* hi, uint16_t* lo);
+
+}  // namespace stp

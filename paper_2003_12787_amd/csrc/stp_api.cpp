@@ -1,0 +1,365 @@
+// stp_api.cpp -- the C ABI of libstp.so (declared in include/stp.h): plans, argument validation, kernel
+// dispatch for uniform and heterogeneous batches, the algorithmic cost model, and error reporting.
+// The serving runtime behind stp_submit / stp_poll lives in stp_serve.cpp.
+#include "stp_plan.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "basis.hpp"
+
+namespace stp {
+
+thread_local std::string g_last_error;
+
+stp_status fail(stp_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+stp_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(STP_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+int quantities_read(const stp_class& c, int d)
+{
+    (void)d;
+    if (c.physics == STP_ACOUSTIC) return 2;  // p and v_d
+    if (c.physics == STP_ELASTIC) return 6;   // three velocities and three stresses s_{d,i}
+    return c.nquant;
+}
+
+}  // namespace
+
+// Algorithmic bytes (inputs once, outputs once) and flops of one element of a class.
+void class_cost(const stp_class& c, int io_bytes, double* bytes, double* flops)
+{
+    const double n = c.order + 1, n3 = n * n * n, n2 = n * n, m = c.nquant, N = c.order;
+    const bool hasA = c.physics == STP_GENERIC && (c.flags & STP_A_PRESENT);
+    const bool src = (c.flags & STP_SRC_POINT) != 0;
+    double in = n3 * m;
+    if (c.physics == STP_ACOUSTIC || c.physics == STP_ELASTIC) {
+        const double np = c.physics == STP_ACOUSTIC ? 2 : 3;
+        in += (c.flags & STP_PARAM_PER_ELEMENT) ? np : n3 * np;
+    } else {
+        const double per = (c.flags & STP_COEF_PER_ELEMENT) ? 3 * m * m : 3 * n3 * m * m;
+        in += per * (hasA ? 2 : 1);
+    }
+    if (src) in += n3 + m + N;
+    double out = n3 * m + ((c.flags & STP_FAVG_SUM) ? 1 : 3) * n3 * m + 6 * n2 * m * (hasA ? 2 : 1);
+    if (bytes) *bytes = (in + out) * io_bytes;
+    if (flops) {
+        double contr = 0, point = 0;
+        for (int d = 0; d < 3; ++d) {
+            contr += 2.0 * n * n3 * quantities_read(c, d);
+            if (c.physics == STP_ACOUSTIC) point += 2.0 * 2 * n3;
+            else if (c.physics == STP_ELASTIC) point += 2.0 * 8 * n3;
+            else point += 2.0 * m * m * n3;
+            if (hasA) {
+                contr += 2.0 * n * n3 * m;
+                point += 2.0 * m * m * n3;
+            }
+        }
+        double f = (N + 1) * (contr + point);  // N Taylor applications + the favg application
+        f += 2.0 * n3 * m * N;                 // time accumulation
+        f += 12.0 * n3 * m;                    // face extrapolation of q-bar
+        if (hasA) f += 12.0 * n3 * m + 3 * 2.0 * m * m * n3;
+        if (src) f += 3.0 * n3 * m * N;
+        *flops = f;
+    }
+}
+
+}  // namespace stp
+
+using namespace stp;
+
+namespace {
+
+stp_status validate_class(const stp_class& c)
+{
+    if (c.order < 1 || c.order > kMaxOrder)
+        return fail(STP_E_UNSUPPORTED, "order N=%d outside 1..%d", c.order, kMaxOrder);
+    if (c.physics == STP_ACOUSTIC) {
+        if (c.nquant != 4) return fail(STP_E_UNSUPPORTED, "acoustic preset needs m=4 (got %d)", c.nquant);
+    } else if (c.physics == STP_ELASTIC) {
+        if (c.nquant != 9) return fail(STP_E_UNSUPPORTED, "elastic preset needs m=9 (got %d)", c.nquant);
+    } else if (c.physics == STP_GENERIC) {
+        if (c.nquant < 1 || c.nquant > 16)
+            return fail(STP_E_UNSUPPORTED, "generic m=%d outside 1..16", c.nquant);
+    } else {
+        return fail(STP_E_INVAL, "unknown physics %d", c.physics);
+    }
+    const unsigned known = STP_PARAM_PER_ELEMENT | STP_A_PRESENT | STP_COEF_PER_ELEMENT | STP_FAVG_SUM | STP_SRC_POINT;
+    if (c.flags & ~known) return fail(STP_E_INVAL, "unknown class flags 0x%x", c.flags & ~known);
+    if (c.physics != STP_GENERIC && (c.flags & (STP_A_PRESENT | STP_COEF_PER_ELEMENT)))
+        return fail(STP_E_INVAL, "A_PRESENT / COEF_PER_ELEMENT are generic-only flags");
+    if (c.physics == STP_GENERIC && (c.flags & STP_PARAM_PER_ELEMENT))
+        return fail(STP_E_INVAL, "PARAM_PER_ELEMENT is a preset-only flag");
+    return STP_OK;
+}
+
+template <typename T>
+stp_status upload(const T* host, size_t count, void** dev)
+{
+    hipError_t e = hipMalloc(dev, sizeof(T) * count);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(table)");
+    e = hipMemcpy(*dev, host, sizeof(T) * count, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(table)");
+    return STP_OK;
+}
+
+stp_status build_class(stp_plan_s* p, ClassState& cs)
+{
+    const int n = cs.cls.order + 1;
+    double xi[kMaxNodes], w[kMaxNodes], D[kMaxNodes * kMaxNodes], e0[kMaxNodes], e1[kMaxNodes];
+    gauss_legendre_01(n, xi, w);
+    derivative_matrix(n, xi, D);
+    lagrange_values(n, xi, 0.0, e0);
+    lagrange_values(n, xi, 1.0, e1);
+    stp_status st;
+    if (p->prec == STP_FP64) {
+        if ((st = upload(D, n * n, &cs.dD)) != STP_OK) return st;
+        if ((st = upload(e0, n, &cs.de0)) != STP_OK) return st;
+        if ((st = upload(e1, n, &cs.de1)) != STP_OK) return st;
+    } else {
+        float Df[kMaxNodes * kMaxNodes], e0f[kMaxNodes], e1f[kMaxNodes];
+        derivative_matrix_f32(n, D, Df);
+        for (int i = 0; i < n; ++i) {
+            e0f[i] = (float)e0[i];
+            e1f[i] = (float)e1[i];
+        }
+        if ((st = upload(Df, n * n, &cs.dD)) != STP_OK) return st;
+        if ((st = upload(e0f, n, &cs.de0)) != STP_OK) return st;
+        if ((st = upload(e1f, n, &cs.de1)) != STP_OK) return st;
+        // FP64 face vectors for classes that accumulate in FP64
+        if ((st = upload(e0, n, &cs.de0_64)) != STP_OK) return st;
+        if ((st = upload(e1, n, &cs.de1_64)) != STP_OK) return st;
+    }
+    cs.acc64 = p->prec != STP_FP64 && p->acc64_min_order > 0 && cs.cls.order >= p->acc64_min_order;
+    const bool hasA = cs.cls.physics == STP_GENERIC && (cs.cls.flags & STP_A_PRESENT);
+    cs.kernel = select_kernel(p, cs);
+    if (!cs.kernel.fn) return fail(STP_E_UNSUPPORTED, "no kernel for N=%d m=%d physics=%d", cs.cls.order,
+                                   cs.cls.nquant, cs.cls.physics);
+    cs.lds = cs.kernel.lds(cs.cls.nquant, hasA);
+    if (cs.lds > kMaxLds)
+        return fail(STP_E_UNSUPPORTED, "class N=%d m=%d needs %zu B of LDS (> %zu)", cs.cls.order, cs.cls.nquant,
+                    cs.lds, (size_t)kMaxLds);
+    if (cs.lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(cs.kernel.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cs.lds);
+        if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(LDS)");
+    }
+    const int io = p->prec == STP_FP64 ? 8 : 4;
+    class_cost(cs.cls, io, &cs.bytes, &cs.flops);
+    const int64_t n3 = (int64_t)n * n * n, n2 = (int64_t)n * n, m = cs.cls.nquant;
+    cs.size_q = n3 * m;
+    cs.size_face = 6 * n2 * m;
+    cs.size_src = n3 + m + cs.cls.order;
+    if (cs.cls.physics == STP_GENERIC)
+        cs.size_coef = (cs.cls.flags & STP_COEF_PER_ELEMENT) ? 3 * m * m : 3 * n3 * m * m;
+    else
+        cs.size_coef = (cs.cls.flags & STP_PARAM_PER_ELEMENT) ? (cs.cls.physics == STP_ACOUSTIC ? 2 : 3)
+                                                               : n3 * (cs.cls.physics == STP_ACOUSTIC ? 2 : 3);
+    return STP_OK;
+}
+
+void free_plan_memory(stp_plan_s* p)
+{
+    for (auto& cs : p->classes) {
+        for (void* q : {cs.dD, cs.de0, cs.de1, cs.de0_64, cs.de1_64, cs.dDsplit})
+            if (q) (void)hipFree(q);
+    }
+    if (p->d_lists) (void)hipFree(p->d_lists);
+    if (p->d_counts) (void)hipFree(p->d_counts);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* stp_last_error(void) { return g_last_error.c_str(); }
+
+stp_status stp_plan(const stp_plan_desc* desc, stp_plan_t* out)
+{
+    g_last_error.clear();
+    if (!out) return fail(STP_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!desc) return fail(STP_E_INVAL, "desc is NULL");
+    if (desc->nclass < 1 || desc->nclass > kMaxClasses || !desc->classes)
+        return fail(STP_E_INVAL, "nclass=%d outside 1..%d or classes NULL", desc->nclass, kMaxClasses);
+    if (desc->prec < STP_FP64 || desc->prec > STP_BF16X3) return fail(STP_E_INVAL, "unknown precision %d", desc->prec);
+    if (desc->acc64_min_order < 0) return fail(STP_E_INVAL, "acc64_min_order < 0");
+    if (desc->variant < STP_VARIANT_AUTO || desc->variant > STP_VARIANT_MFMA)
+        return fail(STP_E_INVAL, "unknown variant %d", desc->variant);
+    for (int i = 0; i < desc->nclass; ++i) {
+        stp_status st = validate_class(desc->classes[i]);
+        if (st != STP_OK) return st;
+    }
+    if (desc->device < 0) return fail(STP_E_INVAL, "device %d < 0", desc->device);
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (desc->device >= ndev) return fail(STP_E_INVAL, "device %d of %d", desc->device, ndev);
+    DeviceGuard g(desc->device);
+    stp_plan_s* p = new (std::nothrow) stp_plan_s();
+    if (!p) return fail(STP_E_NOMEM, "out of host memory");
+    p->device = desc->device;
+    p->prec = desc->prec;
+    p->acc64_min_order = desc->acc64_min_order;
+    p->variant = desc->variant;
+    p->serve_budget = desc->serve_mem_budget;
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, desc->device)) != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipGetDeviceProperties");
+    }
+    p->num_cus = prop.multiProcessorCount;
+    p->classes.resize(desc->nclass);
+    for (int i = 0; i < desc->nclass; ++i) {
+        p->classes[i].cls = desc->classes[i];
+        stp_status st = build_class(p, p->classes[i]);
+        if (st != STP_OK) {
+            free_plan_memory(p);
+            delete p;
+            return st;
+        }
+    }
+    if (desc->nclass > 1) {
+        if ((e = hipMalloc(&p->d_counts, sizeof(int32_t) * kMaxClasses)) != hipSuccess) {
+            free_plan_memory(p);
+            delete p;
+            return hip_fail(e, "hipMalloc(counts)");
+        }
+    }
+    if (p->serve_budget > 0) {
+        stp_status st = serve_start(p);
+        if (st != STP_OK) {
+            free_plan_memory(p);
+            delete p;
+            return st;
+        }
+    }
+    *out = p;
+    return STP_OK;
+}
+
+void stp_plan_free(stp_plan_t p)
+{
+    if (!p) return;
+    DeviceGuard g(p->device);
+    serve_stop(p);
+    (void)hipDeviceSynchronize();
+    free_plan_memory(p);
+    delete p;
+}
+
+stp_status stp_class_cost(stp_plan_t p, int cls, double* bytes, double* flops)
+{
+    if (!p) return fail(STP_E_INVAL, "plan is NULL");
+    if (cls < 0 || cls >= (int)p->classes.size()) return fail(STP_E_INVAL, "class %d out of range", cls);
+    if (bytes) *bytes = p->classes[cls].bytes;
+    if (flops) *flops = p->classes[cls].flops;
+    return STP_OK;
+}
+
+stp_status stp_run(stp_plan_t p, const stp_batch* b, void* stream)
+{
+    g_last_error.clear();
+    if (!p) return fail(STP_E_INVAL, "plan is NULL");
+    stp_status st = validate_batch(p, b);
+    if (st != STP_OK) return st;
+    if (b->nelem == 0) return STP_OK;
+    DeviceGuard g(p->device);
+    return launch_batch(p, b, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+namespace stp {
+
+stp_status validate_batch(stp_plan_s* p, const stp_batch* b)
+{
+    if (!b) return fail(STP_E_INVAL, "batch is NULL");
+    if (b->nelem < 0) return fail(STP_E_INVAL, "nelem < 0");
+    if (b->nelem > (int64_t)INT32_MAX) return fail(STP_E_INVAL, "nelem > 2^31-1");
+    if (b->nelem == 0) return STP_OK;
+    const bool multi = p->classes.size() > 1;
+    if (multi && (!b->cls || !b->off_q || !b->off_coef || !b->off_face))
+        return fail(STP_E_INVAL, "heterogeneous plans need cls, off_q, off_coef and off_face");
+    if (!b->dt || !b->h) return fail(STP_E_INVAL, "dt / h are NULL");
+    if (b->dt_h_scalar) {
+        if (!(b->h[0] > 0) || !std::isfinite(b->h[0])) return fail(STP_E_INVAL, "h must be > 0 (got %g)", b->h[0]);
+        if (!(b->dt[0] >= 0) || !std::isfinite(b->dt[0])) return fail(STP_E_INVAL, "dt must be >= 0 (got %g)", b->dt[0]);
+    }
+    if (!b->Q || !b->qavg || !b->favg || !b->qface) return fail(STP_E_INVAL, "Q / qavg / favg / qface is NULL");
+    bool anyA = false, anyPreset = false, anyGeneric = false, anySrc = false;
+    for (auto& cs : p->classes) {
+        anyA |= cs.cls.physics == STP_GENERIC && (cs.cls.flags & STP_A_PRESENT);
+        anyPreset |= cs.cls.physics != STP_GENERIC;
+        anyGeneric |= cs.cls.physics == STP_GENERIC;
+        anySrc |= (cs.cls.flags & STP_SRC_POINT) != 0;
+    }
+    if (anyPreset && !b->params) return fail(STP_E_INVAL, "params is NULL for a preset class");
+    if (anyGeneric && !b->B) return fail(STP_E_INVAL, "B is NULL for a generic class");
+    if (anyA && (!b->A || !b->fface)) return fail(STP_E_INVAL, "A / fface is NULL for a class with A present");
+    if (anySrc && !b->src) return fail(STP_E_INVAL, "src is NULL for a class with a point source");
+    if (anySrc && multi && !b->off_src) return fail(STP_E_INVAL, "heterogeneous point sources need off_src");
+    // outputs must not alias inputs or each other (checked on the element ranges of a uniform batch)
+    if (!multi) {
+        const ClassState& cs = p->classes[0];
+        const int64_t io = p->prec == STP_FP64 ? 8 : 4, E = b->nelem;
+        const int64_t fmul = (cs.cls.flags & STP_FAVG_SUM) ? 1 : 3;
+        struct R { const void* p; int64_t bytes; const char* name; };
+        std::vector<R> ins = {{b->Q, E * cs.size_q * io, "Q"}};
+        if (b->params && cs.cls.physics != STP_GENERIC) ins.push_back({b->params, E * cs.size_coef * io, "params"});
+        if (b->B && cs.cls.physics == STP_GENERIC) ins.push_back({b->B, E * cs.size_coef * io, "B"});
+        if (b->A && anyA) ins.push_back({b->A, E * cs.size_coef * io, "A"});
+        if (b->src && anySrc) ins.push_back({b->src, E * cs.size_src * io, "src"});
+        std::vector<R> outs = {{b->qavg, E * cs.size_q * io, "qavg"}, {b->favg, E * fmul * cs.size_q * io, "favg"},
+                               {b->qface, E * cs.size_face * io, "qface"}};
+        if (anyA) outs.push_back({b->fface, E * cs.size_face * io, "fface"});
+        auto overlap = [](const R& a, const R& c) {
+            auto a0 = (uintptr_t)a.p, c0 = (uintptr_t)c.p;
+            return a0 < c0 + (uintptr_t)c.bytes && c0 < a0 + (uintptr_t)a.bytes;
+        };
+        for (size_t i = 0; i < outs.size(); ++i) {
+            for (auto& in : ins)
+                if (overlap(outs[i], in)) return fail(STP_E_INVAL, "output %s aliases input %s", outs[i].name, in.name);
+            for (size_t j = i + 1; j < outs.size(); ++j)
+                if (overlap(outs[i], outs[j]))
+                    return fail(STP_E_INVAL, "outputs %s and %s overlap", outs[i].name, outs[j].name);
+        }
+    }
+    return STP_OK;
+}
+
+}  // namespace stp

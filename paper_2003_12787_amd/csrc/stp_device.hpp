@@ -1,0 +1,149 @@
+// stp_device.hpp -- definitions shared by the predictor's HIP kernels: the launch argument block, element
+// addressing, and the pointwise PDE terms of the physics presets.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace stp {
+
+enum Physics : int { kAcoustic = 0, kElastic = 1, kGeneric = 2 };
+
+// Class flags (mirror the STP_* flags of stp.h).
+constexpr unsigned kParamPerElement = 1u << 0;
+constexpr unsigned kAPresent = 1u << 1;
+constexpr unsigned kCoefPerElement = 1u << 2;
+constexpr unsigned kFavgSum = 1u << 3;
+constexpr unsigned kSrcPoint = 1u << 4;
+
+// Launch argument block (passed by value). Pointers are device pointers.
+struct StpArgs {
+    int64_t nelem;             // elements handled by this launch
+    const int32_t* list;       // element ids of this launch (NULL: 0..nelem-1)
+    const int32_t* count;      // device element count of `list` (NULL: nelem)
+    const int64_t* off_q;      // per-element offsets (NULL: contiguous with the strides below)
+    const int64_t* off_coef;
+    const int64_t* off_face;
+    const int64_t* off_src;
+    int64_t stride_q, stride_coef, stride_face, stride_src;
+    const double* dt;          // per element (NULL: dt_s)
+    const double* h;           // per element (NULL: h_s)
+    double dt_s, h_s;
+    const void* Q;
+    const void* params;
+    const void* A;
+    const void* B;
+    const void* src;
+    void* qavg;
+    void* favg;
+    void* qface;
+    void* fface;
+    const void* D;             // [n][n] derivative matrix in the compute precision
+    const void* e0;            // [n] l_j(0)
+    const void* e1;            // [n] l_j(1)
+    const void* Dsplit;        // BF16 tables for the MFMA variant (layout owned by that kernel)
+    int m;                     // quantity count (generic; presets use their fixed m)
+    unsigned flags;
+};
+
+struct ElemRef {
+    int64_t e, q, coef, face, src;
+    double dt, h;
+};
+
+__device__ inline bool elem_ref(const StpArgs& a, int64_t i, ElemRef& r)
+{
+    int64_t cnt = a.count ? (int64_t)*a.count : a.nelem;
+    if (i >= cnt) return false;
+    int64_t e = a.list ? (int64_t)a.list[i] : i;
+    r.e = e;
+    r.q = a.off_q ? a.off_q[e] : e * a.stride_q;
+    r.coef = a.off_coef ? a.off_coef[e] : e * a.stride_coef;
+    r.face = a.off_face ? a.off_face[e] : e * a.stride_face;
+    r.src = a.off_src ? a.off_src[e] : e * a.stride_src;
+    r.dt = a.dt ? a.dt[e] : a.dt_s;
+    r.h = a.h ? a.h[e] : a.h_s;
+    return true;
+}
+
+template <int PHYS>
+struct PhysTraits;
+template <>
+struct PhysTraits<kAcoustic> {
+    static constexpr int m = 4;
+    static constexpr int np = 2;
+    // quantities that B_d reads in direction d: p (0) and v_d (1+d)
+    __host__ __device__ static constexpr bool needs(int d, int s) { return s == 0 || s == 1 + d; }
+};
+template <>
+struct PhysTraits<kElastic> {
+    static constexpr int m = 9;
+    static constexpr int np = 3;
+    // stress index of the symmetric pair (i, j): xx,yy,zz = 3,4,5; xy = 6, yz = 7, xz = 8
+    __host__ __device__ static constexpr int sig(int i, int j)
+    {
+        return i == j ? 3 + i : ((i + j == 1) ? 6 : ((i + j == 3) ? 7 : 8));
+    }
+    // quantities that B_d reads in direction d: the three velocities and the stresses s_{d,i}
+    __host__ __device__ static constexpr bool needs(int d, int s)
+    {
+        return s < 3 || s == sig(d, 0) || s == sig(d, 1) || s == sig(d, 2);
+    }
+};
+
+template <>
+struct PhysTraits<kGeneric> {
+    static constexpr int m = 0;   // runtime
+    static constexpr int np = 0;  // no material parameters: A_d, B_d are given
+    __host__ __device__ static constexpr bool needs(int, int) { return true; }
+};
+
+// Per-node material coefficients with -1/h folded in, in the compute precision.
+//   acoustic: c0 = -K/h, c1 = -1/(rho h)
+//   elastic : c0 = 1/(rho h), c1 = lambda/h, c2 = mu/h, c3 = (lambda + 2 mu)/h
+template <typename T, int PHYS>
+struct Material {
+    T c[4];
+    __device__ inline void load(const T* par, double inv_h)
+    {
+        if constexpr (PHYS == kAcoustic) {
+            double rho = (double)par[0], K = (double)par[1];
+            c[0] = (T)(-K * inv_h);
+            c[1] = (T)(-inv_h / rho);
+            c[2] = c[3] = (T)0;
+        } else if constexpr (PHYS == kElastic) {
+            double rho = (double)par[0], lam = (double)par[1], mu = (double)par[2];
+            c[0] = (T)(inv_h / rho);
+            c[1] = (T)(lam * inv_h);
+            c[2] = (T)(mu * inv_h);
+            c[3] = (T)((lam + 2.0 * mu) * inv_h);
+        }
+    }
+};
+
+// r += -(1/h) B_d g  for a preset, with g the reference derivative along d of the quantities B_d reads.
+template <typename T, int PHYS, int D>
+__device__ inline void apply_ncp(const Material<T, PHYS>& mt, const T* g, T* r)
+{
+    if constexpr (PHYS == kAcoustic) {
+        r[0] = fma(mt.c[0], g[1 + D], r[0]);  // p_t = -K dv_d/dx_d
+        r[1 + D] = fma(mt.c[1], g[0], r[1 + D]);  // v_d,t = -(1/rho) dp/dx_d
+    } else {
+        using P = PhysTraits<kElastic>;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) r[i] = fma(mt.c[0], g[P::sig(i, D)], r[i]);  // rho v_i,t = d s_id / dx_d
+#pragma unroll
+        for (int i = 0; i < 3; ++i) r[3 + i] = fma(i == D ? mt.c[3] : mt.c[1], g[D], r[3 + i]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            if (i != D) r[P::sig(D, i)] = fma(mt.c[2], g[i], r[P::sig(D, i)]);  // s_di,t = mu dv_i/dx_d
+    }
+}
+
+template <typename T>
+__device__ inline T ld(const void* p, int64_t i)
+{
+    return static_cast<const T*>(p)[i];
+}
+
+}  // namespace stp

@@ -1,0 +1,27 @@
+// stp_kernels.hpp -- host-visible descriptors of the predictor's kernel instantiations.
+#pragma once
+#include <cstddef>
+
+#include "stp_device.hpp"
+
+namespace stp {
+
+struct KernelInfo {
+    const void* fn = nullptr;               // __global__ function, launched with one StpArgs argument
+    int block = 0;                          // threads per workgroup
+    int mb = 0;                             // register bound on the quantity count
+    int elems_per_block = 1;                // elements processed per workgroup iteration
+    size_t (*lds)(int m, bool hasA) = nullptr;  // dynamic LDS bytes per workgroup
+};
+
+// Plain kernel (any class): FP64, or FP32 I/O with FP32 or FP64 accumulation.
+KernelInfo plain_kernel_f64(int N, int physics, int m);
+KernelInfo plain_kernel_f32(int N, int physics, int m);
+KernelInfo plain_kernel_f32acc64(int N, int physics, int m);
+inline KernelInfo plain_kernel(int prec_fp64, int acc64, int N, int physics, int m)
+{
+    if (prec_fp64) return plain_kernel_f64(N, physics, m);
+    return acc64 ? plain_kernel_f32acc64(N, physics, m) : plain_kernel_f32(N, physics, m);
+}
+
+}  // namespace stp

@@ -1,0 +1,347 @@
+// stp_plain.hpp -- plain STP kernel: one element per workgroup, one thread per node, the element's
+// current Taylor term p_o staged in LDS.
+//
+// Per element (Sec. II-A, Eq. (4) and the recursion below it; Sec. II-B outputs):
+//   p_0 = Q;  for o = 1..N:  p_o = V(p_{o-1}) (+ S_{o-1});  qavg += dt^o/(o+1)! p_o
+//   favg[d] = V_d(qavg)  (time-averaged fluxes recomputed from qavg by linearity, Fig. 5)
+//   qface[f] = sum_j l_j(0 or 1) qavg along the face normal; fface[f] likewise for A_{d_f} qavg.
+// with V_d(u) = -(1/h)[ D x_d (A_d u) + B_d (D x_d u) ].
+//
+// This is the straightforward GPU formulation (the generic algorithm's structure with the SplitCK
+// footprint): each thread owns one node, keeps its qavg (accumulator precision) and its next Taylor term
+// in registers, and reads the n values along each of the three lines through its node from LDS. It
+// supports every class (presets and generic, optional A and point source), and the FP64 instantiation is
+// the plain FP64 GPU baseline.
+#pragma once
+#include <type_traits>
+
+#include "stp_device.hpp"
+#include "stp_kernels.hpp"
+
+namespace stp {
+namespace plain {
+
+template <typename T, typename ACC, int N, int PHYS, int MB>
+struct Plain {
+    static constexpr int n = N + 1;
+    static constexpr int n2 = n * n;
+    static constexpr int nn = n * n * n;
+    static constexpr int NT = ((nn + 63) / 64) * 64;
+    static constexpr bool kPreset = PHYS != kGeneric;
+
+    // Byte offsets of the LDS regions, each 16-byte aligned; `total` is the dynamic LDS size.
+    struct Layout {
+        size_t coefs, pbuf, fbuf, qacc, total;
+    };
+    __host__ __device__ static constexpr size_t al16(size_t b) { return (b + 15) & ~size_t(15); }
+    __host__ __device__ static Layout layout(int m, bool hasA)
+    {
+        Layout L{};
+        L.coefs = al16(sizeof(T) * (n * n + 2 * n));
+        L.pbuf = al16(L.coefs + (kPreset ? 0 : sizeof(T) * 6 * MB * MB));
+        L.fbuf = al16(L.pbuf + sizeof(T) * nn * m);
+        L.qacc = al16(L.fbuf + (hasA ? sizeof(T) * nn * m : 0));
+        L.total = L.qacc + (std::is_same<ACC, T>::value ? 0 : sizeof(ACC) * nn * m);
+        return L;
+    }
+
+    // D x_d u at node (z, y, x) for quantity s; u is the LDS tile [node][m].
+    template <int D>
+    __device__ static inline T dline(const T* Ds, const T* u, int m, int tid, int z, int y, int x, int s)
+    {
+        const int kd = D == 0 ? x : (D == 1 ? y : z);
+        const int base = D == 0 ? tid - x : (D == 1 ? tid - y * n : tid - z * n2);
+        constexpr int stride = D == 0 ? 1 : (D == 1 ? n : n2);
+        T acc = 0;
+#pragma unroll
+        for (int j = 0; j < n; ++j) acc = fma(Ds[kd * n + j], u[(base + j * stride) * m + s], acc);
+        return acc;
+    }
+
+    // r += V_d(u) at the thread's node. Must be called by every thread of the block (barriers when A is
+    // present). fbuf: LDS scratch [nn][m] for the conservative flux A_d u.
+    template <int D>
+    __device__ static inline void accum_Vd(const StpArgs& a, const ElemRef& er, const T* Ds, const T* u,
+                                           T* fbuf, const T* coefs, const Material<T, PHYS>& mt, int m,
+                                           T inv_h, int tid, int z, int y, int x, bool own, bool hasA, T* r)
+    {
+        const bool per_elem = (a.flags & kCoefPerElement) != 0;
+        if constexpr (!kPreset) {
+            if (hasA) {
+                // flux F_d = A_d u at every node, then its derivative along d
+                if (own) {
+                    const T* Ad = per_elem ? coefs + (3 + D) * m * m
+                                           : static_cast<const T*>(a.A) + er.coef + ((int64_t)D * nn + tid) * m * m;
+#pragma unroll
+                    for (int s = 0; s < MB; ++s) {
+                        if (s >= m) break;
+                        T acc = 0;
+#pragma unroll
+                        for (int q = 0; q < MB; ++q) {
+                            if (q >= m) break;
+                            acc = fma(Ad[s * m + q], u[tid * m + q], acc);
+                        }
+                        fbuf[tid * m + s] = acc;
+                    }
+                }
+                __syncthreads();
+                if (own) {
+#pragma unroll
+                    for (int s = 0; s < MB; ++s) {
+                        if (s >= m) break;
+                        r[s] = fma(-inv_h, dline<D>(Ds, fbuf, m, tid, z, y, x, s), r[s]);
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (!own) return;
+        T g[MB];
+#pragma unroll
+        for (int s = 0; s < MB; ++s) {
+            if constexpr (kPreset) {
+                g[s] = PhysTraits<PHYS>::needs(D, s) ? dline<D>(Ds, u, MB, tid, z, y, x, s) : T(0);
+            } else {
+                g[s] = s < m ? dline<D>(Ds, u, m, tid, z, y, x, s) : T(0);
+            }
+        }
+        if constexpr (kPreset) {
+            apply_ncp<T, PHYS, D>(mt, g, r);
+        } else {
+            const T* Bd = per_elem ? coefs + D * m * m
+                                   : static_cast<const T*>(a.B) + er.coef + ((int64_t)D * nn + tid) * m * m;
+#pragma unroll
+            for (int s = 0; s < MB; ++s) {
+                if (s >= m) break;
+                T acc = 0;
+#pragma unroll
+                for (int q = 0; q < MB; ++q) {
+                    if (q >= m) break;
+                    acc = fma(Bd[s * m + q], g[q], acc);
+                }
+                r[s] = fma(-inv_h, acc, r[s]);
+            }
+        }
+    }
+
+    __device__ static void run(const StpArgs& a)
+    {
+        extern __shared__ __align__(16) unsigned char smem[];
+        const int m = kPreset ? PhysTraits<PHYS>::m : a.m;
+        const int tid = threadIdx.x;
+        const bool own = tid < nn;
+        const int x = tid % n, y = (tid / n) % n, z = tid / n2;
+        const bool hasA = !kPreset && (a.flags & kAPresent);
+        const bool hasSrc = (a.flags & kSrcPoint) != 0;
+        const bool per_elem = (a.flags & (kPreset ? kParamPerElement : kCoefPerElement)) != 0;
+
+        // LDS carve-up: tables, coefficient block (generic per element), p tile, flux tile, FP64 qavg tile
+        const Layout L = layout(m, hasA);
+        T* Ds = reinterpret_cast<T*>(smem);
+        T* e0s = Ds + n * n;
+        T* e1s = e0s + n;
+        T* coefs = reinterpret_cast<T*>(smem + L.coefs);  // [6][m][m]: B_0..B_2 then A_0..A_2
+        T* pbuf = reinterpret_cast<T*>(smem + L.pbuf);
+        T* fbuf = reinterpret_cast<T*>(smem + L.fbuf);    // only touched when A is present
+        ACC* qacc = reinterpret_cast<ACC*>(smem + L.qacc);
+
+        for (int i = tid; i < n * n; i += NT) Ds[i] = ld<T>(a.D, i);
+        for (int i = tid; i < n; i += NT) {
+            e0s[i] = ld<T>(a.e0, i);
+            e1s[i] = ld<T>(a.e1, i);
+        }
+
+        for (int64_t it = blockIdx.x;; it += gridDim.x) {
+            ElemRef er;
+            if (!elem_ref(a, it, er)) break;
+            const T inv_h = (T)(1.0 / er.h);
+            const T* Q = static_cast<const T*>(a.Q) + er.q;
+            for (int i = tid; i < nn * m; i += NT) pbuf[i] = Q[i];
+            Material<T, PHYS> mt;
+            if constexpr (kPreset) {
+                constexpr int np = PhysTraits<PHYS>::np;
+                const T* par = static_cast<const T*>(a.params) + er.coef + (per_elem ? 0 : tid * np);
+                if (own) mt.load(par, 1.0 / er.h);
+            } else if (per_elem) {
+                const T* Bsrc = static_cast<const T*>(a.B) + er.coef;
+                for (int i = tid; i < 3 * m * m; i += NT) coefs[i] = Bsrc[i];
+                if (hasA) {
+                    const T* Asrc = static_cast<const T*>(a.A) + er.coef;
+                    for (int i = tid; i < 3 * m * m; i += NT) coefs[3 * m * m + i] = Asrc[i];
+                }
+            }
+            T srcP = 0, srca[MB];
+            const T* src = static_cast<const T*>(a.src) + er.src;
+            if (hasSrc && own) {
+                srcP = src[tid];
+#pragma unroll
+                for (int s = 0; s < MB; ++s) srca[s] = s < m ? src[nn + s] : T(0);
+            }
+            __syncthreads();
+
+            ACC qb[MB];
+            T r[MB];
+#pragma unroll
+            for (int s = 0; s < MB; ++s) qb[s] = (own && s < m) ? (ACC)pbuf[tid * m + s] : ACC(0);
+            ACC w = 1;
+            const ACC dt = (ACC)er.dt;
+            for (int o = 1; o <= N; ++o) {
+#pragma unroll
+                for (int s = 0; s < MB; ++s) r[s] = 0;
+                accum_Vd<0>(a, er, Ds, pbuf, fbuf, coefs, mt, m, inv_h, tid, z, y, x, own, hasA, r);
+                accum_Vd<1>(a, er, Ds, pbuf, fbuf, coefs, mt, m, inv_h, tid, z, y, x, own, hasA, r);
+                accum_Vd<2>(a, er, Ds, pbuf, fbuf, coefs, mt, m, inv_h, tid, z, y, x, own, hasA, r);
+                if (hasSrc && own) {
+                    const T sg = src[nn + m + (o - 1)];
+#pragma unroll
+                    for (int s = 0; s < MB; ++s) r[s] = fma(srcP * srca[s], sg, r[s]);
+                }
+                __syncthreads();
+                w = w * dt / (ACC)(o + 1);
+                if (own) {
+#pragma unroll
+                    for (int s = 0; s < MB; ++s) {
+                        if (s >= m) break;
+                        pbuf[tid * m + s] = r[s];
+                        qb[s] = fma(w, (ACC)r[s], qb[s]);
+                    }
+                }
+                __syncthreads();
+            }
+
+            // q-bar into LDS (I/O precision, plus the accumulator precision for the faces)
+            if (own) {
+#pragma unroll
+                for (int s = 0; s < MB; ++s) {
+                    if (s >= m) break;
+                    pbuf[tid * m + s] = (T)qb[s];
+                    if constexpr (!std::is_same<ACC, T>::value) qacc[tid * m + s] = qb[s];
+                }
+            }
+            __syncthreads();
+            T* qavg = static_cast<T*>(a.qavg) + er.q;
+            for (int i = tid; i < nn * m; i += NT) qavg[i] = pbuf[i];
+
+            // faces of q-bar, in the accumulator precision
+            T* qface = static_cast<T*>(a.qface) + er.face;
+            for (int i = tid; i < 6 * n2 * m; i += NT) {
+                const int s = i % m, t = i / m, b = t % n, aa = (t / n) % n, f = t / n2;
+                const int axis = f >> 1;
+                const T* ev = (f & 1) ? e1s : e0s;
+                ACC acc = 0;
+#pragma unroll
+                for (int j = 0; j < n; ++j) {
+                    const int node = axis == 0 ? (aa * n + b) * n + j
+                                               : (axis == 1 ? (aa * n + j) * n + b : (j * n + aa) * n + b);
+                    if constexpr (std::is_same<ACC, T>::value)
+                        acc = fma((ACC)ev[j], pbuf[node * m + s], acc);
+                    else
+                        acc = fma((ACC)ev[j], qacc[node * m + s], acc);
+                }
+                qface[i] = (T)acc;
+            }
+            if (hasA) {
+                // extrapolated conservative flux A_{d_f} q-bar
+                T* fface = static_cast<T*>(a.fface) + er.face;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    if (own) {
+                        const T* Ad = per_elem ? coefs + (3 + d) * m * m
+                                               : static_cast<const T*>(a.A) + er.coef + ((int64_t)d * nn + tid) * m * m;
+                        for (int s = 0; s < m; ++s) {
+                            T acc = 0;
+                            for (int q = 0; q < m; ++q) acc = fma(Ad[s * m + q], pbuf[tid * m + q], acc);
+                            fbuf[tid * m + s] = acc;
+                        }
+                    }
+                    __syncthreads();
+                    for (int i = tid; i < 2 * n2 * m; i += NT) {
+                        const int s = i % m, t = i / m, b = t % n, aa = (t / n) % n, side = t / n2;
+                        const T* ev = side ? e1s : e0s;
+                        T acc = 0;
+                        for (int j = 0; j < n; ++j) {
+                            const int node = d == 0 ? (aa * n + b) * n + j
+                                                    : (d == 1 ? (aa * n + j) * n + b : (j * n + aa) * n + b);
+                            acc = fma(ev[j], fbuf[node * m + s], acc);
+                        }
+                        fface[(2 * d) * n2 * m + i] = acc;
+                    }
+                    __syncthreads();
+                }
+            }
+
+            // time-averaged fluxes favg[d] = V_d(q-bar)
+            T fv[3][MB];
+#pragma unroll
+            for (int s = 0; s < MB; ++s) fv[0][s] = fv[1][s] = fv[2][s] = 0;
+            accum_Vd<0>(a, er, Ds, pbuf, fbuf, coefs, mt, m, inv_h, tid, z, y, x, own, hasA, fv[0]);
+            accum_Vd<1>(a, er, Ds, pbuf, fbuf, coefs, mt, m, inv_h, tid, z, y, x, own, hasA, fv[1]);
+            accum_Vd<2>(a, er, Ds, pbuf, fbuf, coefs, mt, m, inv_h, tid, z, y, x, own, hasA, fv[2]);
+            __syncthreads();
+            const bool fsum = (a.flags & kFavgSum) != 0;
+            T* favg = static_cast<T*>(a.favg) + (fsum ? er.q : 3 * er.q);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                if (fsum && d > 0) break;
+                if (own) {
+#pragma unroll
+                    for (int s = 0; s < MB; ++s) {
+                        if (s >= m) break;
+                        pbuf[tid * m + s] = fsum ? fv[0][s] + fv[1][s] + fv[2][s] : fv[d][s];
+                    }
+                }
+                __syncthreads();
+                for (int i = tid; i < nn * m; i += NT) favg[d * nn * m + i] = pbuf[i];
+                __syncthreads();
+            }
+        }
+    }
+};
+
+template <typename T, typename ACC, int N, int PHYS, int MB>
+__global__ void __launch_bounds__(((N + 1) * (N + 1) * (N + 1) + 63) / 64 * 64) stp_plain_kernel(StpArgs a)
+{
+    Plain<T, ACC, N, PHYS, MB>::run(a);
+}
+
+template <typename T, typename ACC, int N, int PHYS, int MB>
+KernelInfo plain_info()
+{
+    using K = Plain<T, ACC, N, PHYS, MB>;
+    KernelInfo ki;
+    ki.fn = reinterpret_cast<const void*>(&stp_plain_kernel<T, ACC, N, PHYS, MB>);
+    ki.block = K::NT;
+    ki.mb = MB;
+    ki.lds = [](int m, bool hasA) -> size_t { return K::layout(m, hasA).total; };
+    return ki;
+}
+
+template <typename T, typename ACC, int PHYS, int MB>
+KernelInfo plain_by_order(int N)
+{
+    switch (N) {
+    case 1: return plain_info<T, ACC, 1, PHYS, MB>();
+    case 2: return plain_info<T, ACC, 2, PHYS, MB>();
+    case 3: return plain_info<T, ACC, 3, PHYS, MB>();
+    case 4: return plain_info<T, ACC, 4, PHYS, MB>();
+    case 5: return plain_info<T, ACC, 5, PHYS, MB>();
+    case 6: return plain_info<T, ACC, 6, PHYS, MB>();
+    case 7: return plain_info<T, ACC, 7, PHYS, MB>();
+    case 8: return plain_info<T, ACC, 8, PHYS, MB>();
+    case 9: return plain_info<T, ACC, 9, PHYS, MB>();
+    default: return KernelInfo{};
+    }
+}
+
+template <typename T, typename ACC>
+KernelInfo plain_by_physics(int N, int physics, int m)
+{
+    if (physics == kAcoustic) return plain_by_order<T, ACC, kAcoustic, 4>(N);
+    if (physics == kElastic) return plain_by_order<T, ACC, kElastic, 9>(N);
+    if (m <= 4) return plain_by_order<T, ACC, kGeneric, 4>(N);
+    if (m <= 9) return plain_by_order<T, ACC, kGeneric, 9>(N);
+    return plain_by_order<T, ACC, kGeneric, 16>(N);
+}
+
+}  // namespace plain
+}  // namespace stp

@@ -1,0 +1,78 @@
+// stp_plan.hpp -- internal state of a plan (the opaque stp_plan_t of stp.h).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "stp.h"
+#include "stp_kernels.hpp"
+
+namespace stp {
+
+constexpr int kMaxClasses = 64;
+constexpr size_t kMaxLds = 160 * 1024;
+
+struct ClassState {
+    stp_class cls{};
+    void* dD = nullptr;      // derivative matrix in the compute precision
+    void* de0 = nullptr;     // face vectors in the compute precision
+    void* de1 = nullptr;
+    void* de0_64 = nullptr;  // FP64 face vectors (FP32 plans)
+    void* de1_64 = nullptr;
+    void* dDsplit = nullptr; // BF16 hi/lo tables (split-BF16x3 variant)
+    bool acc64 = false;      // FP64 accumulation of q-bar and faces
+    KernelInfo kernel;
+    size_t lds = 0;
+    double bytes = 0, flops = 0;  // algorithmic cost per element
+    int64_t size_q = 0, size_face = 0, size_coef = 0, size_src = 0;  // values per element
+};
+
+// Device scratch of heterogeneous launches: per-class element lists and counts.
+struct HeteroScratch {
+    int32_t* lists = nullptr;  // [nclass][cap]
+    int32_t* counts = nullptr; // [kMaxClasses]
+    int64_t cap = 0;
+};
+
+struct ServeState;
+
+}  // namespace stp
+
+struct stp_plan_s {
+    int device = 0;
+    int prec = STP_FP64;
+    int acc64_min_order = 0;
+    int variant = 0;
+    int num_cus = 256;
+    size_t serve_budget = 0;
+    std::vector<stp::ClassState> classes;
+    void* d_lists = nullptr;   // unused (kept for layout stability of free_plan_memory)
+    void* d_counts = nullptr;
+    std::mutex run_mu;         // guards `run_scratch` growth
+    stp::HeteroScratch run_scratch;
+    stp::ServeState* serve = nullptr;
+};
+
+namespace stp {
+
+stp_status fail(stp_status st, const char* fmt, ...);
+stp_status hip_fail(hipError_t e, const char* what);
+void class_cost(const stp_class& c, int io_bytes, double* bytes, double* flops);
+stp_status validate_batch(stp_plan_s* p, const stp_batch* b);
+KernelInfo select_kernel(stp_plan_s* p, const ClassState& cs);
+// Queue the kernels of a validated, non-empty batch on `stream`, using `scratch` for heterogeneous lists.
+stp_status launch_batch(stp_plan_s* p, const stp_batch* b, hipStream_t stream, HeteroScratch* scratch = nullptr);
+void free_scratch(HeteroScratch& s);
+stp_status serve_start(stp_plan_s* p);
+void serve_stop(stp_plan_s* p);
+double now_seconds();
+
+}  // namespace stp

@@ -1,0 +1,255 @@
+// stp_serve.cpp -- serving runtime behind stp_submit / stp_poll / stp_drain.
+//
+// A plan created with serve_mem_budget > 0 owns one HIP stream (default priority) and two host threads:
+//   dispatcher : takes submitted batches in arrival order and admits one when the bytes of its outputs
+//                plus heterogeneous scratch fit the budget next to the batches still in flight; it then
+//                queues the launches on the serving stream and records a completion event;
+//   completer  : waits for the in-flight events in launch order (one stream, so they finish in order),
+//                stamps the completion time and releases the batch's bytes.
+// Tickets carry host monotonic timestamps (submit, launch, completion) for latency statistics.
+#include <chrono>
+
+#include "stp_plan.hpp"
+
+namespace stp {
+
+double now_seconds()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+namespace {
+
+struct Pending {
+    uint64_t ticket;
+    stp_batch batch;
+    double dt_s, h_s;  // copies of host scalars (the batch points at them when dt_h_scalar)
+    size_t bytes;
+};
+
+struct InFlight {
+    uint64_t ticket;
+    hipEvent_t ev;
+    size_t bytes;
+};
+
+struct TicketRec {
+    stp_ticket_info info;
+};
+
+}  // namespace
+
+struct ServeState {
+    hipStream_t stream = nullptr;
+    HeteroScratch scratch;
+    std::mutex mu;
+    std::condition_variable cv_dispatch, cv_complete, cv_idle;
+    std::deque<Pending> queue;
+    std::deque<InFlight> inflight;
+    std::unordered_map<uint64_t, TicketRec> tickets;
+    size_t inflight_bytes = 0;
+    int launching = 0;  // batches popped by the dispatcher whose launch is being queued
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread dispatcher, completer;
+};
+
+namespace {
+
+constexpr size_t kMaxPending = 65536;
+
+size_t batch_bytes(const stp_plan_s* p, const stp_batch* b)
+{
+    const size_t io = p->prec == STP_FP64 ? 8 : 4;
+    size_t per = 0;
+    for (auto& cs : p->classes) {
+        const bool hasA = cs.cls.physics == STP_GENERIC && (cs.cls.flags & STP_A_PRESENT);
+        const size_t fmul = (cs.cls.flags & STP_FAVG_SUM) ? 1 : 3;
+        size_t out = io * (cs.size_q * (1 + fmul) + cs.size_face * (hasA ? 2 : 1));
+        per = std::max(per, out);
+    }
+    size_t scratch = p->classes.size() > 1 ? sizeof(int32_t) * p->classes.size() : 0;
+    return (size_t)b->nelem * (per + scratch);
+}
+
+void dispatcher_main(stp_plan_s* p)
+{
+    ServeState* s = p->serve;
+    (void)hipSetDevice(p->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        s->cv_dispatch.wait(lk, [&] {
+            return (!s->queue.empty() && s->inflight_bytes + s->queue.front().bytes <= p->serve_budget) ||
+                   (s->stop && s->queue.empty());
+        });
+        if (s->queue.empty()) break;  // stopping, nothing left to launch
+        Pending job = s->queue.front();
+        s->queue.pop_front();
+        s->inflight_bytes += job.bytes;
+        ++s->launching;
+        auto& rec = s->tickets[job.ticket];
+        rec.info.t_start = now_seconds();
+        lk.unlock();
+        if (job.batch.dt_h_scalar) {
+            job.batch.dt = &job.dt_s;
+            job.batch.h = &job.h_s;
+        }
+        stp_status st = launch_batch(p, &job.batch, s->stream, &s->scratch);
+        hipEvent_t ev = nullptr;
+        if (st == STP_OK) {
+            hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventRecord(ev, s->stream);
+            if (e != hipSuccess) st = STP_E_DEVICE;
+        }
+        lk.lock();
+        --s->launching;
+        if (st != STP_OK) {
+            if (ev) (void)hipEventDestroy(ev);
+            auto& r = s->tickets[job.ticket];
+            r.info.status = st;
+            r.info.t_done = now_seconds();
+            s->inflight_bytes -= job.bytes;
+            s->cv_complete.notify_one();
+            if (s->queue.empty() && s->inflight.empty() && s->launching == 0) s->cv_idle.notify_all();
+            continue;
+        }
+        s->inflight.push_back({job.ticket, ev, job.bytes});
+        s->cv_complete.notify_one();
+    }
+    s->cv_complete.notify_all();
+}
+
+void completer_main(stp_plan_s* p)
+{
+    ServeState* s = p->serve;
+    (void)hipSetDevice(p->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        s->cv_complete.wait(lk, [&] {
+            return !s->inflight.empty() || (s->stop && s->queue.empty() && s->launching == 0);
+        });
+        if (s->inflight.empty()) break;  // stopping and everything has completed
+        InFlight f = s->inflight.front();
+        lk.unlock();
+        hipError_t e = hipEventSynchronize(f.ev);
+        double t = now_seconds();
+        (void)hipEventDestroy(f.ev);
+        lk.lock();
+        s->inflight.pop_front();
+        auto& r = s->tickets[f.ticket];
+        r.info.t_done = t;
+        r.info.status = e == hipSuccess ? STP_OK : STP_E_DEVICE;
+        s->inflight_bytes -= f.bytes;
+        s->cv_dispatch.notify_one();
+        if (s->queue.empty() && s->inflight.empty() && s->launching == 0) s->cv_idle.notify_all();
+    }
+}
+
+}  // namespace
+
+stp_status serve_start(stp_plan_s* p)
+{
+    auto* s = new (std::nothrow) ServeState();
+    if (!s) return fail(STP_E_NOMEM, "out of host memory");
+    hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete s;
+        return hip_fail(e, "hipStreamCreate(serving)");
+    }
+    p->serve = s;
+    s->dispatcher = std::thread(dispatcher_main, p);
+    s->completer = std::thread(completer_main, p);
+    return STP_OK;
+}
+
+void serve_stop(stp_plan_s* p)
+{
+    ServeState* s = p->serve;
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_dispatch.notify_all();
+    s->cv_complete.notify_all();
+    if (s->dispatcher.joinable()) s->dispatcher.join();
+    s->cv_complete.notify_all();
+    if (s->completer.joinable()) s->completer.join();
+    (void)hipStreamSynchronize(s->stream);
+    (void)hipStreamDestroy(s->stream);
+    free_scratch(s->scratch);
+    delete s;
+    p->serve = nullptr;
+}
+
+}  // namespace stp
+
+using namespace stp;
+
+extern "C" {
+
+stp_status stp_submit(stp_plan_t p, const stp_batch* b, uint64_t* ticket)
+{
+    if (!p) return fail(STP_E_INVAL, "plan is NULL");
+    if (!ticket) return fail(STP_E_INVAL, "ticket is NULL");
+    if (!p->serve) return fail(STP_E_INVAL, "plan was created without a serving budget");
+    stp_status st = validate_batch(p, b);
+    if (st != STP_OK) return st;
+    const size_t bytes = batch_bytes(p, b);
+    if (bytes > p->serve_budget)
+        return fail(STP_E_NOMEM, "batch needs %zu B, more than the serving budget %zu B", bytes, p->serve_budget);
+    ServeState* s = p->serve;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->queue.size() >= kMaxPending) return fail(STP_E_BUSY, "serving queue full");
+    Pending job{};
+    job.ticket = s->next_ticket++;
+    job.batch = *b;
+    job.bytes = bytes;
+    if (b->dt_h_scalar) {
+        job.dt_s = b->dt[0];
+        job.h_s = b->h[0];
+    }
+    TicketRec rec{};
+    rec.info.t_submit = now_seconds();
+    rec.info.status = STP_PENDING;
+    s->tickets[job.ticket] = rec;
+    if (b->nelem == 0) {  // nothing to launch: complete immediately
+        auto& r = s->tickets[job.ticket];
+        r.info.t_start = r.info.t_done = r.info.t_submit;
+        r.info.status = STP_OK;
+    } else {
+        s->queue.push_back(job);
+        s->cv_dispatch.notify_one();
+    }
+    *ticket = job.ticket;
+    return STP_OK;
+}
+
+stp_status stp_poll(stp_plan_t p, uint64_t ticket, stp_ticket_info* info)
+{
+    if (!p) return fail(STP_E_INVAL, "plan is NULL");
+    if (!p->serve) return fail(STP_E_INVAL, "plan was created without a serving budget");
+    ServeState* s = p->serve;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return fail(STP_E_INVAL, "unknown or retired ticket %llu", (unsigned long long)ticket);
+    if (info) *info = it->second.info;
+    stp_status st = (stp_status)it->second.info.status;
+    if (st == STP_PENDING) return STP_PENDING;
+    s->tickets.erase(it);
+    if (st != STP_OK) return fail(st, "ticket %llu failed on the device", (unsigned long long)ticket);
+    return STP_OK;
+}
+
+stp_status stp_drain(stp_plan_t p)
+{
+    if (!p) return fail(STP_E_INVAL, "plan is NULL");
+    if (!p->serve) return STP_OK;
+    ServeState* s = p->serve;
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_idle.wait(lk, [&] { return s->queue.empty() && s->inflight.empty() && s->launching == 0; });
+    return STP_OK;
+}
+
+}  // extern "C"

@@ -102,7 +102,7 @@ def acoustic_plane_wave_batch(N: int, nelem: int, seed: int, h: float = 1.0, noi
     pz = (ez[:, None] + Z.reshape(1, -1)) * h
     phase = kvec[0] * px + kvec[1] * py + kvec[2] * pz
     p = np.sin(phase)
-    v = khat[None, None, :] * (p / (rho * c))[:, :, None] if nelem else np.zeros((0, n ** 3, 3))
+    v = khat[None, None, :] * (p / (rho * c)[:, None])[:, :, None]
     Q = np.concatenate([p[..., None], v], axis=-1)
     Q = Q + noise * rng.standard_normal(Q.shape)
     dt = np.full(nelem, cfl_dt(N, h, c.max() if nelem else 1.0))
@@ -180,3 +180,64 @@ def serving_batch_sizes(nbatch: int, seed: int) -> np.ndarray:
     """Log-uniform batch sizes floor(exp(U[0, ln 4097))) in 1..4096."""
     rng = np.random.default_rng(seed)
     return np.minimum(4096, np.floor(np.exp(rng.uniform(0, math.log(4097), nbatch))).astype(np.int64))
+
+
+@dataclasses.dataclass
+class HeteroBatch:
+    """A batch of elements of several classes in one flat buffer per array (FP64 host arrays).
+
+    classes: list of (N, m, physics, flags); cls[e] is the class of element e; off_q / off_coef /
+    off_face are per-element offsets (in values) into Q / B (or params) / qface; `parts` holds the
+    uniform sub-batch of each class with `members[c]` the element ids of class c."""
+    classes: list
+    cls: np.ndarray
+    off_q: np.ndarray
+    off_coef: np.ndarray
+    off_face: np.ndarray
+    Q: np.ndarray
+    coef: np.ndarray
+    dt: np.ndarray
+    h: np.ndarray
+    parts: list
+    members: list
+    size_q: int
+    size_face: int
+
+
+def hetero_generic_batch(nelem: int, seed: int, orders=None, nquants=None, h: float = 1.0) -> HeteroBatch:
+    """Heterogeneous elements with dense per-node B_d ~ N(0, 1/m) (no A), Q ~ N(0,1), dt_e from
+    c_e = max over nodes and directions of ||B_d||_F. Orders N_e ~ U{2..9} and m_e ~ U{4, 9} by default."""
+    rng = np.random.default_rng(seed)
+    if orders is None:
+        Ns, ms = c4_classes(nelem, seed)
+    else:
+        Ns = rng.choice(np.asarray(orders), nelem)
+        ms = rng.choice(np.asarray(nquants), nelem)
+    keys = sorted(set(zip(Ns.tolist(), ms.tolist())))
+    classes = [(N, m, GENERIC, 0) for N, m in keys]
+    index = {k: i for i, k in enumerate(keys)}
+    cls = np.array([index[(int(a), int(b))] for a, b in zip(Ns, ms)], dtype=np.int32)
+    parts, members = [], []
+    for c, (N, m) in enumerate(keys):
+        ids = np.nonzero(cls == c)[0]
+        members.append(ids)
+        parts.append(generic_batch(N, m, len(ids), seed + 1000 + c, h=h))
+    size_q = np.array([(N + 1) ** 3 * m for N, m in keys])
+    size_face = np.array([6 * (N + 1) ** 2 * m for N, m in keys])
+    size_coef = np.array([3 * (N + 1) ** 3 * m * m for N, m in keys])
+    sq, sf, sc = size_q[cls], size_face[cls], size_coef[cls]
+    off_q = np.concatenate([[0], np.cumsum(sq)[:-1]]).astype(np.int64)
+    off_face = np.concatenate([[0], np.cumsum(sf)[:-1]]).astype(np.int64)
+    off_coef = np.concatenate([[0], np.cumsum(sc)[:-1]]).astype(np.int64)
+    Q = np.zeros(int(sq.sum()))
+    coef = np.zeros(int(sc.sum()))
+    dt = np.zeros(nelem)
+    hh = np.full(nelem, h)
+    for c, ids in enumerate(members):
+        p = parts[c]
+        for j, e in enumerate(ids):
+            Q[off_q[e]:off_q[e] + sq[e]] = p.Q[j].ravel()
+            coef[off_coef[e]:off_coef[e] + sc[e]] = p.B[j].ravel()
+            dt[e] = p.dt[j]
+    return HeteroBatch(classes, cls, off_q, off_coef, off_face, Q, coef, dt, hh, parts, members,
+                       int(sq.sum()), int(sf.sum()))

@@ -1,0 +1,284 @@
+"""GPU parity: the HIP predictor through the C ABI against the FP64 oracle on the same seeded inputs.
+
+Reduced-precision runs feed the oracle the inputs rounded to FP32, so input quantisation is not counted as
+kernel error. The metric is the per-element max-relative error of each output (see parity.py) with the
+tolerances FP64 1e-12, FP32 1e-5 and split-BF16x3 1e-4. Full-size workloads are checked on a sample of
+elements spread over the batch, in the same launch configuration the benchmark times.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2003_12787_amd import stp
+from paper_2003_12787_amd import workloads as W
+from parity import TOL, max_rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build()
+    return torch
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def oracle_run(b, **kw):
+    return oracle.stp(b.N, b.physics, b.Q, b.dt, b.h, params=b.params, A=b.A, B=b.B, src=b.src,
+                      coef_per_element=b.coef_per_element, **kw)
+
+
+def subset(b, ids):
+    import copy
+    s = copy.copy(b)
+    for k in ("Q", "dt", "h", "params", "A", "B", "src"):
+        v = getattr(b, k)
+        if v is not None:
+            setattr(s, k, v[ids])
+    return s
+
+
+def check(b, prec, variant=stp.VARIANT_AUTO, acc64=0, sample=None, favg_sum=False, label=""):
+    from paper_2003_12787_amd import runner
+    cls = runner.class_of(b, stp.FAVG_SUM if favg_sum else 0)
+    plan = stp.Plan([cls], prec=prec, variant=variant, acc64_min_order=acc64)
+    say(f"[parity] {label} N={b.N} m={b.m} phys={b.physics} E={b.nelem} prec={prec} variant={variant}")
+    got = runner.run(plan, b, favg_sum=favg_sum)
+    rb = runner.rounded(b, prec)
+    ids = np.arange(b.nelem) if sample is None else sample
+    rb = subset(rb, ids)
+    got = {k: v[ids] for k, v in got.items()}
+    ref = oracle_run(rb)
+    if favg_sum:
+        ref["favg"] = ref["favg"].sum(axis=1)
+    err = max_rel_err(got, ref, rb.Q, rb.h)
+    say(f"[parity]   max rel err {err}")
+    for k, v in err.items():
+        assert v < TOL[prec], (k, v)
+    plan.close()
+    return err
+
+
+def spread(E, k, seed=0):
+    rng = np.random.default_rng(seed)
+    ids = np.unique(np.concatenate([[0, E - 1], rng.choice(E, size=min(k, E), replace=False)]))
+    return np.sort(ids)
+
+
+# ------------------------------------------------------------------------------------------------ presets
+def test_c1_elastic_n3_fp64():
+    check(W.c1_elastic_n3(), stp.FP64, label="C1")
+
+
+@pytest.mark.parametrize("acc64", [0, 1])
+def test_c1_elastic_n3_fp32(acc64):
+    check(W.c1_elastic_n3(), stp.FP32, acc64=acc64, label="C1")
+
+
+@pytest.mark.parametrize("prec", [stp.FP64, stp.FP32])
+def test_c2_acoustic_plane_wave_small(prec):
+    check(W.c2_acoustic_n5(nelem=1000), prec, label="C2-small")
+
+
+@pytest.mark.parametrize("prec", [stp.FP64, stp.FP32])
+def test_c3_elastic_n7_small(prec):
+    check(W.c3_elastic_n7(nelem=300), prec, label="C3-small")
+
+
+@pytest.mark.parametrize("N", [1, 2, 4, 6, 8, 9])
+@pytest.mark.parametrize("prec", [stp.FP64, stp.FP32])
+def test_elastic_all_orders(N, prec):
+    check(W.elastic_batch(N, 70, 500 + N), prec, acc64=8, label="elastic-orders")
+
+
+@pytest.mark.parametrize("N", [1, 3, 9])
+def test_acoustic_orders_per_node(N):
+    check(W.acoustic_batch(N, 65, 600 + N), stp.FP32, label="acoustic-per-node")
+    check(W.acoustic_batch(N, 65, 600 + N), stp.FP64, label="acoustic-per-node")
+
+
+def test_elastic_per_element_material_and_favg_sum():
+    b = W.elastic_batch(5, 130, 21, per_node=False)
+    check(b, stp.FP32, label="elastic-per-element")
+    check(b, stp.FP64, favg_sum=True, label="elastic-favg-sum")
+
+
+def test_c3_full_size_sampled():
+    b = W.c3_elastic_n7()
+    check(b, stp.FP32, sample=spread(b.nelem, 40), label="C3-full")
+
+
+def test_c2_full_size_sampled():
+    b = W.c2_acoustic_n5()
+    check(b, stp.FP32, sample=spread(b.nelem, 40, 1), label="C2-full")
+    check(b, stp.FP64, sample=spread(b.nelem, 40, 2), label="C2-full")
+
+
+# ------------------------------------------------------------------------------------------------ generic
+@pytest.mark.parametrize("N,m", [(1, 1), (2, 5), (3, 9), (4, 16)])
+@pytest.mark.parametrize("prec", [stp.FP64, stp.FP32])
+def test_generic_dense_B_per_node(N, m, prec):
+    check(W.generic_batch(N, m, 67, 700 + N * 20 + m), prec, label="generic")
+
+
+@pytest.mark.parametrize("prec", [stp.FP64, stp.FP32])
+def test_generic_with_A_and_point_source(prec):
+    b = W.generic_batch(3, 6, 66, 801, with_A=True)
+    b.src = W.point_source(b, 802)
+    check(b, prec, label="generic-A-src")
+
+
+@pytest.mark.parametrize("prec", [stp.FP64, stp.FP32])
+def test_generic_per_element_coefficients(prec):
+    b = W.generic_batch(5, 9, 65, 803, with_A=True, per_node=False)
+    check(b, prec, label="generic-per-element")
+
+
+def test_per_element_dt_and_h():
+    b = W.elastic_batch(4, 90, 804)
+    rng = np.random.default_rng(5)
+    b.h = rng.uniform(0.5, 2.0, b.nelem)
+    b.dt = b.dt * b.h * rng.uniform(0.2, 1.0, b.nelem)
+    check(b, stp.FP64, label="per-element-dt-h")
+    check(b, stp.FP32, label="per-element-dt-h")
+
+
+def test_dt_zero_returns_Q():
+    from paper_2003_12787_amd import runner
+    b = W.elastic_batch(3, 10, 805)
+    b.dt = np.zeros(b.nelem)
+    plan = stp.Plan([runner.class_of(b)], prec=stp.FP64)
+    got = runner.run(plan, b)
+    assert np.array_equal(got["qavg"], b.Q)
+
+
+# ------------------------------------------------------------------------------------------------ hetero
+def _hetero(hb, prec, sample_per_class=None, label="hetero"):
+    import torch
+    dt = torch.float64 if prec == stp.FP64 else torch.float32
+    dev = "cuda"
+    plan = stp.Plan(hb.classes, prec=prec)
+    say(f"[parity] {label} classes={len(hb.classes)} E={len(hb.cls)} prec={prec}")
+    Q = torch.from_numpy(hb.Q).to(dev, dt)
+    B = torch.from_numpy(hb.coef).to(dev, dt)
+    qavg = torch.zeros(hb.size_q, device=dev, dtype=dt)
+    favg = torch.zeros(3 * hb.size_q, device=dev, dtype=dt)
+    qface = torch.zeros(hb.size_face, device=dev, dtype=dt)
+    to = lambda a, t: torch.from_numpy(np.ascontiguousarray(a)).to(dev, t)
+    cls, oq, oc, of = to(hb.cls, torch.int32), to(hb.off_q, torch.int64), to(hb.off_coef, torch.int64), to(hb.off_face, torch.int64)
+    dts, hs = to(hb.dt, torch.float64), to(hb.h, torch.float64)
+    batch = plan.batch(len(hb.cls), Q, qavg, favg, qface, dts, hs, B=B, cls=cls, off_q=oq, off_coef=oc, off_face=of)
+    plan.run(batch)
+    torch.cuda.synchronize()
+    qa, fa, qf = qavg.double().cpu().numpy(), favg.double().cpu().numpy(), qface.double().cpu().numpy()
+    worst = 0.0
+    for c, (N, m, _, _) in enumerate(hb.classes):
+        ids = hb.members[c]
+        pick = np.arange(len(ids)) if sample_per_class is None else spread(len(ids), sample_per_class, c)[:sample_per_class]
+        part = subset(hb.parts[c], pick)
+        if prec != stp.FP64:
+            part.Q = part.Q.astype(np.float32).astype(np.float64)
+            part.B = part.B.astype(np.float32).astype(np.float64)
+        ref = oracle_run(part)
+        n3, n2 = (N + 1) ** 3, (N + 1) ** 2
+        got = {"qavg": [], "favg": [], "qface": []}
+        for j in pick:
+            e = ids[j]
+            got["qavg"].append(qa[hb.off_q[e]:hb.off_q[e] + n3 * m].reshape(n3, m))
+            got["favg"].append(fa[3 * hb.off_q[e]:3 * hb.off_q[e] + 3 * n3 * m].reshape(3, n3, m))
+            got["qface"].append(qf[hb.off_face[e]:hb.off_face[e] + 6 * n2 * m].reshape(6, n2, m))
+        got = {k: np.stack(v) for k, v in got.items()}
+        err = max_rel_err(got, ref, part.Q, part.h)
+        worst = max(worst, max(err.values()))
+        for k, v in err.items():
+            assert v < TOL[prec], (N, m, k, v)
+    say(f"[parity]   worst max rel err {worst}")
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", [stp.FP64, stp.FP32])
+def test_heterogeneous_small(prec):
+    _hetero(W.hetero_generic_batch(600, 901, orders=[1, 2, 3, 5], nquants=[1, 4, 9]), prec)
+
+
+def test_c4_heterogeneous_full_size_sampled():
+    _hetero(W.hetero_generic_batch(16384, W.SEED0 + 3), stp.FP32, sample_per_class=6, label="C4-full")
+
+
+# ------------------------------------------------------------------------------------------------ edges
+def test_empty_batch_is_noop():
+    from paper_2003_12787_amd import runner
+    b = W.elastic_batch(3, 0, 1)
+    plan = stp.Plan([runner.class_of(b)], prec=stp.FP32)
+    db = runner.DeviceBatch(plan, b)
+    assert plan.run_status(db.cbatch) == stp.OK
+
+
+def test_deterministic_bitwise():
+    from paper_2003_12787_amd import runner
+    b = W.elastic_batch(7, 200, 31)
+    for prec in (stp.FP32, stp.FP64):
+        plan = stp.Plan([runner.class_of(b)], prec=prec)
+        o1 = runner.run(plan, b)
+        o2 = runner.run(plan, b)
+        for k in o1:
+            assert np.array_equal(o1[k], o2[k]), k
+
+
+def test_host_validation_errors():
+    import torch
+    from paper_2003_12787_amd import runner
+    b = W.elastic_batch(3, 8, 32)
+    plan = stp.Plan([runner.class_of(b)], prec=stp.FP32)
+    db = runner.DeviceBatch(plan, b)
+    bad = plan.batch(8, db.Q, db.Q, db.favg, db.qface, db.dt, db.h, params=db.params)  # qavg aliases Q
+    assert plan.run_status(bad) == stp.E_INVAL and "alias" in stp.last_error()
+    bad = plan.batch(8, None, db.qavg, db.favg, db.qface, db.dt, db.h, params=db.params)
+    assert plan.run_status(bad) == stp.E_INVAL
+    bad = plan.batch(8, db.Q, db.qavg, db.favg, db.qface, db.dt, -1.0, params=db.params)
+    assert plan.run_status(bad) == stp.E_INVAL
+    bad = plan.batch(8, db.Q, db.qavg, db.favg, db.qface, -0.1, 1.0, params=db.params)
+    assert plan.run_status(bad) == stp.E_INVAL
+    bad = plan.batch(8, db.Q, db.qavg, db.favg, db.qface, db.dt, db.h, params=None)
+    assert plan.run_status(bad) == stp.E_INVAL
+    torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------------------------------------------ serving
+def test_serving_submit_poll_matches_run():
+    import time
+    import torch
+    from paper_2003_12787_amd import runner
+    b = W.elastic_batch(4, 40, 33)
+    cls = runner.class_of(b)
+    plan = stp.Plan([cls], prec=stp.FP32, serve_mem_budget=64 << 20)
+    ref = runner.run(plan, b)
+    dbs = [runner.DeviceBatch(plan, b) for _ in range(5)]
+    tickets = [plan.submit(db.cbatch) for db in dbs]
+    plan.drain()
+    for t in tickets:
+        st, info = plan.poll(t)
+        assert st == stp.OK and info.t_done >= info.t_start >= info.t_submit
+        st, _ = plan.poll(t)
+        assert st == stp.E_INVAL  # retired
+    for db in dbs:
+        out = db.outputs()
+        for k in ref:
+            assert np.array_equal(out[k], ref[k])
+    # a batch larger than the whole budget is refused
+    small = stp.Plan([cls], prec=stp.FP32, serve_mem_budget=1024)
+    with pytest.raises(stp.StpError) as ei:
+        small.submit(runner.DeviceBatch(small, b).cbatch)
+    assert ei.value.status == stp.E_NOMEM
+    st, _ = plan.poll(123456789)
+    assert st == stp.E_INVAL
+    torch.cuda.synchronize()
+    del time

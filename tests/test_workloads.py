@@ -1,0 +1,49 @@
+"""The seeded input generators: shapes, seeding and the recipe's value ranges (no GPU)."""
+import numpy as np
+
+from paper_2003_12787_amd import workloads as W
+
+
+def test_named_workload_shapes_and_dt():
+    b = W.c1_elastic_n3()
+    assert b.Q.shape == (64, 64, 9) and b.params.shape == (64, 64, 3)
+    assert abs(b.dt[0] - 0.4 / (7 * np.sqrt((b.params[..., 1] + 2 * b.params[..., 2]) / b.params[..., 0]).max())) < 1e-15
+    assert 0.0255 < b.dt[0] < 0.027  # the bound 0.4/(7 sqrt(5)) for the sup of the material ranges
+    b = W.c2_acoustic_n5(nelem=1000)
+    assert b.Q.shape == (1000, 216, 4) and b.params.shape == (1000, 2) and b.coef_per_element
+    assert np.all(b.params[:, 0] == 1.0) and 1 <= b.params[:, 1].min() and b.params[:, 1].max() <= 2
+    assert 0.0257 < b.dt[0] < 0.0258
+    b = W.c3_elastic_n7(nelem=10)
+    assert b.Q.shape == (10, 512, 9)
+
+
+def test_seeding_is_reproducible():
+    a, b = W.elastic_batch(3, 5, 7), W.elastic_batch(3, 5, 7)
+    assert np.array_equal(a.Q, b.Q) and np.array_equal(a.params, b.params)
+    c = W.elastic_batch(3, 5, 8)
+    assert not np.array_equal(a.Q, c.Q)
+
+
+def test_plane_wave_recipe():
+    b = W.acoustic_plane_wave_batch(3, 27, 1, noise=0.0)
+    p, v = b.Q[..., 0], b.Q[..., 1:]
+    c = np.sqrt(b.params[:, 1] / b.params[:, 0])
+    khat = np.array([1.0, 2.0, 2.0]) / 3.0
+    assert np.allclose(v, khat[None, None, :] * (p / c[:, None])[..., None])
+
+
+def test_generic_and_hetero():
+    g = W.generic_batch(2, 5, 4, 3, with_A=True)
+    assert g.B.shape == (4, 3, 27, 5, 5) and g.A.shape == g.B.shape
+    s = W.point_source(g, 4)
+    assert s.shape == (4, 27 + 5 + 2)
+    hb = W.hetero_generic_batch(200, 5, orders=[1, 2], nquants=[1, 4])
+    assert len(hb.cls) == 200 and hb.Q.size == hb.size_q
+    for c, ids in enumerate(hb.members):
+        N, m = hb.classes[c][:2]
+        e = ids[0]
+        assert np.array_equal(hb.Q[hb.off_q[e]:hb.off_q[e] + (N + 1) ** 3 * m], hb.parts[c].Q[0].ravel())
+    Ns, ms = W.c4_classes(1000)
+    assert set(np.unique(Ns)) == set(range(2, 10)) and set(np.unique(ms)) == {4, 9}
+    sz = W.serving_batch_sizes(10000, 1)
+    assert sz.min() >= 1 and sz.max() <= 4096
