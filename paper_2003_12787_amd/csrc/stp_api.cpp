@@ -170,6 +170,30 @@ stp_status build_class(stp_plan_s* p, ClassState& cs)
     cs.kernel = select_kernel(p, cs);
     if (!cs.kernel.fn) return fail(STP_E_UNSUPPORTED, "no kernel for N=%d m=%d physics=%d", cs.cls.order,
                                    cs.cls.nquant, cs.cls.physics);
+    if (cs.kernel.aux == KernelInfo::kAuxEvenOdd) {
+        // even/odd split of D on the symmetric nodes: A = (D[i][j] - D[i][n-1-j])/2, B = (D[i][j] + D[i][n-1-j])/2
+        // (i, j < n/2), Cm[i] = D[i][mid], Am[j] = D[mid][j] for odd n
+        const int hh = n / 2;
+        double t[2 * 5 * 5 + 2 * 5] = {0};
+        for (int i = 0; i < hh; ++i)
+            for (int j = 0; j < hh; ++j) {
+                t[i * hh + j] = 0.5 * (D[i * n + j] - D[i * n + (n - 1 - j)]);
+                t[hh * hh + i * hh + j] = 0.5 * (D[i * n + j] + D[i * n + (n - 1 - j)]);
+            }
+        if (n % 2)
+            for (int i = 0; i < hh; ++i) {
+                t[2 * hh * hh + i] = D[i * n + hh];
+                t[2 * hh * hh + hh + i] = D[hh * n + i];
+            }
+        const int cnt = 2 * hh * hh + 2 * hh;
+        if (p->prec == STP_FP64) {
+            if ((st = upload(t, cnt > 0 ? cnt : 1, &cs.daux)) != STP_OK) return st;
+        } else {
+            float tf[2 * 5 * 5 + 2 * 5];
+            for (int i = 0; i < cnt; ++i) tf[i] = (float)t[i];
+            if ((st = upload(tf, cnt > 0 ? cnt : 1, &cs.daux)) != STP_OK) return st;
+        }
+    }
     cs.lds = cs.kernel.lds(cs.cls.nquant, hasA);
     if (cs.lds > kMaxLds)
         return fail(STP_E_UNSUPPORTED, "class N=%d m=%d needs %zu B of LDS (> %zu)", cs.cls.order, cs.cls.nquant,
@@ -195,7 +219,7 @@ stp_status build_class(stp_plan_s* p, ClassState& cs)
 void free_plan_memory(stp_plan_s* p)
 {
     for (auto& cs : p->classes) {
-        for (void* q : {cs.dD, cs.de0, cs.de1, cs.de0_64, cs.de1_64, cs.dDsplit})
+        for (void* q : {cs.dD, cs.de0, cs.de1, cs.de0_64, cs.de1_64, cs.dDsplit, cs.daux})
             if (q) (void)hipFree(q);
     }
     if (p->d_lists) (void)hipFree(p->d_lists);

@@ -7,17 +7,22 @@
 namespace stp {
 
 struct KernelInfo {
+    enum Aux { kAuxNone = 0, kAuxEvenOdd = 1 };  // which derivative table the kernel reads through StpArgs::D
     const void* fn = nullptr;               // __global__ function, launched with one StpArgs argument
     int block = 0;                          // threads per workgroup
     int mb = 0;                             // register bound on the quantity count
     int elems_per_block = 1;                // elements processed per workgroup iteration
     size_t (*lds)(int m, bool hasA) = nullptr;  // dynamic LDS bytes per workgroup
+    int aux = kAuxNone;
 };
 
 // Plain kernel (any class): FP64, or FP32 I/O with FP32 or FP64 accumulation.
 KernelInfo plain_kernel_f64(int N, int physics, int m);
 KernelInfo plain_kernel_f32(int N, int physics, int m);
 KernelInfo plain_kernel_f32acc64(int N, int physics, int m);
+// Fused kernel (presets, FP32, N <= 7): lanes own x-lines, even/odd derivatives, LDS transposes.
+KernelInfo fused_kernel_f32(int N, int physics);
+
 inline KernelInfo plain_kernel(int prec_fp64, int acc64, int N, int physics, int m)
 {
     if (prec_fp64) return plain_kernel_f64(N, physics, m);

@@ -54,7 +54,7 @@ StpArgs base_args(const stp_plan_s* p, const ClassState& cs, const stp_batch* b)
     a.favg = b->favg;
     a.qface = b->qface;
     a.fface = b->fface;
-    a.D = cs.dD;
+    a.D = cs.kernel.aux == KernelInfo::kAuxEvenOdd ? cs.daux : cs.dD;
     a.e0 = cs.de0;
     a.e1 = cs.de1;
     a.Dsplit = cs.dDsplit;
@@ -83,7 +83,20 @@ void free_scratch(HeteroScratch& s)
 
 KernelInfo select_kernel(stp_plan_s* p, const ClassState& cs)
 {
-    return plain_kernel(p->prec == STP_FP64, cs.acc64, cs.cls.order, cs.cls.physics, cs.cls.nquant);
+    const bool preset = cs.cls.physics != STP_GENERIC;
+    const bool fused_ok = preset && p->prec == STP_FP32 && !cs.acc64 && cs.cls.order <= 7 &&
+                          !(cs.cls.flags & STP_SRC_POINT);
+    switch (p->variant) {
+    case STP_VARIANT_PLAIN:
+        return plain_kernel(p->prec == STP_FP64, cs.acc64, cs.cls.order, cs.cls.physics, cs.cls.nquant);
+    case STP_VARIANT_FUSED:
+        return fused_ok ? fused_kernel_f32(cs.cls.order, cs.cls.physics) : KernelInfo{};
+    case STP_VARIANT_MFMA:
+        return KernelInfo{};
+    default:
+        if (fused_ok) return fused_kernel_f32(cs.cls.order, cs.cls.physics);
+        return plain_kernel(p->prec == STP_FP64, cs.acc64, cs.cls.order, cs.cls.physics, cs.cls.nquant);
+    }
 }
 
 stp_status launch_batch(stp_plan_s* p, const stp_batch* b, hipStream_t stream, HeteroScratch* scratch)

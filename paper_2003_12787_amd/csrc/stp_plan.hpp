@@ -28,6 +28,7 @@ struct ClassState {
     void* de0_64 = nullptr;  // FP64 face vectors (FP32 plans)
     void* de1_64 = nullptr;
     void* dDsplit = nullptr; // BF16 hi/lo tables (split-BF16x3 variant)
+    void* daux = nullptr;    // even/odd derivative tables in the compute precision (fused variant)
     bool acc64 = false;      // FP64 accumulation of q-bar and faces
     KernelInfo kernel;
     size_t lds = 0;

@@ -122,6 +122,36 @@ def test_c2_full_size_sampled():
     check(b, stp.FP64, sample=spread(b.nelem, 40, 2), label="C2-full")
 
 
+# ------------------------------------------------------------------------------------------------ variants
+@pytest.mark.parametrize("variant", [stp.VARIANT_PLAIN, stp.VARIANT_FUSED])
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7])
+def test_fp32_variants_elastic(variant, N):
+    check(W.elastic_batch(N, 37 + 13 * N, 900 + N), stp.FP32, variant=variant, label="elastic-variant")
+
+
+@pytest.mark.parametrize("variant", [stp.VARIANT_PLAIN, stp.VARIANT_FUSED])
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7])
+def test_fp32_variants_acoustic(variant, N):
+    check(W.acoustic_batch(N, 41 + 11 * N, 950 + N), stp.FP32, variant=variant, label="acoustic-variant")
+
+
+@pytest.mark.parametrize("variant", [stp.VARIANT_PLAIN, stp.VARIANT_FUSED])
+def test_c3_full_size_variants(variant):
+    b = W.c3_elastic_n7()
+    check(b, stp.FP32, variant=variant, sample=spread(b.nelem, 24, 7), label="C3-full")
+
+
+def test_fused_per_element_material_favg_sum_and_hetero_offsets():
+    b = W.acoustic_plane_wave_batch(5, 300, 17)
+    check(b, stp.FP32, variant=stp.VARIANT_FUSED, favg_sum=True, label="fused-favg-sum")
+
+
+def test_unsupported_variant_is_reported():
+    with pytest.raises(stp.StpError) as ei:
+        stp.Plan([(8, 9, stp.ELASTIC, 0)], prec=stp.FP32, variant=stp.VARIANT_FUSED)
+    assert ei.value.status == stp.E_UNSUPPORTED
+
+
 # ------------------------------------------------------------------------------------------------ generic
 @pytest.mark.parametrize("N,m", [(1, 1), (2, 5), (3, 9), (4, 16)])
 @pytest.mark.parametrize("prec", [stp.FP64, stp.FP32])
