@@ -67,6 +67,26 @@ def time_variant(name, plan, db, steps, warmup, torch):
             "wall_ms_per_step": wall / steps * 1e3}
 
 
+def measured_traffic(variant, launches_bytes):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of this variant,
+    scaled by the counters' reading of a copy of known size; None when the kernel source has changed since
+    the counters were taken (or none were taken)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None, None
+    rec = json.load(open(path)).get(variant)
+    if rec is None:
+        return None, None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update(open(os.path.join(ROOT, "paper_2003_12787_amd", "csrc", f), "rb").read())
+    if h.hexdigest()[:16] != rec["source_hash"]:
+        return None, None
+    t = (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024.0
+    return t, t / launches_bytes
+
+
 def copy_bandwidth(gib, torch):
     """Device-to-device copy of `gib` GiB (read + write), the measured HBM reference."""
     n = int(gib * (1 << 30)) // 4
@@ -143,7 +163,7 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": h["gflops"] / 1e3, "peak": ALU_PEAK_TFS[h["dtype"]], "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"], roof["traffic_over_algorithmic"] = measured_traffic(head, h["bytes_per_element"] * E)
     roof["kernel"] = head
     roof["hbm_frac"] = h["hbm_gbs_algorithmic"] / HBM_PEAK_GBS
     roof["alu_frac"] = h["gflops"] / 1e3 / ALU_PEAK_TFS[h["dtype"]]
