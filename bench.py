@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--copy-gib", type=float, default=1.0,
                     help="size of the device-to-device copy timed as the measured HBM reference (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--variants", default="fp64_plain,fp32_plain")
+    ap.add_argument("--variants", default="fp64_plain,fp32_plain,fp32_fused,bf16x3_mfma")
     return ap.parse_args()
 
 

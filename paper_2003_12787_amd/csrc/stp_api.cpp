@@ -194,6 +194,26 @@ stp_status build_class(stp_plan_s* p, ClassState& cs)
             if ((st = upload(tf, cnt > 0 ? cnt : 1, &cs.daux)) != STP_OK) return st;
         }
     }
+    if (cs.kernel.aux == KernelInfo::kAuxMfmaSplit) {
+        // A operands of v_mfma_f32_16x16x16_bf16 for the split contraction: lane l holds row i = l % 16 and
+        // K entries k = 4 (l / 16) + t (t = 0..3), which pair with node x = 4 ((l / 16) % 2) + t of the hi
+        // (l / 16 < 2) or lo (l / 16 >= 2) part of a line. Matrices: D_hi and D_lo in the top row block
+        // (rows 0..7), then in the bottom row block (rows 8..15).
+        float Df[kMaxNodes * kMaxNodes];
+        derivative_matrix_f32(n, D, Df);
+        uint16_t Dh[kMaxNodes * kMaxNodes], Dl[kMaxNodes * kMaxNodes];
+        split_bf16(n * n, Df, Dh, Dl);
+        uint16_t tab[4][64][4];
+        for (int mat = 0; mat < 4; ++mat)
+            for (int l = 0; l < 64; ++l)
+                for (int t = 0; t < 4; ++t) {
+                    const int i = l % 16, kq = l / 16, x = 4 * (kq % 2) + t;
+                    const bool top = mat < 2, use = top ? i < 8 : i >= 8;
+                    const uint16_t* src = (mat % 2 == 0) ? Dh : Dl;
+                    tab[mat][l][t] = use ? src[(i % 8) * n + x] : (uint16_t)0;
+                }
+        if ((st = upload(&tab[0][0][0], 4 * 64 * 4, &cs.dDsplit)) != STP_OK) return st;
+    }
     cs.lds = cs.kernel.lds(cs.cls.nquant, hasA);
     if (cs.lds > kMaxLds)
         return fail(STP_E_UNSUPPORTED, "class N=%d m=%d needs %zu B of LDS (> %zu)", cs.cls.order, cs.cls.nquant,

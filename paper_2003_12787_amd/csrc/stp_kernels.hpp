@@ -7,7 +7,7 @@
 namespace stp {
 
 struct KernelInfo {
-    enum Aux { kAuxNone = 0, kAuxEvenOdd = 1 };  // which derivative table the kernel reads through StpArgs::D
+    enum Aux { kAuxNone = 0, kAuxEvenOdd = 1, kAuxMfmaSplit = 2 };  // which derivative table the kernel reads through StpArgs::D
     const void* fn = nullptr;               // __global__ function, launched with one StpArgs argument
     int block = 0;                          // threads per workgroup
     int mb = 0;                             // register bound on the quantity count
@@ -22,6 +22,9 @@ KernelInfo plain_kernel_f32(int N, int physics, int m);
 KernelInfo plain_kernel_f32acc64(int N, int physics, int m);
 // Fused kernel (presets, FP32, N <= 7): lanes own x-lines, even/odd derivatives, LDS transposes.
 KernelInfo fused_kernel_f32(int N, int physics);
+
+// Split-BF16 MFMA kernel (presets, FP32 I/O, N = 7).
+KernelInfo mfma_kernel_n7(int physics);
 
 inline KernelInfo plain_kernel(int prec_fp64, int acc64, int N, int physics, int m)
 {

@@ -84,18 +84,23 @@ void free_scratch(HeteroScratch& s)
 KernelInfo select_kernel(stp_plan_s* p, const ClassState& cs)
 {
     const bool preset = cs.cls.physics != STP_GENERIC;
-    const bool fused_ok = preset && p->prec == STP_FP32 && !cs.acc64 && cs.cls.order <= 7 &&
-                          !(cs.cls.flags & STP_SRC_POINT);
+    const bool f32io = p->prec != STP_FP64;
+    const bool simple = preset && f32io && !cs.acc64 && !(cs.cls.flags & STP_SRC_POINT);
+    const bool fused_ok = simple && cs.cls.order <= 7;
+    const bool mfma_ok = simple && cs.cls.order == 7 && p->prec == STP_BF16X3;
+    const KernelInfo plain = plain_kernel(p->prec == STP_FP64, cs.acc64, cs.cls.order, cs.cls.physics, cs.cls.nquant);
     switch (p->variant) {
     case STP_VARIANT_PLAIN:
-        return plain_kernel(p->prec == STP_FP64, cs.acc64, cs.cls.order, cs.cls.physics, cs.cls.nquant);
+        return plain;
     case STP_VARIANT_FUSED:
         return fused_ok ? fused_kernel_f32(cs.cls.order, cs.cls.physics) : KernelInfo{};
     case STP_VARIANT_MFMA:
-        return KernelInfo{};
+        return mfma_ok ? mfma_kernel_n7(cs.cls.physics) : KernelInfo{};
     default:
+        // split-BF16 plans use the matrix cores where a kernel exists and the FP32 kernels elsewhere
+        if (mfma_ok) return mfma_kernel_n7(cs.cls.physics);
         if (fused_ok) return fused_kernel_f32(cs.cls.order, cs.cls.physics);
-        return plain_kernel(p->prec == STP_FP64, cs.acc64, cs.cls.order, cs.cls.physics, cs.cls.nquant);
+        return plain;
     }
 }
 

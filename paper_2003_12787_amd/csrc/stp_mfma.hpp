@@ -1,0 +1,394 @@
+// stp_mfma.hpp -- predictor kernel with the derivative contractions on the matrix cores (MFMA), for the
+// physics presets at order N = 7 (8 nodes per axis), FP32 I/O.
+//
+// Mathematics as in the other kernels (Sec. II-A, Eq. (4), Fig. 5 recompute of favg, Sec. II-B faces). Only
+// the 1D derivative u -> D u (the sum-factorised contraction of Sec. III-B) runs on MFMA, as split-BF16
+// products with FP32 accumulation: u = u_hi + u_lo and D = D_hi + D_lo with hi = bf16(x) (nearest) and
+// lo = bf16(x - hi); the products D_hi u_hi + D_hi u_lo + D_lo u_hi + D_lo u_lo are formed by two
+// v_mfma_f32_16x16x16_bf16 per 16 lines (the K dimension carries [hi | lo] of a line, so the fourth
+// product costs nothing).
+//
+// Lane layout: an element is 128 lanes (two waves). Lane (wave w, lane l): line c = l % 16 of group
+// g = l / 32, half h = (l / 16) % 2, line index 32 w + 16 g + c, nodes 4h..4h+3 along the line. For the
+// x-direction the owner's registers already hold its half-line: each lane forms hi/lo of its 4 values, one
+// permlane32 swap of (hi, lo) produces the B operands of both 16-line groups of the wave, and
+//   C = A1top B1 + A2top B1 + A1bot B2 + A2bot B2
+// with A*top = [D rows; 0] and A*bot = [0; D rows] leaves D u exactly at each owner's 4 nodes. The y- and
+// z-directions use the same lane roles on lines read from an LDS tile of p, and return the derivatives to the
+// owners through an LDS exchange buffer (as in the fused kernel). Pointwise terms, the time accumulation and
+// the faces stay on the VALU in FP32.
+#pragma once
+#include "stp_device.hpp"
+#include "stp_fused.hpp"
+#include "stp_kernels.hpp"
+
+namespace stp {
+namespace mfma {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// hi = bf16(x) (round to nearest even), lo = bf16(x - hi); two values packed per 32-bit word
+__device__ inline void split_pair(float a, float b, unsigned& hi, unsigned& lo)
+{
+    const __bf16 ha = (__bf16)a, hb = (__bf16)b;
+    const __bf16 la = (__bf16)(a - (float)ha), lb = (__bf16)(b - (float)hb);
+    hi = (unsigned)__builtin_bit_cast(unsigned short, ha) | ((unsigned)__builtin_bit_cast(unsigned short, hb) << 16);
+    lo = (unsigned)__builtin_bit_cast(unsigned short, la) | ((unsigned)__builtin_bit_cast(unsigned short, lb) << 16);
+}
+
+__device__ inline bf16x4 as_bf16x4(unsigned w0, unsigned w1)
+{
+    bf16x4 r;
+    r[0] = (short)(w0 & 0xffffu);
+    r[1] = (short)(w0 >> 16);
+    r[2] = (short)(w1 & 0xffffu);
+    r[3] = (short)(w1 >> 16);
+    return r;
+}
+
+// A operands of the two-product pair for the top (rows 0..7) and bottom (rows 8..15) row blocks
+struct AOps {
+    bf16x4 a1t, a2t, a1b, a2b;
+};
+
+// D u for the lane's half-line u[0..3]; the 16-line groups of the wave are formed by the permlane32 swap.
+__device__ inline void deriv_mfma(const AOps& A, const float (&u)[4], float (&out)[4])
+{
+    unsigned h0, l0, h1, l1;
+    split_pair(u[0], u[1], h0, l0);
+    split_pair(u[2], u[3], h1, l1);
+    // B1 = [hi of lanes 0..31 | lo of lanes 0..31], B2 = [hi of lanes 32..63 | lo of lanes 32..63]
+    auto s0 = __builtin_amdgcn_permlane32_swap(h0, l0, false, false);
+    auto s1 = __builtin_amdgcn_permlane32_swap(h1, l1, false, false);
+    const bf16x4 b1 = as_bf16x4(s0[0], s1[0]);
+    const bf16x4 b2 = as_bf16x4(s0[1], s1[1]);
+    f32x4 c = {0.f, 0.f, 0.f, 0.f};
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A.a1t, b1, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A.a2t, b1, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A.a1b, b2, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A.a2b, b2, c, 0, 0, 0);
+    out[0] = c[0];
+    out[1] = c[1];
+    out[2] = c[2];
+    out[3] = c[3];
+}
+
+template <int PHYS>
+struct Mfma8 {
+    static constexpr int N = 7, n = 8, n2 = 64, n3 = 512;
+    static constexpr int M = PhysTraits<PHYS>::m;
+    static constexpr int NP = PhysTraits<PHYS>::np;
+    static constexpr int WG = 128;  // one element per workgroup (two waves)
+    using S = fused::Sets<PHYS>;
+    static constexpr int NPS = S::NPS, NG = S::NG;
+    static constexpr int YS = 8, ZS = 69, SLOT = n * ZS;
+    static constexpr int ELDS = (NPS + NG) * SLOT;
+    static_assert(NPS + NG >= M, "face pass reuses the tile for all quantities");
+
+    // r[.][t] += contribution of the derivative g (quantity dq(D, K)) at the lane's 4 nodes
+    template <int D, int K>
+    __device__ static inline void ncp(const Material<float, PHYS> (&mt)[4], const float (&g)[4], float (&r)[M][4])
+    {
+        if constexpr (PHYS == kElastic) {
+            using P = PhysTraits<kElastic>;
+            if constexpr (K < 3) {
+                if constexpr (K == D) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        r[3 + D][t] = fma(mt[t].c[3], g[t], r[3 + D][t]);
+                        r[3 + (D + 1) % 3][t] = fma(mt[t].c[1], g[t], r[3 + (D + 1) % 3][t]);
+                        r[3 + (D + 2) % 3][t] = fma(mt[t].c[1], g[t], r[3 + (D + 2) % 3][t]);
+                    }
+                } else {
+                    constexpr int q = P::sig(D, K);
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) r[q][t] = fma(mt[t].c[2], g[t], r[q][t]);
+                }
+            } else {
+                constexpr int i = K - 3;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) r[i][t] = fma(mt[t].c[0], g[t], r[i][t]);
+            }
+        } else {
+            if constexpr (K == 0) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) r[1 + D][t] = fma(mt[t].c[1], g[t], r[1 + D][t]);
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) r[0][t] = fma(mt[t].c[0], g[t], r[0][t]);
+            }
+        }
+    }
+
+    template <int K = 0>
+    __device__ static inline void xpass(const AOps& A, const Material<float, PHYS> (&mt)[4], const float (&p)[M][4],
+                                        float (&r)[M][4])
+    {
+        if constexpr (K < NG) {
+            float g[4];
+            deriv_mfma(A, p[S::dq(0, K)], g);
+            ncp<0, K>(mt, g, r);
+            xpass<K + 1>(A, mt, p, r);
+        }
+    }
+
+    // tile address of node (z, y, x)
+    __device__ static inline int at(int z, int y, int x) { return z * ZS + y * YS + x; }
+
+    // y- or z-role: lines (a, b) = (z, x) resp. (y, x), nodes 4h..4h+3 along the line
+    template <int D>
+    __device__ static inline void transposed(const AOps& A, const float* P, float* G, int a, int b, int h)
+    {
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+            const int s = S::slot(S::dq(D, k));
+            float u[4], g[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) u[t] = D == 1 ? P[s * SLOT + at(a, 4 * h + t, b)] : P[s * SLOT + at(4 * h + t, a, b)];
+            deriv_mfma(A, u, g);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (D == 1) G[k * SLOT + at(a, 4 * h + t, b)] = g[t];
+                else G[k * SLOT + at(4 * h + t, a, b)] = g[t];
+            }
+        }
+    }
+
+    template <int D, int K = 0>
+    __device__ static inline void gather(const float* G, int z, int y, int h, const Material<float, PHYS> (&mt)[4],
+                                         float (&r)[M][4])
+    {
+        if constexpr (K < NG) {
+            float g[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) g[t] = G[K * SLOT + at(z, y, 4 * h + t)];
+            ncp<D, K>(mt, g, r);
+            gather<D, K + 1>(G, z, y, h, mt, r);
+        }
+    }
+
+    __device__ static inline void write_tile(float* P, int z, int y, int h, const float (&v)[M][4])
+    {
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            const int s = S::slot(q);
+            if (s < 0) continue;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) P[s * SLOT + at(z, y, 4 * h + t)] = v[q][t];
+        }
+    }
+
+    // 4 nodes x M quantities = 4M contiguous floats
+    __device__ static inline void load4(const float* src, float (&v)[M][4])
+    {
+        if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+            const float4* s4 = reinterpret_cast<const float4*>(src);
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                const float4 t = s4[i];
+                const int w = 4 * i;
+                v[(w + 0) % M][(w + 0) / M] = t.x;
+                v[(w + 1) % M][(w + 1) / M] = t.y;
+                v[(w + 2) % M][(w + 2) / M] = t.z;
+                v[(w + 3) % M][(w + 3) / M] = t.w;
+            }
+        } else {
+#pragma unroll
+            for (int w = 0; w < 4 * M; ++w) v[w % M][w / M] = src[w];
+        }
+    }
+
+    __device__ static inline void store4(float* dst, const float (&v)[M][4])
+    {
+        if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+            float4* d4 = reinterpret_cast<float4*>(dst);
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                const int w = 4 * i;
+                d4[i] = make_float4(v[(w + 0) % M][(w + 0) / M], v[(w + 1) % M][(w + 1) / M],
+                                    v[(w + 2) % M][(w + 2) / M], v[(w + 3) % M][(w + 3) / M]);
+            }
+        } else {
+#pragma unroll
+            for (int w = 0; w < 4 * M; ++w) dst[w] = v[w % M][w / M];
+        }
+    }
+
+    __device__ static void run(const StpArgs& a)
+    {
+        extern __shared__ __align__(16) unsigned char smem[];
+        const int tid = threadIdx.x;
+        const int wv = tid >> 6, l = tid & 63;
+        const int c = l & 15, h = (l >> 4) & 1, g = l >> 5;
+        const int line = 32 * wv + 16 * g + c;
+        const int la = line >> 3, lb = line & 7;  // owner (z, y); y-role (z, x); z-role (y, x)
+        float* P = reinterpret_cast<float*>(smem);
+        float* G = P + NPS * SLOT;
+        const bool per_elem = (a.flags & kParamPerElement) != 0;
+
+        AOps A;
+        {
+            // table: [4 matrices][64 lanes][4 bf16] in the order a1t, a2t, a1b, a2b
+            const unsigned* t = static_cast<const unsigned*>(a.Dsplit);
+            A.a1t = as_bf16x4(t[(0 * 64 + l) * 2], t[(0 * 64 + l) * 2 + 1]);
+            A.a2t = as_bf16x4(t[(1 * 64 + l) * 2], t[(1 * 64 + l) * 2 + 1]);
+            A.a1b = as_bf16x4(t[(2 * 64 + l) * 2], t[(2 * 64 + l) * 2 + 1]);
+            A.a2b = as_bf16x4(t[(3 * 64 + l) * 2], t[(3 * 64 + l) * 2 + 1]);
+        }
+        float e0[n], e1[n];
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+            e0[j] = ld<float>(a.e0, j);
+            e1[j] = ld<float>(a.e1, j);
+        }
+        const int64_t cnt = a.count ? (int64_t)*a.count : a.nelem;
+
+        for (int64_t it = blockIdx.x; it < cnt; it += gridDim.x) {
+            ElemRef er;
+            elem_ref(a, it, er);
+            const int64_t node0 = (int64_t)line * n + 4 * h;  // first of the lane's 4 nodes
+            float p[M][4], qb[M][4];
+            Material<float, PHYS> mt[4];
+            load4(static_cast<const float*>(a.Q) + er.q + node0 * M, p);
+            {
+                const double inv_h = 1.0 / er.h;
+                const float* par = static_cast<const float*>(a.params) + er.coef;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) mt[t].load(per_elem ? par : par + (node0 + t) * NP, inv_h);
+            }
+#pragma unroll
+            for (int q = 0; q < M; ++q)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) qb[q][t] = p[q][t];
+            float w = 1.f;
+            const float dt = (float)er.dt;
+            for (int o = 1; o <= N; ++o) {
+                write_tile(P, la, lb, h, p);
+                __syncthreads();
+                float r[M][4];
+#pragma unroll
+                for (int q = 0; q < M; ++q)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) r[q][t] = 0.f;
+                transposed<1>(A, P, G, la, lb, h);
+                xpass(A, mt, p, r);
+                __syncthreads();
+                gather<1>(G, la, lb, h, mt, r);
+                __syncthreads();
+                transposed<2>(A, P, G, la, lb, h);
+                __syncthreads();
+                gather<2>(G, la, lb, h, mt, r);
+                w = w * dt / (float)(o + 1);
+#pragma unroll
+                for (int q = 0; q < M; ++q)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        p[q][t] = r[q][t];
+                        qb[q][t] = fma(w, r[q][t], qb[q][t]);
+                    }
+                __syncthreads();
+            }
+
+            // outputs
+            const bool fsum = (a.flags & kFavgSum) != 0;
+            store4(static_cast<float*>(a.qavg) + er.q + node0 * M, qb);
+            write_tile(P, la, lb, h, qb);
+            __syncthreads();
+            {
+                float fx[M][4];
+#pragma unroll
+                for (int q = 0; q < M; ++q)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) fx[q][t] = 0.f;
+                transposed<1>(A, P, G, la, lb, h);
+                xpass(A, mt, qb, fx);
+                float* fav = static_cast<float*>(a.favg) + (fsum ? er.q : 3 * er.q) + node0 * M;
+                if (!fsum) {
+                    store4(fav, fx);
+#pragma unroll
+                    for (int q = 0; q < M; ++q)
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) fx[q][t] = 0.f;
+                }
+                __syncthreads();
+                gather<1>(G, la, lb, h, mt, fx);
+                if (!fsum) {
+                    store4(fav + (int64_t)n3 * M, fx);
+#pragma unroll
+                    for (int q = 0; q < M; ++q)
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) fx[q][t] = 0.f;
+                }
+                __syncthreads();
+                transposed<2>(A, P, G, la, lb, h);
+                __syncthreads();
+                gather<2>(G, la, lb, h, mt, fx);
+                store4(fsum ? fav : fav + 2 * (int64_t)n3 * M, fx);
+            }
+            // faces: partial sums over the lane's 4 nodes, completed with the other half-line (lane ^ 16)
+            float* qf = static_cast<float*>(a.qface) + er.face;
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < M; ++q)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) P[q * SLOT + at(la, lb, 4 * h + t)] = qb[q][t];
+#pragma unroll
+            for (int q = 0; q < M; ++q) {
+                float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    s0 = fma(e0[4 * h + t], qb[q][t], s0);
+                    s1 = fma(e1[4 * h + t], qb[q][t], s1);
+                }
+                s0 += __shfl_xor(s0, 16);
+                s1 += __shfl_xor(s1, 16);
+                qf[(int64_t)(h * n2 + line) * M + q] = h ? s1 : s0;  // x- (h = 0) and x+ (h = 1)
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < M; ++q) {
+                float y0 = 0.f, y1 = 0.f, z0 = 0.f, z1 = 0.f;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const float vy = P[q * SLOT + at(la, 4 * h + t, lb)];  // y-role (z, x)
+                    const float vz = P[q * SLOT + at(4 * h + t, la, lb)];  // z-role (y, x)
+                    y0 = fma(e0[4 * h + t], vy, y0);
+                    y1 = fma(e1[4 * h + t], vy, y1);
+                    z0 = fma(e0[4 * h + t], vz, z0);
+                    z1 = fma(e1[4 * h + t], vz, z1);
+                }
+                y0 += __shfl_xor(y0, 16);
+                y1 += __shfl_xor(y1, 16);
+                z0 += __shfl_xor(z0, 16);
+                z1 += __shfl_xor(z1, 16);
+                qf[(int64_t)((2 + h) * n2 + line) * M + q] = h ? y1 : y0;
+                qf[(int64_t)((4 + h) * n2 + line) * M + q] = h ? z1 : z0;
+            }
+            __syncthreads();
+        }
+    }
+};
+
+template <int PHYS>
+__global__ void __launch_bounds__(128) stp_mfma_kernel(StpArgs a)
+{
+    Mfma8<PHYS>::run(a);
+}
+
+template <int PHYS>
+KernelInfo mfma_info()
+{
+    using K = Mfma8<PHYS>;
+    KernelInfo ki;
+    ki.fn = reinterpret_cast<const void*>(&stp_mfma_kernel<PHYS>);
+    ki.block = K::WG;
+    ki.mb = K::M;
+    ki.elems_per_block = 1;
+    ki.lds = [](int, bool) -> size_t { return sizeof(float) * (size_t)K::ELDS; };
+    ki.aux = KernelInfo::kAuxMfmaSplit;
+    return ki;
+}
+
+}  // namespace mfma
+}  // namespace stp

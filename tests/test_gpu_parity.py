@@ -46,7 +46,7 @@ def subset(b, ids):
     return s
 
 
-def check(b, prec, variant=stp.VARIANT_AUTO, acc64=0, sample=None, favg_sum=False, label=""):
+def check(b, prec, variant=stp.VARIANT_AUTO, acc64=0, sample=None, favg_sum=False, label="", tol=None):
     from paper_2003_12787_amd import runner
     cls = runner.class_of(b, stp.FAVG_SUM if favg_sum else 0)
     plan = stp.Plan([cls], prec=prec, variant=variant, acc64_min_order=acc64)
@@ -62,7 +62,7 @@ def check(b, prec, variant=stp.VARIANT_AUTO, acc64=0, sample=None, favg_sum=Fals
     err = max_rel_err(got, ref, rb.Q, rb.h)
     say(f"[parity]   max rel err {err}")
     for k, v in err.items():
-        assert v < TOL[prec], (k, v)
+        assert v < (tol or TOL[prec]), (k, v)
     plan.close()
     return err
 
@@ -146,9 +146,52 @@ def test_fused_per_element_material_favg_sum_and_hetero_offsets():
     check(b, stp.FP32, variant=stp.VARIANT_FUSED, favg_sum=True, label="fused-favg-sum")
 
 
+@pytest.mark.parametrize("variant", [stp.VARIANT_AUTO, stp.VARIANT_MFMA])
+def test_bf16x3_mfma_elastic_n7(variant):
+    check(W.c3_elastic_n7(nelem=300), stp.BF16X3, variant=variant, label="bf16x3-C3-small")
+
+
+def test_bf16x3_mfma_acoustic_n7_and_favg_sum():
+    check(W.acoustic_batch(7, 150, 971), stp.BF16X3, variant=stp.VARIANT_MFMA, label="bf16x3-acoustic")
+    check(W.acoustic_batch(7, 150, 971), stp.BF16X3, variant=stp.VARIANT_MFMA, favg_sum=True,
+          label="bf16x3-acoustic-favg-sum")
+
+
+def test_bf16x3_mfma_smooth_plane_wave_error_bound():
+    """Smooth fields: the two-term BF16 split keeps about 16 significant bits (representation error up to
+    2^-16 relative), and the derivative of a smooth line cancels entries of D whose absolute row sum reaches
+    129 at n = 8 while |D u| ~ k h |u|. The derivative's relative error is then bounded by about
+    2^-16 * 129 / (k h) ~ 2.5e-3 for k h = 2 pi / 8; 1e-3 holds with the observed error cancellation.
+    (The FP32 kernels meet 1e-5 on the same data.)"""
+    b = W.acoustic_plane_wave_batch(7, 125, 972)
+    check(b, stp.BF16X3, variant=stp.VARIANT_MFMA, favg_sum=True, label="bf16x3-plane-wave", tol=1e-3)
+    check(b, stp.FP32, variant=stp.VARIANT_FUSED, favg_sum=True, label="fp32-plane-wave")
+
+
+def test_bf16x3_mfma_per_element_material_and_dt_h():
+    b = W.elastic_batch(7, 77, 973, per_node=False)
+    rng = np.random.default_rng(9)
+    b.h = rng.uniform(0.5, 2.0, b.nelem)
+    b.dt = b.dt * b.h * rng.uniform(0.2, 1.0, b.nelem)
+    check(b, stp.BF16X3, variant=stp.VARIANT_MFMA, label="bf16x3-per-element")
+
+
+def test_bf16x3_full_size_sampled():
+    b = W.c3_elastic_n7()
+    check(b, stp.BF16X3, variant=stp.VARIANT_MFMA, sample=spread(b.nelem, 24, 11), label="bf16x3-C3-full")
+
+
+@pytest.mark.parametrize("N", [2, 5, 8])
+def test_bf16x3_plan_other_orders_use_fp32_kernels(N):
+    check(W.elastic_batch(N, 40, 980 + N), stp.BF16X3, label="bf16x3-fallback")
+
+
 def test_unsupported_variant_is_reported():
     with pytest.raises(stp.StpError) as ei:
         stp.Plan([(8, 9, stp.ELASTIC, 0)], prec=stp.FP32, variant=stp.VARIANT_FUSED)
+    assert ei.value.status == stp.E_UNSUPPORTED
+    with pytest.raises(stp.StpError) as ei:
+        stp.Plan([(6, 9, stp.ELASTIC, 0)], prec=stp.BF16X3, variant=stp.VARIANT_MFMA)
     assert ei.value.status == stp.E_UNSUPPORTED
 
 
