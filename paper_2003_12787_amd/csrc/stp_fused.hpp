@@ -256,6 +256,36 @@ struct Fused {
         for (int w = 0; w < n * M; ++w) dst[w] = v[w % M][w / M];
     }
 
+    // Store one output block of the element (n^2 lines x n nodes x M contiguous values at `dst`) through the
+    // LDS scratch `S` of `cap` values, as many lines per round as fit, so that consecutive lanes of the
+    // element store consecutive words. Starts with a barrier (the scratch may still be read) and ends with
+    // one. Unaligned blocks are stored line by line from registers.
+    __device__ static inline void store_block(T* S, int cap, T* dst, const T (&v)[M][n], int li, bool act, bool aligned)
+    {
+        constexpr int LV = n * M;
+        const int R = cap / LV;
+        __syncthreads();
+        for (int r0 = 0; r0 < n2; r0 += R) {
+            if (aligned && li >= r0 && li < r0 + R) {
+#pragma unroll
+                for (int w = 0; w < LV; ++w) S[(li - r0) * LV + w] = v[w % M][w / M];
+            }
+            __syncthreads();
+            if (aligned) {
+                const int nv = (n2 - r0 < R ? n2 - r0 : R) * LV;
+                T* d = dst + (int64_t)r0 * LV;
+                if constexpr (sizeof(T) == 4 && (LV % 4) == 0) {
+                    for (int i = li; i < nv / 4; i += n2)
+                        reinterpret_cast<float4*>(d)[i] = reinterpret_cast<const float4*>(S)[i];
+                } else {
+                    for (int i = li; i < nv; i += n2) d[i] = S[i];
+                }
+            }
+            __syncthreads();
+        }
+        if (act && !aligned) store_line(dst + (int64_t)li * LV, v);
+    }
+
     __device__ static void run(const StpArgs& a)
     {
         extern __shared__ __align__(16) unsigned char smem[];
@@ -325,33 +355,33 @@ struct Fused {
                 __syncthreads();
             }
 
-            // outputs: q-bar, favg[d] = V_d(q-bar), faces
+            // outputs: q-bar, favg[d] = V_d(q-bar), faces. Output blocks are staged through the element's LDS
+            // region so that consecutive lanes store consecutive words.
             const bool fsum = (a.flags & kFavgSum) != 0;
-            if (act) {
-                store_line(static_cast<T*>(a.qavg) + er.q + (int64_t)li * n * M, qb);
-                write_tile(P, la, lb, qb);
-            }
-            __syncthreads();
+            const bool al = act && ((er.q & 3) == 0);
+            store_block(P, ELDS, act ? static_cast<T*>(a.qavg) + er.q : nullptr, qb, li, act, al);
             {
                 T fx[M][n];
 #pragma unroll
                 for (int q = 0; q < M; ++q)
 #pragma unroll
                     for (int x = 0; x < n; ++x) fx[q][x] = 0;
-                if (act) transposed<1>(tb, P, G, la, lb);
                 xpass(tb, mt, qb, fx);
-                T* fav = static_cast<T*>(a.favg) + (fsum ? er.q : 3 * er.q) + (int64_t)li * n * M;
-                if (act && !fsum) store_line(fav, fx);
+                T* fav = act ? static_cast<T*>(a.favg) + (fsum ? er.q : 3 * er.q) : nullptr;
                 if (!fsum) {
+                    store_block(P, ELDS, fav, fx, li, act, al);
 #pragma unroll
                     for (int q = 0; q < M; ++q)
 #pragma unroll
                         for (int x = 0; x < n; ++x) fx[q][x] = 0;
                 }
+                if (act) write_tile(P, la, lb, qb);
+                __syncthreads();
+                if (act) transposed<1>(tb, P, G, la, lb);
                 __syncthreads();
                 if (act) gather<1>(G, la, lb, mt, fx);
-                if (act && !fsum) store_line(fav + (int64_t)n3 * M, fx);
                 if (!fsum) {
+                    store_block(G, NG * SLOT, act ? fav + (int64_t)n3 * M : nullptr, fx, li, act, al);
 #pragma unroll
                     for (int q = 0; q < M; ++q)
 #pragma unroll
@@ -361,7 +391,7 @@ struct Fused {
                 if (act) transposed<2>(tb, P, G, la, lb);
                 __syncthreads();
                 if (act) gather<2>(G, la, lb, mt, fx);
-                if (act) store_line(fsum ? fav : fav + 2 * (int64_t)n3 * M, fx);
+                store_block(P, ELDS, act ? (fsum ? fav : fav + 2 * (int64_t)n3 * M) : nullptr, fx, li, act, al);
             }
             // faces: x-faces from the owner's line; y- and z-faces from the full tile of q-bar
             T* qf = static_cast<T*>(a.qface) + er.face;

@@ -28,23 +28,35 @@ namespace mfma {
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// hi = bf16(x) (round to nearest even), lo = bf16(x - hi); two values packed per 32-bit word
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+// hi = bf16(x) (round to nearest even), lo = bf16(x - hi); two values packed per 32-bit word (one packed
+// conversion per pair; the hi parts are widened back to FP32 by shifting the bit patterns)
 __device__ inline void split_pair(float a, float b, unsigned& hi, unsigned& lo)
 {
-    const __bf16 ha = (__bf16)a, hb = (__bf16)b;
-    const __bf16 la = (__bf16)(a - (float)ha), lb = (__bf16)(b - (float)hb);
-    hi = (unsigned)__builtin_bit_cast(unsigned short, ha) | ((unsigned)__builtin_bit_cast(unsigned short, hb) << 16);
-    lo = (unsigned)__builtin_bit_cast(unsigned short, la) | ((unsigned)__builtin_bit_cast(unsigned short, lb) << 16);
+    const f32x2 v = {a, b};
+    const unsigned hu = __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
+    const f32x2 r = {a - __builtin_bit_cast(float, hu << 16), b - __builtin_bit_cast(float, hu & 0xffff0000u)};
+    hi = hu;
+    lo = __builtin_bit_cast(unsigned, __builtin_convertvector(r, bf16x2));
 }
 
 __device__ inline bf16x4 as_bf16x4(unsigned w0, unsigned w1)
 {
-    bf16x4 r;
-    r[0] = (short)(w0 & 0xffffu);
-    r[1] = (short)(w0 >> 16);
-    r[2] = (short)(w1 & 0xffffu);
-    r[3] = (short)(w1 >> 16);
-    return r;
+    const u32x2 t = {w0, w1};
+    return __builtin_bit_cast(bf16x4, t);
+}
+
+// A zero the compiler cannot see through: LDS base addresses derived from it are recomputed where they are
+// used instead of being hoisted out of the Taylor loop (each quantity slot needs its own base register for
+// the paired LDS accesses, and keeping them all live would halve the occupancy).
+__device__ inline int opaque_zero()
+{
+    int z = 0;
+    asm volatile("" : "+v"(z));
+    return z;
 }
 
 // A operands of the two-product pair for the top (rows 0..7) and bottom (rows 8..15) row blocks
@@ -82,8 +94,12 @@ struct Mfma8 {
     static constexpr int WG = 128;  // one element per workgroup (two waves)
     using S = fused::Sets<PHYS>;
     static constexpr int NPS = S::NPS, NG = S::NG;
-    static constexpr int YS = 8, ZS = 69, SLOT = n * ZS;
+    static constexpr int YS = 8, ZS = 69, SLOT = n * ZS;  // compact tile: 4 elements per CU fit in LDS
     static constexpr int ELDS = (NPS + NG) * SLOT;
+    static constexpr int STAGE = 16 * n * M;  // per-wave staging of 16 lines of an output block (floats)
+    static constexpr int LDS_FLOATS = ELDS + 2 * STAGE;
+    static constexpr int FACE_OFF = M * SLOT;  // face staging after the q-bar tile of the face pass
+    static_assert(FACE_OFF + 6 * n2 * M <= LDS_FLOATS, "face staging fits the LDS region");
     static_assert(NPS + NG >= M, "face pass reuses the tile for all quantities");
 
     // r[.][t] += contribution of the derivative g (quantity dq(D, K)) at the lane's 4 nodes
@@ -129,6 +145,7 @@ struct Mfma8 {
             float g[4];
             deriv_mfma(A, p[S::dq(0, K)], g);
             ncp<0, K>(mt, g, r);
+            __builtin_amdgcn_sched_barrier(0);  // one quantity at a time: bounds the live registers
             xpass<K + 1>(A, mt, p, r);
         }
     }
@@ -138,8 +155,11 @@ struct Mfma8 {
 
     // y- or z-role: lines (a, b) = (z, x) resp. (y, x), nodes 4h..4h+3 along the line
     template <int D>
-    __device__ static inline void transposed(const AOps& A, const float* P, float* G, int a, int b, int h)
+    __device__ static inline void transposed(const AOps& A, const float* P0, float* G0, int a, int b, int h)
     {
+        const int z0 = opaque_zero();
+        const float* P = P0 + z0;
+        float* G = G0 + z0;
 #pragma unroll
         for (int k = 0; k < NG; ++k) {
             const int s = S::slot(S::dq(D, k));
@@ -152,13 +172,15 @@ struct Mfma8 {
                 if (D == 1) G[k * SLOT + at(a, 4 * h + t, b)] = g[t];
                 else G[k * SLOT + at(4 * h + t, a, b)] = g[t];
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 
     template <int D, int K = 0>
-    __device__ static inline void gather(const float* G, int z, int y, int h, const Material<float, PHYS> (&mt)[4],
+    __device__ static inline void gather(const float* G0, int z, int y, int h, const Material<float, PHYS> (&mt)[4],
                                          float (&r)[M][4])
     {
+        const float* G = G0 + (K == 0 ? opaque_zero() : 0);
         if constexpr (K < NG) {
             float g[4];
 #pragma unroll
@@ -168,8 +190,9 @@ struct Mfma8 {
         }
     }
 
-    __device__ static inline void write_tile(float* P, int z, int y, int h, const float (&v)[M][4])
+    __device__ static inline void write_tile(float* P0, int z, int y, int h, const float (&v)[M][4])
     {
+        float* P = P0 + opaque_zero();
 #pragma unroll
         for (int q = 0; q < M; ++q) {
             const int s = S::slot(q);
@@ -215,6 +238,36 @@ struct Mfma8 {
         }
     }
 
+    // Store the wave's 32 half-line pairs of one output block (32 lines x 8 nodes x M contiguous floats at
+    // `dst`) through the wave's LDS staging area, 16 lines per round, so that each 16-byte store instruction
+    // of the wave covers 1 KB of consecutive addresses. Falls back to per-lane stores when misaligned.
+    __device__ static inline void store_block(float* S, float* dst, const float (&v)[M][4], int l, int g, int c, int h,
+                                              bool aligned)
+    {
+        if (!aligned) {
+            store4(dst + ((16 * g + c) * n + 4 * h) * M, v);
+            return;
+        }
+#pragma unroll
+        for (int rnd = 0; rnd < 2; ++rnd) {
+            if (g == rnd) {
+                float4* s4 = reinterpret_cast<float4*>(S + (c * 2 + h) * 4 * M);
+#pragma unroll
+                for (int i = 0; i < M; ++i) {
+                    const int w = 4 * i;
+                    s4[i] = make_float4(v[(w + 0) % M][(w + 0) / M], v[(w + 1) % M][(w + 1) / M],
+                                        v[(w + 2) % M][(w + 2) / M], v[(w + 3) % M][(w + 3) / M]);
+                }
+            }
+            __syncthreads();
+            const float4* r4 = reinterpret_cast<const float4*>(S);
+            float4* d4 = reinterpret_cast<float4*>(dst + rnd * STAGE);
+#pragma unroll 2
+            for (int i = l; i < STAGE / 4; i += 64) d4[i] = r4[i];
+            __syncthreads();
+        }
+    }
+
     __device__ static void run(const StpArgs& a)
     {
         extern __shared__ __align__(16) unsigned char smem[];
@@ -225,6 +278,7 @@ struct Mfma8 {
         const int la = line >> 3, lb = line & 7;  // owner (z, y); y-role (z, x); z-role (y, x)
         float* P = reinterpret_cast<float*>(smem);
         float* G = P + NPS * SLOT;
+        float* Sw = P + ELDS + wv * STAGE;  // this wave's staging area
         const bool per_elem = (a.flags & kParamPerElement) != 0;
 
         AOps A;
@@ -235,12 +289,6 @@ struct Mfma8 {
             A.a2t = as_bf16x4(t[(1 * 64 + l) * 2], t[(1 * 64 + l) * 2 + 1]);
             A.a1b = as_bf16x4(t[(2 * 64 + l) * 2], t[(2 * 64 + l) * 2 + 1]);
             A.a2b = as_bf16x4(t[(3 * 64 + l) * 2], t[(3 * 64 + l) * 2 + 1]);
-        }
-        float e0[n], e1[n];
-#pragma unroll
-        for (int j = 0; j < n; ++j) {
-            e0[j] = ld<float>(a.e0, j);
-            e1[j] = ld<float>(a.e1, j);
         }
         const int64_t cnt = a.count ? (int64_t)*a.count : a.nelem;
 
@@ -263,6 +311,7 @@ struct Mfma8 {
                 for (int t = 0; t < 4; ++t) qb[q][t] = p[q][t];
             float w = 1.f;
             const float dt = (float)er.dt;
+#pragma unroll 1
             for (int o = 1; o <= N; ++o) {
                 write_tile(P, la, lb, h, p);
                 __syncthreads();
@@ -292,7 +341,9 @@ struct Mfma8 {
 
             // outputs
             const bool fsum = (a.flags & kFavgSum) != 0;
-            store4(static_cast<float*>(a.qavg) + er.q + node0 * M, qb);
+            const bool al = (er.q & 3) == 0;  // 16-byte aligned element blocks (float offsets)
+            const int64_t wbase = (int64_t)32 * wv * n * M;  // first float of this wave's lines in a block
+            store_block(Sw, static_cast<float*>(a.qavg) + er.q + wbase, qb, l, g, c, h, al);
             write_tile(P, la, lb, h, qb);
             __syncthreads();
             {
@@ -303,9 +354,9 @@ struct Mfma8 {
                     for (int t = 0; t < 4; ++t) fx[q][t] = 0.f;
                 transposed<1>(A, P, G, la, lb, h);
                 xpass(A, mt, qb, fx);
-                float* fav = static_cast<float*>(a.favg) + (fsum ? er.q : 3 * er.q) + node0 * M;
+                float* fav = static_cast<float*>(a.favg) + (fsum ? er.q : 3 * er.q) + wbase;
                 if (!fsum) {
-                    store4(fav, fx);
+                    store_block(Sw, fav, fx, l, g, c, h, al);
 #pragma unroll
                     for (int q = 0; q < M; ++q)
 #pragma unroll
@@ -314,7 +365,7 @@ struct Mfma8 {
                 __syncthreads();
                 gather<1>(G, la, lb, h, mt, fx);
                 if (!fsum) {
-                    store4(fav + (int64_t)n3 * M, fx);
+                    store_block(Sw, fav + (int64_t)n3 * M, fx, l, g, c, h, al);
 #pragma unroll
                     for (int q = 0; q < M; ++q)
 #pragma unroll
@@ -324,10 +375,17 @@ struct Mfma8 {
                 transposed<2>(A, P, G, la, lb, h);
                 __syncthreads();
                 gather<2>(G, la, lb, h, mt, fx);
-                store4(fsum ? fav : fav + 2 * (int64_t)n3 * M, fx);
+                store_block(Sw, fsum ? fav : fav + 2 * (int64_t)n3 * M, fx, l, g, c, h, al);
             }
-            // faces: partial sums over the lane's 4 nodes, completed with the other half-line (lane ^ 16)
-            float* qf = static_cast<float*>(a.qface) + er.face;
+            // faces: partial sums over the lane's 4 nodes, completed with the other half-line (lane ^ 16); the
+            // face values are staged in LDS in the output layout [f][a][b][s] and written with coalesced stores
+            float* F = P + FACE_OFF;
+            float e0[4], e1[4];  // face vectors at the lane's 4 nodes along a line
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                e0[t] = ld<float>(a.e0, 4 * h + t);
+                e1[t] = ld<float>(a.e1, 4 * h + t);
+            }
             __syncthreads();
 #pragma unroll
             for (int q = 0; q < M; ++q)
@@ -338,12 +396,12 @@ struct Mfma8 {
                 float s0 = 0.f, s1 = 0.f;
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    s0 = fma(e0[4 * h + t], qb[q][t], s0);
-                    s1 = fma(e1[4 * h + t], qb[q][t], s1);
+                    s0 = fma(e0[t], qb[q][t], s0);
+                    s1 = fma(e1[t], qb[q][t], s1);
                 }
                 s0 += __shfl_xor(s0, 16);
                 s1 += __shfl_xor(s1, 16);
-                qf[(int64_t)(h * n2 + line) * M + q] = h ? s1 : s0;  // x- (h = 0) and x+ (h = 1)
+                F[(h * n2 + line) * M + q] = h ? s1 : s0;  // x- (h = 0) and x+ (h = 1)
             }
             __syncthreads();
 #pragma unroll
@@ -353,17 +411,27 @@ struct Mfma8 {
                 for (int t = 0; t < 4; ++t) {
                     const float vy = P[q * SLOT + at(la, 4 * h + t, lb)];  // y-role (z, x)
                     const float vz = P[q * SLOT + at(4 * h + t, la, lb)];  // z-role (y, x)
-                    y0 = fma(e0[4 * h + t], vy, y0);
-                    y1 = fma(e1[4 * h + t], vy, y1);
-                    z0 = fma(e0[4 * h + t], vz, z0);
-                    z1 = fma(e1[4 * h + t], vz, z1);
+                    y0 = fma(e0[t], vy, y0);
+                    y1 = fma(e1[t], vy, y1);
+                    z0 = fma(e0[t], vz, z0);
+                    z1 = fma(e1[t], vz, z1);
                 }
                 y0 += __shfl_xor(y0, 16);
                 y1 += __shfl_xor(y1, 16);
                 z0 += __shfl_xor(z0, 16);
                 z1 += __shfl_xor(z1, 16);
-                qf[(int64_t)((2 + h) * n2 + line) * M + q] = h ? y1 : y0;
-                qf[(int64_t)((4 + h) * n2 + line) * M + q] = h ? z1 : z0;
+                F[((2 + h) * n2 + line) * M + q] = h ? y1 : y0;
+                F[((4 + h) * n2 + line) * M + q] = h ? z1 : z0;
+            }
+            __syncthreads();
+            float* qf = static_cast<float*>(a.qface) + er.face;
+            if ((er.face & 3) == 0) {
+                const float4* f4 = reinterpret_cast<const float4*>(F);
+                float4* d4 = reinterpret_cast<float4*>(qf);
+#pragma unroll 2
+                for (int i = tid; i < 6 * n2 * M / 4; i += WG) d4[i] = f4[i];
+            } else {
+                for (int i = tid; i < 6 * n2 * M; i += WG) qf[i] = F[i];
             }
             __syncthreads();
         }
@@ -385,7 +453,7 @@ KernelInfo mfma_info()
     ki.block = K::WG;
     ki.mb = K::M;
     ki.elems_per_block = 1;
-    ki.lds = [](int, bool) -> size_t { return sizeof(float) * (size_t)K::ELDS; };
+    ki.lds = [](int, bool) -> size_t { return sizeof(float) * (size_t)K::LDS_FLOATS; };
     ki.aux = KernelInfo::kAuxMfmaSplit;
     return ki;
 }
