@@ -45,8 +45,8 @@
  * Ownership: the caller owns every buffer and passes raw pointers; device pointers must be device memory
  * of the plan's device. The library never frees or retains caller buffers after stp_run returns (after
  * stp_submit they must stay valid until stp_poll reports completion). The plan owns its constant tables,
- * streams, events and scratch; it is immutable after creation and stp_run may be called concurrently from
- * several host threads on different streams.
+ * streams, events and scratch; its tables are immutable after creation and stp_run may be called from
+ * several host threads on different streams (see stp_run for heterogeneous plans).
  *
  * Errors: every entry point returns a stp_status and never throws or aborts. Problems detectable on the
  * host (bad sizes, NULL required pointers, unsupported order/quantity count, h <= 0 or dt < 0 given as host
@@ -154,9 +154,23 @@ stp_status stp_plan(const stp_plan_desc* desc, stp_plan_t* out);
 void stp_plan_free(stp_plan_t plan);
 
 /* Run the predictor on a batch, asynchronously on the HIP stream `hip_stream` (NULL = the null stream).
- * Returns after the launches are queued. Stream-capturable when batch->dt_h_scalar = 1 or dt/h are
- * device arrays (no host synchronisation, no allocation). */
+ * Returns after the launches are queued.
+ * Single-class plan: one launch, no allocation; stream-capturable. Calls may overlap on different streams.
+ * Heterogeneous plan (nclass > 1): a bucketing pass sorts the elements by class, then classes of order <= 7
+ * in FP32 I/O without FP64 accumulation run in one persistent launch per physics bucket (workgroups take
+ * tiles of one class from a queue, most expensive classes first) and the other classes run one launch each.
+ * The element lists and tile queues live in the plan's scratch, which the first call that needs more of it
+ * allocates synchronously (stp_reserve avoids that, after which the call is stream-capturable). Because the
+ * scratch is shared, stp_run calls of one heterogeneous plan must not overlap on the device: queue them on
+ * one stream, or use one plan per stream. */
 stp_status stp_run(stp_plan_t plan, const stp_batch* batch, void* hip_stream);
+
+/* Reserve the device scratch of heterogeneous plans (per-class element lists and tile queues) for batches of
+ * up to max_nelem elements, so that later stp_run calls allocate nothing: with a reservation in place stp_run
+ * queues only kernels (no allocation, memset or host synchronisation) and can be captured into a HIP graph.
+ * Synchronous; a no-op for single-class plans. STP_E_INVAL for a NULL plan or max_nelem outside
+ * 0..2^31-1, STP_E_DEVICE if the allocation fails. */
+stp_status stp_reserve(stp_plan_t plan, int64_t max_nelem);
 
 /* Serving: enqueue a batch for the plan's dispatcher thread. The batch descriptor is copied; its device
  * buffers must stay valid until stp_poll reports completion. Admission: the batch's output+scratch bytes

@@ -40,14 +40,15 @@ namespace {
 
 struct DeviceGuard {
     int prev = -1;
+    bool changed = false;
     explicit DeviceGuard(int dev)
     {
         if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
+        if (prev != dev) changed = hipSetDevice(dev) == hipSuccess;
     }
     ~DeviceGuard()
     {
-        if (prev >= 0) (void)hipSetDevice(prev);
+        if (changed && prev >= 0) (void)hipSetDevice(prev);
     }
 };
 
@@ -242,8 +243,9 @@ void free_plan_memory(stp_plan_s* p)
         for (void* q : {cs.dD, cs.de0, cs.de1, cs.de0_64, cs.de1_64, cs.dDsplit, cs.daux})
             if (q) (void)hipFree(q);
     }
-    if (p->d_lists) (void)hipFree(p->d_lists);
-    if (p->d_counts) (void)hipFree(p->d_counts);
+    for (void* q : {p->d_lists, p->d_counts, p->d_hcls, (void*)p->d_slots, (void*)p->d_orders, (void*)p->d_bncls})
+        if (q) (void)hipFree(q);
+    free_scratch(p->run_scratch);
 }
 
 }  // namespace
@@ -298,10 +300,11 @@ stp_status stp_plan(const stp_plan_desc* desc, stp_plan_t* out)
         }
     }
     if (desc->nclass > 1) {
-        if ((e = hipMalloc(&p->d_counts, sizeof(int32_t) * kMaxClasses)) != hipSuccess) {
+        stp_status st = hetero_prepare(p);
+        if (st != STP_OK) {
             free_plan_memory(p);
             delete p;
-            return hip_fail(e, "hipMalloc(counts)");
+            return st;
         }
     }
     if (p->serve_budget > 0) {
@@ -324,6 +327,17 @@ void stp_plan_free(stp_plan_t p)
     (void)hipDeviceSynchronize();
     free_plan_memory(p);
     delete p;
+}
+
+stp_status stp_reserve(stp_plan_t p, int64_t max_nelem)
+{
+    g_last_error.clear();
+    if (!p) return fail(STP_E_INVAL, "plan is NULL");
+    if (max_nelem < 0 || max_nelem > (int64_t)INT32_MAX) return fail(STP_E_INVAL, "max_nelem out of range");
+    if (p->classes.size() == 1) return STP_OK;  // uniform batches need no scratch
+    DeviceGuard g(p->device);
+    std::lock_guard<std::mutex> lk(p->run_mu);
+    return reserve_scratch(p, p->run_scratch, max_nelem);
 }
 
 stp_status stp_class_cost(stp_plan_t p, int cls, double* bytes, double* flops)

@@ -26,6 +26,15 @@ KernelInfo fused_kernel_f32(int N, int physics);
 // Split-BF16 MFMA kernel (presets, FP32 I/O, N = 7).
 KernelInfo mfma_kernel_n7(int physics);
 
+// Heterogeneous persistent kernel of one physics bucket (FP32 I/O, orders 1..7, 512 threads per workgroup).
+struct HeteroKernel {
+    const void* fn = nullptr;
+    size_t (*slot_lds)(int N, int m, bool hasA) = nullptr;
+    int threads = 0;
+    int max_order = 0;
+};
+HeteroKernel hetero_kernel_f32(int bucket);
+
 inline KernelInfo plain_kernel(int prec_fp64, int acc64, int N, int physics, int m)
 {
     if (prec_fp64) return plain_kernel_f64(N, physics, m);

@@ -3,6 +3,7 @@
 // followed by one persistent-grid launch per class, all on the caller's stream.
 #include <algorithm>
 
+#include "stp_hetero.hpp"
 #include "stp_plan.hpp"
 
 namespace stp {
@@ -24,6 +25,24 @@ __global__ void bucket_by_class(const int32_t* cls, int64_t nelem, int nclass, i
     if (c < 0 || c >= nclass) return;  // elements with an invalid class id are skipped
     int pos = atomicAdd(&counts[c], 1);
     lists[(int64_t)c * cap + pos] = (int32_t)e;
+}
+
+// Tile queues of the persistent kernel: for every bucket, the first tile of each class in processing order
+// and a reset tile counter. One thread per bucket.
+__global__ void hetero_setup(const int32_t* counts, const int32_t* slots, const int32_t* orders, const int32_t* bncls,
+                             int32_t* tile_start, int32_t* heads)
+{
+    const int b = threadIdx.x;
+    if (b >= kHeteroBuckets) return;
+    int acc = 0;
+    const int nc = bncls[b];
+    for (int k = 0; k < nc; ++k) {
+        tile_start[b * (kMaxClasses + 1) + k] = acc;
+        const int c = orders[b * kMaxClasses + k];
+        acc += (counts[c] + slots[c] - 1) / slots[c];
+    }
+    tile_start[b * (kMaxClasses + 1) + nc] = acc;
+    heads[b] = 0;
 }
 
 StpArgs base_args(const stp_plan_s* p, const ClassState& cs, const stp_batch* b)
@@ -76,8 +95,8 @@ stp_status launch_one(const ClassState& cs, StpArgs& a, int64_t grid, hipStream_
 
 void free_scratch(HeteroScratch& s)
 {
-    if (s.lists) (void)hipFree(s.lists);
-    if (s.counts) (void)hipFree(s.counts);
+    for (void* q : {(void*)s.lists, (void*)s.counts, (void*)s.tile_start, (void*)s.heads})
+        if (q) (void)hipFree(q);
     s = HeteroScratch{};
 }
 
@@ -104,6 +123,23 @@ KernelInfo select_kernel(stp_plan_s* p, const ClassState& cs)
     }
 }
 
+stp_status reserve_scratch(stp_plan_s* p, HeteroScratch& s, int64_t nelem)
+{
+    const int nclass = (int)p->classes.size();
+    if (s.cap >= nelem && s.counts) return STP_OK;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    free_scratch(s);
+    const size_t cap = (size_t)std::max<int64_t>(nelem, 1);
+    if ((e = hipMalloc(&s.lists, sizeof(int32_t) * (size_t)nclass * cap)) != hipSuccess) return hip_fail(e, "hipMalloc(lists)");
+    if ((e = hipMalloc(&s.counts, sizeof(int32_t) * kMaxClasses)) != hipSuccess) return hip_fail(e, "hipMalloc(counts)");
+    if ((e = hipMalloc(&s.tile_start, sizeof(int32_t) * kHeteroBuckets * (kMaxClasses + 1))) != hipSuccess)
+        return hip_fail(e, "hipMalloc(tile_start)");
+    if ((e = hipMalloc(&s.heads, sizeof(int32_t) * kHeteroBuckets)) != hipSuccess) return hip_fail(e, "hipMalloc(heads)");
+    s.cap = (int64_t)cap;
+    return STP_OK;
+}
+
 stp_status launch_batch(stp_plan_s* p, const stp_batch* b, hipStream_t stream, HeteroScratch* scratch)
 {
     const int nclass = (int)p->classes.size();
@@ -118,25 +154,22 @@ stp_status launch_batch(stp_plan_s* p, const stp_batch* b, hipStream_t stream, H
     {
         std::lock_guard<std::mutex> lk(p->run_mu);
         if (s->cap < b->nelem || !s->counts) {
-            // grow (synchronous allocation; a plan reused with batches of at most this size never reallocates)
-            hipError_t e = hipStreamSynchronize(stream);
-            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-            free_scratch(*s);
-            e = hipMalloc(&s->lists, sizeof(int32_t) * (size_t)nclass * (size_t)b->nelem);
-            if (e != hipSuccess) return hip_fail(e, "hipMalloc(lists)");
-            e = hipMalloc(&s->counts, sizeof(int32_t) * kMaxClasses);
-            if (e != hipSuccess) return hip_fail(e, "hipMalloc(counts)");
-            s->cap = b->nelem;
+            // grow (synchronous allocation); stp_reserve makes this a no-op, as graph capture requires
+            stp_status st = reserve_scratch(p, *s, b->nelem);
+            if (st != STP_OK) return st;
         }
     }
     hipLaunchKernelGGL(clear_counts, dim3(1), dim3(64), 0, stream, s->counts, nclass);
     hipLaunchKernelGGL(bucket_by_class, dim3((unsigned)((b->nelem + 255) / 256)), dim3(256), 0, stream, b->cls,
                        b->nelem, nclass, s->lists, s->cap, s->counts);
+    hipLaunchKernelGGL(hetero_setup, dim3(1), dim3(64), 0, stream, s->counts, p->d_slots, p->d_orders, p->d_bncls,
+                       s->tile_start, s->heads);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "bucket_by_class launch");
-    // most expensive classes first so that they start while cheaper ones fill in behind
-    std::vector<int> order(nclass);
-    for (int c = 0; c < nclass; ++c) order[c] = c;
+    if (e != hipSuccess) return hip_fail(e, "bucketing launch");
+    // classes with their own launch (high orders, FP64 accumulation or I/O), most expensive first
+    std::vector<int> order;
+    for (int c = 0; c < nclass; ++c)
+        if (!p->classes[c].tiled) order.push_back(c);
     std::sort(order.begin(), order.end(), [&](int x, int y) { return p->classes[x].flops > p->classes[y].flops; });
     for (int c : order) {
         const ClassState& cs = p->classes[c];
@@ -147,6 +180,97 @@ stp_status launch_batch(stp_plan_s* p, const stp_batch* b, hipStream_t stream, H
         stp_status st = launch_one(cs, a, grid, stream);
         if (st != STP_OK) return st;
     }
+    // one persistent launch per physics bucket for the tiled classes
+    for (int bk = 0; bk < kHeteroBuckets; ++bk) {
+        const BucketPlan& bp = p->buckets[bk];
+        if (bp.order.empty()) continue;
+        hetero::HArgs h{};
+        h.a = base_args(p, p->classes[bp.order[0]], b);
+        h.cls = static_cast<const hetero::HClass*>(p->d_hcls);
+        h.lists = s->lists;
+        h.cap = s->cap;
+        h.counts = s->counts;
+        h.order = p->d_orders + bk * kMaxClasses;
+        h.tile_start = s->tile_start + bk * (kMaxClasses + 1);
+        h.head = s->heads + bk;
+        h.ncls = (int)bp.order.size();
+        void* args[] = {&h};
+        const int grid = p->num_cus * p->hetero_grid_per_cu;
+        e = hipLaunchKernel(bp.kernel.fn, dim3(grid), dim3(bp.kernel.threads), args, bp.lds, stream);
+        if (e != hipSuccess) return hip_fail(e, "hipLaunchKernel(heterogeneous)");
+    }
+    return STP_OK;
+}
+
+stp_status hetero_prepare(stp_plan_s* p)
+{
+    const int nclass = (int)p->classes.size();
+    p->buckets.assign(kHeteroBuckets, BucketPlan{});
+    std::vector<hetero::HClass> hc(nclass);
+    std::vector<int32_t> slots(nclass, 1), orders(kHeteroBuckets * kMaxClasses, 0), bncls(kHeteroBuckets, 0);
+    const bool f32io = p->prec != STP_FP64;
+    for (int c = 0; c < nclass; ++c) {
+        ClassState& cs = p->classes[c];
+        const int N = cs.cls.order, nn = (N + 1) * (N + 1) * (N + 1);
+        const bool hasA = cs.cls.physics == STP_GENERIC && (cs.cls.flags & STP_A_PRESENT);
+        cs.tiled = false;
+        if (f32io && !cs.acc64 && N <= hetero::kMaxOrder) {
+            const int bk = hetero::bucket_of(cs.cls.physics, cs.cls.nquant);
+            const HeteroKernel k = hetero_kernel_f32(bk);
+            const size_t sl = k.fn ? k.slot_lds(N, cs.cls.nquant, hasA) : 0;
+            if (k.fn && sl <= kHeteroLdsBudget) {
+                cs.tiled = true;
+                cs.bucket = bk;
+                cs.slot_lds = sl;
+                cs.slots = (int)std::min<size_t>(k.threads / nn, kHeteroLdsBudget / sl);
+                p->buckets[bk].kernel = k;
+                p->buckets[bk].order.push_back(c);
+            }
+        }
+        hetero::HClass& h = hc[c];
+        h.N = N;
+        h.nn = nn;
+        h.slots = cs.tiled ? cs.slots : 1;
+        h.m = cs.cls.nquant;
+        h.flags = cs.cls.flags;
+        h.lds_slot = (unsigned)cs.slot_lds;
+        h.size_q = cs.size_q;
+        h.size_coef = cs.size_coef;
+        h.size_face = cs.size_face;
+        h.size_src = cs.size_src;
+        h.D = cs.dD;  // the plain element routine reads the full derivative matrix
+        h.e0 = cs.de0;
+        h.e1 = cs.de1;
+        slots[c] = h.slots;
+    }
+    for (int bk = 0; bk < kHeteroBuckets; ++bk) {
+        BucketPlan& bp = p->buckets[bk];
+        std::sort(bp.order.begin(), bp.order.end(),
+                  [&](int x, int y) { return p->classes[x].flops > p->classes[y].flops; });
+        bncls[bk] = (int32_t)bp.order.size();
+        for (size_t k = 0; k < bp.order.size(); ++k) {
+            orders[bk * kMaxClasses + k] = bp.order[k];
+            const ClassState& cs = p->classes[bp.order[k]];
+            bp.lds = std::max(bp.lds, cs.slot_lds * (size_t)cs.slots);
+        }
+        if (bp.lds > 64 * 1024) {
+            hipError_t e = hipFuncSetAttribute(bp.kernel.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp.lds);
+            if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(heterogeneous LDS)");
+        }
+    }
+    hipError_t e;
+    if ((e = hipMalloc(&p->d_hcls, sizeof(hetero::HClass) * nclass)) != hipSuccess) return hip_fail(e, "hipMalloc(classes)");
+    if ((e = hipMemcpy(p->d_hcls, hc.data(), sizeof(hetero::HClass) * nclass, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy(classes)");
+    if ((e = hipMalloc(&p->d_slots, sizeof(int32_t) * nclass)) != hipSuccess) return hip_fail(e, "hipMalloc(slots)");
+    if ((e = hipMemcpy(p->d_slots, slots.data(), sizeof(int32_t) * nclass, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy(slots)");
+    if ((e = hipMalloc(&p->d_orders, sizeof(int32_t) * orders.size())) != hipSuccess) return hip_fail(e, "hipMalloc(orders)");
+    if ((e = hipMemcpy(p->d_orders, orders.data(), sizeof(int32_t) * orders.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy(orders)");
+    if ((e = hipMalloc(&p->d_bncls, sizeof(int32_t) * kHeteroBuckets)) != hipSuccess) return hip_fail(e, "hipMalloc(bncls)");
+    if ((e = hipMemcpy(p->d_bncls, bncls.data(), sizeof(int32_t) * kHeteroBuckets, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy(bncls)");
     return STP_OK;
 }
 

@@ -21,7 +21,7 @@
 namespace stp {
 namespace plain {
 
-template <typename T, typename ACC, int N, int PHYS, int MB>
+template <typename T, typename ACC, int N, int PHYS, int MB, bool EX = false>
 struct Plain {
     static constexpr int n = N + 1;
     static constexpr int n2 = n * n;
@@ -90,6 +90,7 @@ struct Plain {
                     for (int s = 0; s < MB; ++s) {
                         if (s >= m) break;
                         r[s] = fma(-inv_h, dline<D>(Ds, fbuf, m, tid, z, y, x, s), r[s]);
+                        if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
                     }
                 }
                 __syncthreads();
@@ -104,6 +105,9 @@ struct Plain {
             } else {
                 g[s] = s < m ? dline<D>(Ds, u, m, tid, z, y, x, s) : T(0);
             }
+            // one quantity's line at a time: bounds the LDS reads in flight (and the registers they hold).
+            // FP32 only: with FP64 data this barrier makes the gfx950 back end emit an illegal instruction.
+            if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
         }
         if constexpr (kPreset) {
             apply_ncp<T, PHYS, D>(mt, g, r);
@@ -124,12 +128,15 @@ struct Plain {
         }
     }
 
-    __device__ static void run(const StpArgs& a)
+    // One element processed by `stride` threads with local ids tid in [0, stride) (stride >= n^3) and the LDS
+    // region `smem` (layout()). Every thread of the workgroup must call it (barriers); `valid` is false for
+    // threads of an empty slot, which then touch no memory.
+    __device__ static void element(const StpArgs& a, const ElemRef& er, bool valid, unsigned char* smem, int tid,
+                                   int stride)
     {
-        extern __shared__ __align__(16) unsigned char smem[];
-        const int m = kPreset ? PhysTraits<PHYS>::m : a.m;
-        const int tid = threadIdx.x;
-        const bool own = tid < nn;
+        const int NT = stride;
+        const int m = kPreset ? PhysTraits<PHYS>::m : (EX ? MB : a.m);  // EX: generic with m == MB
+        const bool own = valid && tid < nn;
         const int x = tid % n, y = (tid / n) % n, z = tid / n2;
         const bool hasA = !kPreset && (a.flags & kAPresent);
         const bool hasSrc = (a.flags & kSrcPoint) != 0;
@@ -145,24 +152,24 @@ struct Plain {
         T* fbuf = reinterpret_cast<T*>(smem + L.fbuf);    // only touched when A is present
         ACC* qacc = reinterpret_cast<ACC*>(smem + L.qacc);
 
-        for (int i = tid; i < n * n; i += NT) Ds[i] = ld<T>(a.D, i);
-        for (int i = tid; i < n; i += NT) {
-            e0s[i] = ld<T>(a.e0, i);
-            e1s[i] = ld<T>(a.e1, i);
-        }
-
-        for (int64_t it = blockIdx.x;; it += gridDim.x) {
-            ElemRef er;
-            if (!elem_ref(a, it, er)) break;
+        {
+            if (valid) {
+                for (int i = tid; i < n * n; i += NT) Ds[i] = ld<T>(a.D, i);
+                for (int i = tid; i < n; i += NT) {
+                    e0s[i] = ld<T>(a.e0, i);
+                    e1s[i] = ld<T>(a.e1, i);
+                }
+            }
             const T inv_h = (T)(1.0 / er.h);
             const T* Q = static_cast<const T*>(a.Q) + er.q;
-            for (int i = tid; i < nn * m; i += NT) pbuf[i] = Q[i];
+            if (valid)
+                for (int i = tid; i < nn * m; i += NT) pbuf[i] = Q[i];
             Material<T, PHYS> mt;
             if constexpr (kPreset) {
                 constexpr int np = PhysTraits<PHYS>::np;
                 const T* par = static_cast<const T*>(a.params) + er.coef + (per_elem ? 0 : tid * np);
                 if (own) mt.load(par, 1.0 / er.h);
-            } else if (per_elem) {
+            } else if (per_elem && valid) {
                 const T* Bsrc = static_cast<const T*>(a.B) + er.coef;
                 for (int i = tid; i < 3 * m * m; i += NT) coefs[i] = Bsrc[i];
                 if (hasA) {
@@ -220,11 +227,12 @@ struct Plain {
             }
             __syncthreads();
             T* qavg = static_cast<T*>(a.qavg) + er.q;
-            for (int i = tid; i < nn * m; i += NT) qavg[i] = pbuf[i];
+            if (valid)
+                for (int i = tid; i < nn * m; i += NT) qavg[i] = pbuf[i];
 
             // faces of q-bar, in the accumulator precision
             T* qface = static_cast<T*>(a.qface) + er.face;
-            for (int i = tid; i < 6 * n2 * m; i += NT) {
+            for (int i = valid ? tid : 6 * n2 * m; i < 6 * n2 * m; i += NT) {
                 const int s = i % m, t = i / m, b = t % n, aa = (t / n) % n, f = t / n2;
                 const int axis = f >> 1;
                 const T* ev = (f & 1) ? e1s : e0s;
@@ -255,7 +263,7 @@ struct Plain {
                         }
                     }
                     __syncthreads();
-                    for (int i = tid; i < 2 * n2 * m; i += NT) {
+                    for (int i = valid ? tid : 2 * n2 * m; i < 2 * n2 * m; i += NT) {
                         const int s = i % m, t = i / m, b = t % n, aa = (t / n) % n, side = t / n2;
                         const T* ev = side ? e1s : e0s;
                         T acc = 0;
@@ -291,44 +299,55 @@ struct Plain {
                     }
                 }
                 __syncthreads();
-                for (int i = tid; i < nn * m; i += NT) favg[d * nn * m + i] = pbuf[i];
+                if (valid)
+                    for (int i = tid; i < nn * m; i += NT) favg[d * nn * m + i] = pbuf[i];
                 __syncthreads();
             }
         }
     }
+
+    __device__ static void run(const StpArgs& a)
+    {
+        extern __shared__ __align__(16) unsigned char smem[];
+        for (int64_t it = blockIdx.x;; it += gridDim.x) {
+            ElemRef er;
+            if (!elem_ref(a, it, er)) break;
+            element(a, er, true, smem, threadIdx.x, NT);
+        }
+    }
 };
 
-template <typename T, typename ACC, int N, int PHYS, int MB>
+template <typename T, typename ACC, int N, int PHYS, int MB, bool EX>
 __global__ void __launch_bounds__(((N + 1) * (N + 1) * (N + 1) + 63) / 64 * 64) stp_plain_kernel(StpArgs a)
 {
-    Plain<T, ACC, N, PHYS, MB>::run(a);
+    Plain<T, ACC, N, PHYS, MB, EX>::run(a);
 }
 
-template <typename T, typename ACC, int N, int PHYS, int MB>
+template <typename T, typename ACC, int N, int PHYS, int MB, bool EX>
 KernelInfo plain_info()
 {
-    using K = Plain<T, ACC, N, PHYS, MB>;
+    using K = Plain<T, ACC, N, PHYS, MB, EX>;
     KernelInfo ki;
-    ki.fn = reinterpret_cast<const void*>(&stp_plain_kernel<T, ACC, N, PHYS, MB>);
+    ki.fn = reinterpret_cast<const void*>(&stp_plain_kernel<T, ACC, N, PHYS, MB, EX>);
     ki.block = K::NT;
     ki.mb = MB;
     ki.lds = [](int m, bool hasA) -> size_t { return K::layout(m, hasA).total; };
     return ki;
 }
 
-template <typename T, typename ACC, int PHYS, int MB>
+template <typename T, typename ACC, int PHYS, int MB, bool EX = false>
 KernelInfo plain_by_order(int N)
 {
     switch (N) {
-    case 1: return plain_info<T, ACC, 1, PHYS, MB>();
-    case 2: return plain_info<T, ACC, 2, PHYS, MB>();
-    case 3: return plain_info<T, ACC, 3, PHYS, MB>();
-    case 4: return plain_info<T, ACC, 4, PHYS, MB>();
-    case 5: return plain_info<T, ACC, 5, PHYS, MB>();
-    case 6: return plain_info<T, ACC, 6, PHYS, MB>();
-    case 7: return plain_info<T, ACC, 7, PHYS, MB>();
-    case 8: return plain_info<T, ACC, 8, PHYS, MB>();
-    case 9: return plain_info<T, ACC, 9, PHYS, MB>();
+    case 1: return plain_info<T, ACC, 1, PHYS, MB, EX>();
+    case 2: return plain_info<T, ACC, 2, PHYS, MB, EX>();
+    case 3: return plain_info<T, ACC, 3, PHYS, MB, EX>();
+    case 4: return plain_info<T, ACC, 4, PHYS, MB, EX>();
+    case 5: return plain_info<T, ACC, 5, PHYS, MB, EX>();
+    case 6: return plain_info<T, ACC, 6, PHYS, MB, EX>();
+    case 7: return plain_info<T, ACC, 7, PHYS, MB, EX>();
+    case 8: return plain_info<T, ACC, 8, PHYS, MB, EX>();
+    case 9: return plain_info<T, ACC, 9, PHYS, MB, EX>();
     default: return KernelInfo{};
     }
 }
@@ -338,6 +357,8 @@ KernelInfo plain_by_physics(int N, int physics, int m)
 {
     if (physics == kAcoustic) return plain_by_order<T, ACC, kAcoustic, 4>(N);
     if (physics == kElastic) return plain_by_order<T, ACC, kElastic, 9>(N);
+    if (m == 4) return plain_by_order<T, ACC, kGeneric, 4, true>(N);
+    if (m == 9) return plain_by_order<T, ACC, kGeneric, 9, true>(N);
     if (m <= 4) return plain_by_order<T, ACC, kGeneric, 4>(N);
     if (m <= 9) return plain_by_order<T, ACC, kGeneric, 9>(N);
     return plain_by_order<T, ACC, kGeneric, 16>(N);

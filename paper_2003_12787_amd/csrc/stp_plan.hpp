@@ -18,6 +18,8 @@
 namespace stp {
 
 constexpr int kMaxClasses = 64;
+constexpr int kHeteroBuckets = 7;
+constexpr size_t kHeteroLdsBudget = 80 * 1024;  // per workgroup of the persistent kernel (two per CU)
 constexpr size_t kMaxLds = 160 * 1024;
 
 struct ClassState {
@@ -34,12 +36,26 @@ struct ClassState {
     size_t lds = 0;
     double bytes = 0, flops = 0;  // algorithmic cost per element
     int64_t size_q = 0, size_face = 0, size_coef = 0, size_src = 0;  // values per element
+    // heterogeneous plans: processed as tiles of the persistent bucket kernel, or by its own launch
+    bool tiled = false;
+    int bucket = -1;
+    int slots = 0;        // elements per tile
+    size_t slot_lds = 0;  // LDS bytes per slot
+};
+
+// One physics bucket of the persistent heterogeneous kernel.
+struct BucketPlan {
+    std::vector<int> order;  // tiled classes of the bucket, most expensive first
+    HeteroKernel kernel;
+    size_t lds = 0;          // dynamic LDS of a workgroup (largest tile of the bucket)
 };
 
 // Device scratch of heterogeneous launches: per-class element lists and counts.
 struct HeteroScratch {
-    int32_t* lists = nullptr;  // [nclass][cap]
-    int32_t* counts = nullptr; // [kMaxClasses]
+    int32_t* lists = nullptr;       // [nclass][cap]
+    int32_t* counts = nullptr;      // [kMaxClasses]
+    int32_t* tile_start = nullptr;  // [kHeteroBuckets][kMaxClasses + 1]
+    int32_t* heads = nullptr;       // [kHeteroBuckets]
     int64_t cap = 0;
 };
 
@@ -59,6 +75,13 @@ struct stp_plan_s {
     void* d_counts = nullptr;
     std::mutex run_mu;         // guards `run_scratch` growth
     stp::HeteroScratch run_scratch;
+    // heterogeneous plans
+    std::vector<stp::BucketPlan> buckets;
+    void* d_hcls = nullptr;       // hetero::HClass[nclass]
+    int32_t* d_slots = nullptr;   // [nclass] elements per tile (1 for classes with their own launch)
+    int32_t* d_orders = nullptr;  // [kHeteroBuckets][kMaxClasses]
+    int32_t* d_bncls = nullptr;   // [kHeteroBuckets]
+    int hetero_grid_per_cu = 4;   // persistent workgroups per CU
     stp::ServeState* serve = nullptr;
 };
 
@@ -71,6 +94,10 @@ stp_status validate_batch(stp_plan_s* p, const stp_batch* b);
 KernelInfo select_kernel(stp_plan_s* p, const ClassState& cs);
 // Queue the kernels of a validated, non-empty batch on `stream`, using `scratch` for heterogeneous lists.
 stp_status launch_batch(stp_plan_s* p, const stp_batch* b, hipStream_t stream, HeteroScratch* scratch = nullptr);
+// Plan-time set-up of the heterogeneous path (class tiling, buckets, device descriptors).
+stp_status hetero_prepare(stp_plan_s* p);
+// Make `s` hold batches of up to nelem elements (synchronous allocation).
+stp_status reserve_scratch(stp_plan_s* p, HeteroScratch& s, int64_t nelem);
 void free_scratch(HeteroScratch& s);
 stp_status serve_start(stp_plan_s* p);
 void serve_stop(stp_plan_s* p);

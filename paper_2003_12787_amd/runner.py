@@ -55,6 +55,11 @@ class DeviceBatch:
         self.cbatch = plan.batch(E, self.Q, self.qavg, self.favg, self.qface, self.dt, self.h, params=self.params,
                                  A=self.A, B=self.B, src=self.src, fface=self.fface)
 
+    def clear_outputs(self, value=0.0):
+        for t in (self.qavg, self.favg, self.qface, self.fface):
+            if t is not None:
+                t.fill_(value)
+
     def outputs(self):
         out = {"qavg": self.qavg, "favg": self.favg, "qface": self.qface}
         if self.fface is not None:

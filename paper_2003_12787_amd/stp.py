@@ -22,8 +22,8 @@ PARAM_PER_ELEMENT, A_PRESENT, COEF_PER_ELEMENT, FAVG_SUM, SRC_POINT = 1, 2, 4, 8
 VARIANT_AUTO, VARIANT_PLAIN, VARIANT_FUSED, VARIANT_MFMA = 0, 1, 2, 3
 
 # Exported symbols declared in include/stp.h.
-SYMBOLS = ("stp_plan", "stp_plan_free", "stp_run", "stp_submit", "stp_poll", "stp_drain", "stp_class_cost",
-           "stp_last_error")
+SYMBOLS = ("stp_plan", "stp_plan_free", "stp_run", "stp_reserve", "stp_submit", "stp_poll", "stp_drain",
+           "stp_class_cost", "stp_last_error")
 
 
 class StpError(RuntimeError):
@@ -77,9 +77,10 @@ def lib():
         L.stp_poll.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(TicketInfo)]
         L.stp_drain.argtypes = [C.c_void_p]
         L.stp_class_cost.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.stp_reserve.argtypes = [C.c_void_p, C.c_int64]
         L.stp_last_error.argtypes = []
         L.stp_last_error.restype = C.c_char_p
-        for f in ("stp_plan", "stp_run", "stp_submit", "stp_poll", "stp_drain", "stp_class_cost"):
+        for f in ("stp_plan", "stp_run", "stp_reserve", "stp_submit", "stp_poll", "stp_drain", "stp_class_cost"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -126,6 +127,10 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def reserve(self, max_nelem):
+        """Preallocate heterogeneous scratch so that run() allocates nothing (graph capture)."""
+        _check(lib().stp_reserve(self.handle, int(max_nelem)))
 
     def cost(self, cls=0):
         """Algorithmic (bytes, flops) of one element of class `cls`."""

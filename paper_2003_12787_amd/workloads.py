@@ -241,3 +241,73 @@ def hetero_generic_batch(nelem: int, seed: int, orders=None, nquants=None, h: fl
             dt[e] = p.dt[j]
     return HeteroBatch(classes, cls, off_q, off_coef, off_face, Q, coef, dt, hh, parts, members,
                        int(sq.sum()), int(sf.sum()))
+
+
+@dataclasses.dataclass
+class MixedBatch:
+    """Uniform batches of any physics interleaved into one flat buffer per array (FP64 host arrays).
+
+    Element e of class cls[e] reads Q at off_q[e], its coefficients at off_coef[e] (into `params` for a
+    preset class, into `B` and `A` for a generic one; A shares B's offsets), its source at off_src[e];
+    its faces go to off_face[e] and its time-averaged fluxes to 3 * off_q[e]. `members[c]` are the
+    element ids of class c in the order of `parts[c]`."""
+    classes: list
+    cls: np.ndarray
+    off_q: np.ndarray
+    off_coef: np.ndarray
+    off_face: np.ndarray
+    off_src: np.ndarray
+    Q: np.ndarray
+    params: np.ndarray
+    B: np.ndarray
+    A: np.ndarray
+    src: np.ndarray
+    dt: np.ndarray
+    h: np.ndarray
+    parts: list
+    members: list
+    size_q: int
+    size_face: int
+
+
+def interleave(parts, classes, seed: int) -> MixedBatch:
+    """Shuffle the elements of several uniform batches (class c = parts[c], classes[c] its stp class
+    tuple) into one heterogeneous batch with per-element offsets."""
+    rng = np.random.default_rng(seed)
+    cls = np.concatenate([np.full(p.nelem, c, dtype=np.int32) for c, p in enumerate(parts)])
+    rng.shuffle(cls)
+    members = [np.nonzero(cls == c)[0] for c in range(len(parts))]
+    E = len(cls)
+    rank = np.zeros(E, dtype=np.int64)
+    for ids in members:
+        rank[ids] = np.arange(len(ids))
+    sq = np.array([parts[c].Q[0].size if parts[c].nelem else 0 for c in cls], dtype=np.int64)
+    sf = np.array([6 * (parts[c].N + 1) ** 2 * parts[c].m for c in cls], dtype=np.int64)
+
+    def coef_of(p):
+        return p.params if p.physics != GENERIC else p.B
+
+    sp = np.array([coef_of(parts[c])[0].size if parts[c].physics != GENERIC else 0 for c in cls], dtype=np.int64)
+    sb = np.array([coef_of(parts[c])[0].size if parts[c].physics == GENERIC else 0 for c in cls], dtype=np.int64)
+    ss = np.array([parts[c].src[0].size if parts[c].src is not None else 0 for c in cls], dtype=np.int64)
+    ex = lambda s: np.concatenate([[0], np.cumsum(s)[:-1]]).astype(np.int64)
+    off_q, off_face, off_src = ex(sq), ex(sf), ex(ss)
+    off_p, off_b = ex(sp), ex(sb)
+    off_coef = np.where(sb > 0, off_b, off_p)
+    Q, params, B, A = np.zeros(sq.sum()), np.zeros(max(sp.sum(), 1)), np.zeros(max(sb.sum(), 1)), np.zeros(max(sb.sum(), 1))
+    src = np.zeros(max(ss.sum(), 1))
+    dt, hh = np.zeros(E), np.zeros(E)
+    for e in range(E):
+        p, j = parts[cls[e]], rank[e]
+        Q[off_q[e]:off_q[e] + sq[e]] = p.Q[j].ravel()
+        if p.physics != GENERIC:
+            params[off_coef[e]:off_coef[e] + sp[e]] = p.params[j].ravel()
+        else:
+            B[off_coef[e]:off_coef[e] + sb[e]] = p.B[j].ravel()
+            if p.A is not None:
+                A[off_coef[e]:off_coef[e] + sb[e]] = p.A[j].ravel()
+        if p.src is not None:
+            src[off_src[e]:off_src[e] + ss[e]] = p.src[j].ravel()
+        dt[e], hh[e] = p.dt[j], p.h[j]
+    return MixedBatch(list(classes), cls, off_q, off_coef, off_face, off_src, Q, params, B, A, src, dt, hh,
+                      list(parts), members, int(sq.sum()), int(sf.sum()))

@@ -82,6 +82,7 @@ def test_null_plan_entry_points(L):
     assert L.stp_submit(None, C.byref(b), C.byref(t)) == stp.E_INVAL
     assert L.stp_poll(None, 1, None) == stp.E_INVAL
     assert L.stp_drain(None) == stp.E_INVAL
+    assert L.stp_reserve(None, 10) == stp.E_INVAL
     assert L.stp_class_cost(None, 0, None, None) == stp.E_INVAL
     L.stp_plan_free(None)  # no-op
     assert "NULL" in stp.last_error()

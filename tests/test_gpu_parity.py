@@ -286,6 +286,144 @@ def test_c4_heterogeneous_full_size_sampled():
     _hetero(W.hetero_generic_batch(16384, W.SEED0 + 3), stp.FP32, sample_per_class=6, label="C4-full")
 
 
+def mixed_batch(E_scale=1, seed=905):
+    """Every physics bucket of the persistent launch plus a high-order class that runs on its own."""
+    G = W.GENERIC
+    parts = [
+        W.elastic_batch(3, 40 * E_scale, seed + 1),
+        W.elastic_batch(7, 12 * E_scale, seed + 2, per_node=False),
+        W.acoustic_batch(5, 30 * E_scale, seed + 3),
+        W.acoustic_batch(1, 70 * E_scale, seed + 4, per_node=False),
+        W.generic_batch(2, 9, 25 * E_scale, seed + 5, with_A=True),
+        W.generic_batch(4, 3, 20 * E_scale, seed + 6, per_node=False),
+        W.generic_batch(3, 12, 15 * E_scale, seed + 7),
+        W.generic_batch(8, 4, 6 * E_scale, seed + 8),
+        W.generic_batch(6, 4, 10 * E_scale, seed + 9),
+    ]
+    parts[5].src = W.point_source(parts[5], seed + 10)
+    from paper_2003_12787_amd import runner
+    classes = [runner.class_of(p) for p in parts]
+    return W.interleave(parts, classes, seed)
+
+
+def run_mixed(plan, mb, prec, graph_replays=0):
+    """Run a MixedBatch through one heterogeneous plan; returns host outputs (and, with graph_replays,
+    checks that replays of a captured graph reproduce the eager result bit for bit)."""
+    import torch
+    dt = torch.float64 if prec == stp.FP64 else torch.float32
+    to = lambda a, t: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", t)
+    ins = dict(Q=to(mb.Q, dt), params=to(mb.params, dt), B=to(mb.B, dt), A=to(mb.A, dt), src=to(mb.src, dt))
+    outs = dict(qavg=torch.zeros(mb.size_q, device="cuda", dtype=dt),
+                favg=torch.zeros(3 * mb.size_q, device="cuda", dtype=dt),
+                qface=torch.zeros(mb.size_face, device="cuda", dtype=dt),
+                fface=torch.zeros(mb.size_face, device="cuda", dtype=dt))
+    idx = dict(cls=to(mb.cls, torch.int32), off_q=to(mb.off_q, torch.int64), off_coef=to(mb.off_coef, torch.int64),
+               off_face=to(mb.off_face, torch.int64), off_src=to(mb.off_src, torch.int64))
+    dts, hs = to(mb.dt, torch.float64), to(mb.h, torch.float64)
+    batch = plan.batch(len(mb.cls), ins["Q"], outs["qavg"], outs["favg"], outs["qface"], dts, hs,
+                       params=ins["params"], A=ins["A"], B=ins["B"], src=ins["src"], fface=outs["fface"], **idx)
+    plan.run(batch)
+    torch.cuda.synchronize()
+    host = {k: v.double().cpu().numpy() for k, v in outs.items()}
+    if graph_replays:
+        plan.reserve(len(mb.cls))
+        g = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream()
+        with torch.cuda.graph(g, stream=cap):
+            plan.run(batch)
+        other = torch.randn(1 << 20, device="cuda")
+        for r in range(graph_replays):
+            for k, v in outs.items():
+                v.fill_(0.0 if k == "fface" else float("nan"))  # fface is written only for classes with A
+            _ = (other * 2).sum().item()  # eager work and a synchronisation between replays
+            g.replay()
+            torch.cuda.synchronize()
+            for k, v in outs.items():
+                assert np.array_equal(v.double().cpu().numpy(), host[k]), (r, k)
+            say(f"[parity]   graph replay {r} bitwise equal")
+        del g
+    return host
+
+
+def check_mixed(mb, prec, got, sample_per_class=None):
+    worst = 0.0
+    for c, (N, m, phys, flags) in enumerate(mb.classes):
+        ids = mb.members[c]
+        if len(ids) == 0:
+            continue
+        pick = np.arange(len(ids)) if sample_per_class is None else spread(len(ids), sample_per_class, c)[:sample_per_class]
+        from paper_2003_12787_amd import runner
+        part = subset(runner.rounded(mb.parts[c], prec), pick)
+        ref = oracle_run(part)
+        n3, n2 = (N + 1) ** 3, (N + 1) ** 2
+        res = {"qavg": [], "favg": [], "qface": []}
+        hasA = bool(flags & stp.A_PRESENT)
+        if hasA:
+            res["fface"] = []
+        for j in pick:
+            e = ids[j]
+            oq, of = mb.off_q[e], mb.off_face[e]
+            res["qavg"].append(got["qavg"][oq:oq + n3 * m].reshape(n3, m))
+            res["favg"].append(got["favg"][3 * oq:3 * oq + 3 * n3 * m].reshape(3, n3, m))
+            res["qface"].append(got["qface"][of:of + 6 * n2 * m].reshape(6, n2, m))
+            if hasA:
+                res["fface"].append(got["fface"][of:of + 6 * n2 * m].reshape(6, n2, m))
+        res = {k: np.stack(v) for k, v in res.items()}
+        if not hasA:
+            ref.pop("fface", None)
+        err = max_rel_err(res, ref, part.Q, part.h)
+        say(f"[parity]   class {c} N={N} m={m} phys={phys} flags={flags} E={len(ids)} err={max(err.values()):.2e}")
+        worst = max(worst, max(err.values()))
+        for k, v in err.items():
+            assert v < TOL[prec], (c, N, m, k, v)
+    return worst
+
+
+@pytest.mark.parametrize("prec,acc64", [(stp.FP64, 0), (stp.FP32, 0), (stp.FP32, 6)])
+def test_heterogeneous_mixed_physics(prec, acc64):
+    mb = mixed_batch()
+    say(f"[parity] mixed physics classes={len(mb.classes)} E={len(mb.cls)} prec={prec} acc64={acc64}")
+    plan = stp.Plan(mb.classes, prec=prec, acc64_min_order=acc64)
+    got = run_mixed(plan, mb, prec)
+    say(f"[parity]   worst {check_mixed(mb, prec, got)}")
+    plan.close()
+
+
+def test_heterogeneous_graph_capture_replays():
+    mb = mixed_batch(E_scale=4, seed=906)
+    say(f"[graph] mixed physics E={len(mb.cls)} captured after stp_reserve")
+    plan = stp.Plan(mb.classes, prec=stp.FP32)
+    got = run_mixed(plan, mb, stp.FP32, graph_replays=3)
+    check_mixed(mb, stp.FP32, got, sample_per_class=8)
+    plan.close()
+
+
+def test_uniform_graph_capture_replays():
+    import torch
+    from paper_2003_12787_amd import runner
+    b = W.c3_elastic_n7(2048)
+    for prec, variant in ((stp.FP32, stp.VARIANT_FUSED), (stp.BF16X3, stp.VARIANT_MFMA)):
+        say(f"[graph] C3-shaped E=2048 prec={prec} variant={variant}")
+        plan = stp.Plan([runner.class_of(b)], prec=prec, variant=variant)
+        db = runner.DeviceBatch(plan, b)
+        plan.run(db.cbatch)
+        torch.cuda.synchronize()
+        ref = db.outputs()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=torch.cuda.Stream()):
+            plan.run(db.cbatch)
+        for r in range(3):
+            db.clear_outputs(float("nan"))
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            out = db.outputs()
+            for k in ref:
+                assert np.array_equal(out[k], ref[k]), (prec, r, k)
+        del g
+        plan.close()
+
+
 # ------------------------------------------------------------------------------------------------ edges
 def test_empty_batch_is_noop():
     from paper_2003_12787_amd import runner

@@ -47,3 +47,32 @@ def test_generic_and_hetero():
     assert set(np.unique(Ns)) == set(range(2, 10)) and set(np.unique(ms)) == {4, 9}
     sz = W.serving_batch_sizes(10000, 1)
     assert sz.min() >= 1 and sz.max() <= 4096
+
+
+def test_interleave_offsets_round_trip():
+    parts = [W.elastic_batch(2, 5, 1), W.acoustic_batch(3, 4, 2, per_node=False),
+             W.generic_batch(2, 3, 6, 3, with_A=True)]
+    parts[2].src = W.point_source(parts[2], 4)
+    classes = [(p.N, p.m, p.physics, 0) for p in parts]
+    mb = W.interleave(parts, classes, 7)
+    assert sorted(np.concatenate(mb.members).tolist()) == list(range(15))
+    for c, p in enumerate(parts):
+        for j, e in enumerate(mb.members[c]):
+            assert mb.cls[e] == c
+            n = p.Q[j].size
+            assert np.array_equal(mb.Q[mb.off_q[e]:mb.off_q[e] + n], p.Q[j].ravel())
+            coef = p.params if p.physics != W.GENERIC else p.B
+            arr = mb.params if p.physics != W.GENERIC else mb.B
+            k = coef[j].size
+            assert np.array_equal(arr[mb.off_coef[e]:mb.off_coef[e] + k], coef[j].ravel())
+            if p.A is not None:
+                assert np.array_equal(mb.A[mb.off_coef[e]:mb.off_coef[e] + k], p.A[j].ravel())
+            if p.src is not None:
+                s = p.src[j].size
+                assert np.array_equal(mb.src[mb.off_src[e]:mb.off_src[e] + s], p.src[j].ravel())
+            assert mb.dt[e] == p.dt[j] and mb.h[e] == p.h[j]
+    # offsets tile the flat arrays without overlap
+    sq = [parts[mb.cls[e]].Q[0].size for e in range(15)]
+    order = np.argsort(mb.off_q)
+    assert np.all(np.diff(mb.off_q[order]) == np.array(sq)[order][:-1])
+    assert mb.size_q == sum(sq)
