@@ -43,6 +43,10 @@ def parse():
                     help="size of the device-to-device copy timed as the measured HBM reference (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--variants", default="fp64_plain,fp32_plain,fp32_fused,bf16x3_mfma")
+    ap.add_argument("--no-hetero", action="store_true", help="skip the heterogeneous 16384-element batch")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop latency measurement")
+    ap.add_argument("--serve-batches", type=int, default=10000, help="measured batches per arrival rate")
+    ap.add_argument("--serve-mesh", type=int, default=131072, help="elements per resident serving mesh")
     return ap.parse_args()
 
 
@@ -110,6 +114,163 @@ def copy_bandwidth(gib, torch):
     return {"bytes_read": n * 4, "bytes_written": n * 4, "ms": ms, "gbs": gbs}
 
 
+def time_launches(fn, steps, warmup, stream, torch):
+    """Per-call HIP-event times (ms) of fn(stream) on one stream."""
+    for _ in range(warmup):
+        fn(stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record(stream)
+        fn(stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    return np.array([a.elapsed_time(b) for a, b in ev])
+
+
+def bench_hetero(args, torch, stp, W):
+    """Mixed orders and quantity counts in one batch: 16384 generic elements, N ~ U{2..9}, m ~ U{4, 9},
+    dense per-node B_d, FP32. Times the heterogeneous stp_run (eager and replayed from a captured HIP graph)
+    against the same elements run as one uniform launch per class."""
+    log("[bench] heterogeneous: generating 16384 generic elements on the device")
+    d = W.c4_device(16384)
+    E = d["nelem"]
+    plan = stp.Plan(d["classes"], prec=stp.FP32)
+    plan.reserve(E)
+    qavg = torch.empty(d["size_q"], device="cuda")
+    favg = torch.empty(3 * d["size_q"], device="cuda")
+    qface = torch.empty(d["size_face"], device="cuda")
+    batch = plan.batch(E, d["Q"], qavg, favg, qface, d["dt"], d["h"], B=d["B"], cls=d["cls"], off_q=d["off_q"],
+                       off_coef=d["off_coef"], off_face=d["off_face"])
+    stream = torch.cuda.Stream()
+    eager = time_launches(lambda st: plan.run(batch, st), args.steps, args.warmup, stream, torch)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        plan.run(batch)
+    graph = time_launches(lambda st: g.replay(), args.steps, 2, torch.cuda.current_stream(), torch)
+    bytes_tot = sum(plan.cost(c)[0] * int(k) for c, k in enumerate(d["counts"]))
+    flops_tot = sum(plan.cost(c)[1] * int(k) for c, k in enumerate(d["counts"]))
+    # the same elements, one uniform plan and launch per class over its contiguous storage
+    per_class = []
+    for c, (first, k) in enumerate(d["class_ranges"]):
+        if k == 0:
+            continue
+        up = stp.Plan([d["classes"][c]], prec=stp.FP32)
+        sq, sf, sc = int(d["sizes_q"][c]), int(d["sizes_face"][c]), int(d["sizes_coef"][c])
+        oq, of, oc = int(d["storage_q"][first]), int(d["storage_face"][first]), int(d["storage_coef"][first])
+        ids = torch.from_numpy(d["order"][first:first + k]).cuda()
+        dts, hs = d["dt"][ids].contiguous(), d["h"][ids].contiguous()
+        ub = up.batch(k, d["Q"][oq:oq + k * sq], qavg[oq:oq + k * sq], favg[3 * oq:3 * (oq + k * sq)],
+                      qface[of:of + k * sf], dts, hs, B=d["B"][oc:oc + k * sc])
+        t = time_launches(lambda st: up.run(ub, st), max(3, args.steps // 2), 2, stream, torch)
+        per_class.append(float(np.median(t)))
+        up.close()
+    del g
+    plan.close()
+    ms = float(np.median(eager))
+    res = {"workload": f"{E} generic elements, N ~ U{{2..9}}, m ~ U{{4,9}}, dense per-node B_d, FP32, "
+                       f"{len(d['classes'])} classes",
+           "ms_eager": ms, "ms_graph": float(np.median(graph)), "elements_per_s": E / (ms * 1e-3),
+           "algorithmic_bytes": bytes_tot, "hbm_gbs_algorithmic": bytes_tot / (ms * 1e-3) / 1e9,
+           "hbm_frac": bytes_tot / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "gflops": flops_tot / (ms * 1e-3) / 1e9,
+           "ms_one_launch_per_class_sum": float(sum(per_class))}
+    log(f"[bench] heterogeneous: eager {ms:.3f} ms, graph {res['ms_graph']:.3f} ms, "
+        f"{res['hbm_gbs_algorithmic']:.0f} GB/s algorithmic; per-class launches sum {sum(per_class):.3f} ms")
+    del d, qavg, favg, qface
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_serving(args, torch, stp, W):
+    """Serving loop: batches of log-uniform size 1..4096 (contiguous runs of element ids) from two resident
+    p-adaptive meshes (acoustic m=4 and elastic m=9, N ~ U{2..9}), FP32 with FP64 accumulation at N >= 8,
+    admission budget 2 GiB. Measures the saturated throughput (batches submitted back to back), then
+    Poisson arrivals at 50 % and 80 % of it; latency = completion - submission (library timestamps)."""
+    import ctypes as C
+    E = args.serve_mesh
+    log(f"[bench] serving: generating two resident meshes of {E} elements")
+    meshes = [W.serving_mesh(W.ACOUSTIC, E, W.SEED0 + 50, 0), W.serving_mesh(W.ELASTIC, E, W.SEED0 + 51, 8)]
+    classes = [(N, 4, stp.ACOUSTIC, 0) for N in range(2, 10)] + [(N, 9, stp.ELASTIC, 0) for N in range(2, 10)]
+    plan = stp.Plan(classes, prec=stp.FP32, acc64_min_order=8, serve_mem_budget=2 << 30)
+    for mh in meshes:
+        mh["qavg"] = torch.empty(mh["size_q"], device="cuda")
+        mh["favg"] = torch.empty(3 * mh["size_q"], device="cuda")
+        mh["qface"] = torch.empty(mh["size_face"], device="cuda")
+    L = stp.lib()
+    rng = np.random.default_rng(W.SEED0 + 52)
+
+    def make_batches(n, seed):
+        sizes = W.serving_batch_sizes(n, seed)
+        which = rng.integers(0, 2, n)
+        out = []
+        for k, w in zip(sizes, which):
+            mh = meshes[w]
+            a = int(rng.integers(0, E - k + 1))
+            b = stp.Batch()
+            b.nelem = int(k)
+            b.cls = mh["cls"].data_ptr() + 4 * a
+            for f in ("off_q", "off_coef", "off_face", "dt", "h"):
+                setattr(b, f, mh[f].data_ptr() + 8 * a)
+            b.dt_h_scalar = 0
+            b.Q, b.params = mh["Q"].data_ptr(), mh["params"].data_ptr()
+            b.qavg, b.favg, b.qface = mh["qavg"].data_ptr(), mh["favg"].data_ptr(), mh["qface"].data_ptr()
+            out.append(b)
+        return out, int(sizes.sum())
+
+    def run(batches, gaps=None):
+        """Submit (back to back, or at the scheduled arrival times), drain, return per-batch latencies."""
+        tickets = np.zeros(len(batches), dtype=np.uint64)
+        t = C.c_uint64()
+        t0 = time.perf_counter()
+        due = t0
+        for i, b in enumerate(batches):
+            if gaps is not None:
+                due += gaps[i]
+                while time.perf_counter() < due:
+                    pass
+            st = L.stp_submit(plan.handle, C.byref(b), C.byref(t))
+            if st != stp.OK:
+                raise stp.StpError(st, stp.last_error())
+            tickets[i] = t.value
+        plan.drain()
+        info = stp.TicketInfo()
+        lat, first, last = np.zeros(len(batches)), None, 0.0
+        for i, tk in enumerate(tickets):
+            st = L.stp_poll(plan.handle, C.c_uint64(int(tk)), C.byref(info))
+            assert st == stp.OK, (st, stp.last_error())
+            lat[i] = info.t_done - info.t_submit
+            first = info.t_submit if first is None else min(first, info.t_submit)
+            last = max(last, info.t_done)
+        return lat, last - first
+
+    warm, _ = make_batches(500, W.SEED0 + 53)
+    run(warm)
+    sat_b, sat_el = make_batches(max(2000, args.serve_batches // 3), W.SEED0 + 54)
+    _, span = run(sat_b)
+    sat_rate = len(sat_b) / span
+    res = {"workload": f"two resident meshes of {E} elements (acoustic m=4, elastic m=9), N ~ U{{2..9}}, "
+                       "batches of log-uniform size 1..4096, FP32 with FP64 accumulation at N >= 8, "
+                       "2 GiB admission budget",
+           "saturated": {"batches_per_s": sat_rate, "elements_per_s": sat_el / span,
+                         "mean_batch_elements": sat_el / len(sat_b)}}
+    log(f"[bench] serving saturated: {sat_rate:.0f} batches/s, {sat_el / span:.3g} el/s")
+    for frac in (0.5, 0.8):
+        bs, n_el = make_batches(args.serve_batches, W.SEED0 + 55 + int(frac * 10))
+        gaps = rng.exponential(1.0 / (frac * sat_rate), len(bs))
+        lat, span = run(bs, gaps)
+        key = f"load_{int(frac * 100)}pct"
+        res[key] = {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                    "mean_ms": float(lat.mean() * 1e3), "batches": len(bs),
+                    "offered_batches_per_s": frac * sat_rate, "achieved_batches_per_s": len(bs) / span,
+                    "elements_per_s": n_el / span}
+        log(f"[bench] serving {key}: p50 {res[key]['p50_ms']:.3f} ms, p99 {res[key]['p99_ms']:.3f} ms")
+    plan.close()
+    del meshes
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -172,6 +333,9 @@ def main():
     if args.copy_gib > 0:
         copy = copy_bandwidth(args.copy_gib, torch)
 
+    hetero = None if args.no_hetero else bench_hetero(args, torch, stp, W)
+    serving = None if args.no_serve else bench_serving(args, torch, stp, W)
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -212,6 +376,10 @@ def main():
         "cpu_baseline": cpu,
         "variants": results,
         "copy_reference": copy,
+        "heterogeneous": hetero,
+        "serving": serving,
+        "latency_p50_ms": serving["load_80pct"]["p50_ms"] if serving else None,
+        "latency_p99_ms": serving["load_80pct"]["p99_ms"] if serving else None,
         "speedup_vs_fp64_plain": (h["elements_per_s"] / results["fp64_plain"]["elements_per_s"]
                                   if "fp64_plain" in results else None),
     }

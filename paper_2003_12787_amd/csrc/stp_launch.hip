@@ -195,7 +195,8 @@ stp_status launch_batch(stp_plan_s* p, const stp_batch* b, hipStream_t stream, H
         h.head = s->heads + bk;
         h.ncls = (int)bp.order.size();
         void* args[] = {&h};
-        const int grid = p->num_cus * p->hetero_grid_per_cu;
+        // never more workgroups than elements (a tile holds at least one)
+        const int grid = (int)std::min<int64_t>((int64_t)p->num_cus * p->hetero_grid_per_cu, b->nelem);
         e = hipLaunchKernel(bp.kernel.fn, dim3(grid), dim3(bp.kernel.threads), args, bp.lds, stream);
         if (e != hipSuccess) return hip_fail(e, "hipLaunchKernel(heterogeneous)");
     }

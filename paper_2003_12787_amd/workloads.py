@@ -311,3 +311,93 @@ def interleave(parts, classes, seed: int) -> MixedBatch:
         dt[e], hh[e] = p.dt[j], p.h[j]
     return MixedBatch(list(classes), cls, off_q, off_coef, off_face, off_src, Q, params, B, A, src, dt, hh,
                       list(parts), members, int(sq.sum()), int(sf.sum()))
+
+
+# ------------------------------------------------------------------------------------------------------------
+# Device-side generators for the full-size heterogeneous and serving workloads (the host generators above
+# build these sizes too slowly). Same distributions as the host recipes; values are drawn with a seeded
+# torch generator on the device, so they differ from the host generators' values.
+
+def _exclusive(sizes: np.ndarray) -> np.ndarray:
+    return np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+
+
+def c4_device(nelem: int = 16384, seed: int = SEED0 + 3, device="cuda", h: float = 1.0):
+    """The heterogeneous generic workload on the device, FP32: N_e ~ U{2..9}, m_e ~ U{4, 9}, per-node dense
+    B_d ~ N(0, 1/m), Q ~ N(0, 1), dt_e from c_e = max over nodes and directions of ||B_d||_F (FP64).
+
+    Element ids are in random class order; storage is class-contiguous (offsets map ids to storage), so each
+    class's elements also form a uniform batch (`class_ranges`). Returns a dict of device tensors and
+    host metadata (classes, counts, class_ranges)."""
+    import torch
+    Ns, ms = c4_classes(nelem, seed)
+    keys = sorted(set(zip(Ns.tolist(), ms.tolist())))
+    classes = [(N, m, GENERIC, 0) for N, m in keys]
+    index = {k: i for i, k in enumerate(keys)}
+    cls = np.array([index[(int(a), int(b))] for a, b in zip(Ns, ms)], dtype=np.int32)
+    order = np.argsort(cls, kind="stable")            # storage slot -> element id
+    counts = np.bincount(cls, minlength=len(keys))
+    n3 = np.array([(N + 1) ** 3 for N, _ in keys])
+    mm = np.array([m for _, m in keys])
+    sq_c, sf_c, sc_c = n3 * mm, 6 * np.array([(N + 1) ** 2 for N, _ in keys]) * mm, 3 * n3 * mm * mm
+    sq, sf, sc = sq_c[cls[order]], sf_c[cls[order]], sc_c[cls[order]]
+    oq_s, of_s, oc_s = _exclusive(sq), _exclusive(sf), _exclusive(sc)
+    off_q, off_face, off_coef = (np.empty(nelem, np.int64) for _ in range(3))
+    off_q[order], off_face[order], off_coef[order] = oq_s, of_s, oc_s
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    Q = torch.randn(int(sq.sum()), generator=g, device=device, dtype=torch.float32)
+    B = torch.randn(int(sc.sum()), generator=g, device=device, dtype=torch.float32)
+    dt = np.empty(nelem)
+    first = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    ranges = []
+    for c, (N, m) in enumerate(keys):
+        k = int(counts[c])
+        ranges.append((int(first[c]), k))
+        if k == 0:
+            continue
+        s0 = int(oc_s[first[c]])
+        blk = B[s0:s0 + k * int(sc_c[c])].view(k, 3 * int(n3[c]), m, m)
+        blk.mul_(1.0 / math.sqrt(m))
+        cmax = torch.linalg.matrix_norm(blk.double()).amax(dim=1).cpu().numpy()
+        dt[order[first[c]:first[c] + k]] = [cfl_dt(N, h, ci) for ci in cmax]
+    to = lambda a, t: torch.from_numpy(np.ascontiguousarray(a)).to(device, t)
+    return dict(classes=classes, counts=counts, class_ranges=ranges, order=order, nelem=nelem,
+                cls=to(cls, torch.int32), off_q=to(off_q, torch.int64), off_coef=to(off_coef, torch.int64),
+                off_face=to(off_face, torch.int64), Q=Q, B=B, dt=to(dt, torch.float64),
+                h=torch.full((nelem,), h, device=device, dtype=torch.float64),
+                size_q=int(sq.sum()), size_face=int(sf.sum()), size_coef=int(sc.sum()),
+                storage_q=oq_s, storage_face=of_s, storage_coef=oc_s, sizes_q=sq_c, sizes_face=sf_c, sizes_coef=sc_c)
+
+
+# Sup of the material ranges: the fastest wave speed any element can have (serving dt rule).
+C_MAX = {ACOUSTIC: math.sqrt(2.0 / 2.0), ELASTIC: math.sqrt((4.0 + 2 * 3.0) / 2.0)}
+
+
+def serving_mesh(physics: int, nelem: int, seed: int, class_base: int, device="cuda", h: float = 1.0):
+    """A resident p-adaptive mesh for the serving workload: N_e ~ U{2..9} per element, per-node material
+    (acoustic rho ~ U[2,3], K ~ U[1,2]; elastic as elastic_material), Q ~ N(0, 1), FP32 on the device,
+    element-contiguous storage. Class id of element e = class_base + N_e - 2. dt_e = 0.4 h / ((2N_e+1) c_max)
+    with c_max the fastest wave speed the material ranges allow."""
+    import torch
+    rng = np.random.default_rng(seed)
+    m, npar = NQUANT[physics], NPARAM[physics]
+    Ns = rng.integers(2, 10, nelem)
+    n3 = (Ns + 1) ** 3
+    sq, sf, sp = n3 * m, 6 * (Ns + 1) ** 2 * m, n3 * npar
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    Q = torch.randn(int(sq.sum()), generator=g, device=device, dtype=torch.float32)
+    u = torch.rand(int(sp.sum()) // npar, npar, generator=g, device=device, dtype=torch.float32)
+    if physics == ACOUSTIC:
+        lo, hi = torch.tensor([2.0, 1.0], device=device), torch.tensor([3.0, 2.0], device=device)
+    else:
+        lo, hi = torch.tensor([2.0, 1.0, 1.0], device=device), torch.tensor([3.0, 4.0, 3.0], device=device)
+    params = (lo + (hi - lo) * u).reshape(-1)
+    dt = np.array([cfl_dt(int(N), h, C_MAX[physics]) for N in Ns])
+    to = lambda a, t: torch.from_numpy(np.ascontiguousarray(a)).to(device, t)
+    return dict(physics=physics, nelem=nelem, N=Ns, cls=to(class_base + Ns - 2, torch.int32),
+                off_q=to(_exclusive(sq), torch.int64), off_coef=to(_exclusive(sp), torch.int64),
+                off_face=to(_exclusive(sf), torch.int64), Q=Q, params=params, dt=to(dt, torch.float64),
+                h=torch.full((nelem,), h, device=device, dtype=torch.float64),
+                size_q=int(sq.sum()), size_face=int(sf.sum()))
