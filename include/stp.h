@@ -27,7 +27,8 @@
  *                                                     other axes, slower first: (z,y), (z,x), (y,x)
  *   params (presets)  [e][z][y][x][p] or [e][p] with STP_PARAM_PER_ELEMENT;
  *                     acoustic p = (rho, K), elastic p = (rho, lambda, mu)
- *   A, B (generic)    [e][d][z][y][x][row s][col r] or [e][d][s][r] with STP_COEF_PER_ELEMENT
+ *   A, B (generic)    [e][d][row s][col r][z][y][x] (node fastest, so that the threads of a workgroup, one
+ *                     per node, read consecutive words), or [e][d][s][r] with STP_COEF_PER_ELEMENT
  *   src (point src)   [e][n^3 + m + N]: nodal projection P[node], amplitude a[s], time derivatives
  *                     sigma^(o)(t_n), o = 0..N-1; S_o[node][s] = P[node] a[s] sigma^(o)
  *   dt, h             [e] doubles (device), or host scalars when dt_h_scalar = 1

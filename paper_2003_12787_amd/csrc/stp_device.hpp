@@ -51,6 +51,15 @@ struct ElemRef {
     double dt, h;
 };
 
+// A zero the compiler cannot see through. Addresses offset by it count as loop-variant, so loads and address
+// arithmetic inside a loop stay there instead of being hoisted out and kept live across all iterations.
+__device__ inline int opaque_zero()
+{
+    int z = 0;
+    asm volatile("" : "+v"(z));
+    return z;
+}
+
 __device__ inline bool elem_ref(const StpArgs& a, int64_t i, ElemRef& r)
 {
     int64_t cnt = a.count ? (int64_t)*a.count : a.nelem;

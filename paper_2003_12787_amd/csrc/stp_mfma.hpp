@@ -49,15 +49,9 @@ __device__ inline bf16x4 as_bf16x4(unsigned w0, unsigned w1)
     return __builtin_bit_cast(bf16x4, t);
 }
 
-// A zero the compiler cannot see through: LDS base addresses derived from it are recomputed where they are
-// used instead of being hoisted out of the Taylor loop (each quantity slot needs its own base register for
-// the paired LDS accesses, and keeping them all live would halve the occupancy).
-__device__ inline int opaque_zero()
-{
-    int z = 0;
-    asm volatile("" : "+v"(z));
-    return z;
-}
+// opaque_zero() (stp_device.hpp) launders the LDS base addresses: they are recomputed where they are used
+// instead of being hoisted out of the Taylor loop (each quantity slot needs its own base register for the
+// paired LDS accesses, and keeping them all live would halve the occupancy).
 
 // A operands of the two-product pair for the top (rows 0..7) and bottom (rows 8..15) row blocks
 struct AOps {

@@ -28,6 +28,11 @@ struct Plain {
     static constexpr int nn = n * n * n;
     static constexpr int NT = ((nn + 63) / 64) * 64;
     static constexpr bool kPreset = PHYS != kGeneric;
+    // Rows of a per-node B_d product issued between scheduling barriers (FP32): three rows (27 loads in
+    // flight at m = 9) for the wider buckets; no barrier for m <= 4 up to N = 7 (the 1024-thread N = 8, 9
+    // blocks run at 128 registers and want one row at a time). Chosen by timing each class of the mixed
+    // 16384-element workload.
+    static constexpr int kNcpGroup = MB >= 9 ? 3 : (N <= 7 ? 0 : 1);
 
     // Byte offsets of the LDS regions, each 16-byte aligned; `total` is the dynamic LDS size.
     struct Layout {
@@ -70,19 +75,27 @@ struct Plain {
             if (hasA) {
                 // flux F_d = A_d u at every node, then its derivative along d
                 if (own) {
-                    const T* Ad = per_elem ? coefs + (3 + D) * m * m
-                                           : static_cast<const T*>(a.A) + er.coef + ((int64_t)D * nn + tid) * m * m;
+                    // Ad: the matrix in LDS (per element, stride 1) or in global memory (per node, stored
+                    // node-fastest so that lanes read consecutive words: stride n^3). The two cases stay
+                    // separate code paths (one pointer for both address spaces miscompiles on gfx950).
+                    auto flux = [&](const T* Ad, int cs) {
 #pragma unroll
-                    for (int s = 0; s < MB; ++s) {
-                        if (s >= m) break;
-                        T acc = 0;
+                        for (int s = 0; s < MB; ++s) {
+                            if (s >= m) break;
+                            T acc = 0;
 #pragma unroll
-                        for (int q = 0; q < MB; ++q) {
-                            if (q >= m) break;
-                            acc = fma(Ad[s * m + q], u[tid * m + q], acc);
+                            for (int q = 0; q < MB; ++q) {
+                                if (q >= m) break;
+                                acc = fma(Ad[(s * m + q) * cs], u[tid * m + q], acc);
+                            }
+                            fbuf[tid * m + s] = acc;
+                            if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
                         }
-                        fbuf[tid * m + s] = acc;
-                    }
+                    };
+                    if (per_elem)
+                        flux(coefs + (3 + D) * m * m, 1);
+                    else  // re-read every Taylor step: the laundered offset keeps the loads inside the loop
+                        flux(static_cast<const T*>(a.A) + er.coef + (int64_t)D * m * m * nn + tid + opaque_zero(), nn);
                 }
                 __syncthreads();
                 if (own) {
@@ -112,19 +125,26 @@ struct Plain {
         if constexpr (kPreset) {
             apply_ncp<T, PHYS, D>(mt, g, r);
         } else {
-            const T* Bd = per_elem ? coefs + D * m * m
-                                   : static_cast<const T*>(a.B) + er.coef + ((int64_t)D * nn + tid) * m * m;
+            // B_d from LDS (per element) or global memory (per node, node-fastest), as for A_d above
+            auto ncp = [&](const T* Bd, int cs) {
 #pragma unroll
-            for (int s = 0; s < MB; ++s) {
-                if (s >= m) break;
-                T acc = 0;
+                for (int s = 0; s < MB; ++s) {
+                    if (s >= m) break;
+                    T acc = 0;
 #pragma unroll
-                for (int q = 0; q < MB; ++q) {
-                    if (q >= m) break;
-                    acc = fma(Bd[s * m + q], g[q], acc);
+                    for (int q = 0; q < MB; ++q) {
+                        if (q >= m) break;
+                        acc = fma(Bd[(s * m + q) * cs], g[q], acc);
+                    }
+                    r[s] = fma(-inv_h, acc, r[s]);
+                    if constexpr (sizeof(T) == 4 && kNcpGroup > 0)
+                        if ((s + 1) % kNcpGroup == 0) __builtin_amdgcn_sched_barrier(0);
                 }
-                r[s] = fma(-inv_h, acc, r[s]);
-            }
+            };
+            if (per_elem)
+                ncp(coefs + D * m * m, 1);
+            else  // re-read every Taylor step: the laundered offset keeps the loads inside the loop
+                ncp(static_cast<const T*>(a.B) + er.coef + (int64_t)D * m * m * nn + tid + opaque_zero(), nn);
         }
     }
 
@@ -254,13 +274,17 @@ struct Plain {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
                     if (own) {
-                        const T* Ad = per_elem ? coefs + (3 + d) * m * m
-                                               : static_cast<const T*>(a.A) + er.coef + ((int64_t)d * nn + tid) * m * m;
-                        for (int s = 0; s < m; ++s) {
-                            T acc = 0;
-                            for (int q = 0; q < m; ++q) acc = fma(Ad[s * m + q], pbuf[tid * m + q], acc);
-                            fbuf[tid * m + s] = acc;
-                        }
+                        auto flux = [&](const T* Ad, int cs) {
+                            for (int s = 0; s < m; ++s) {
+                                T acc = 0;
+                                for (int q = 0; q < m; ++q) acc = fma(Ad[(s * m + q) * cs], pbuf[tid * m + q], acc);
+                                fbuf[tid * m + s] = acc;
+                            }
+                        };
+                        if (per_elem)
+                            flux(coefs + (3 + d) * m * m, 1);
+                        else
+                            flux(static_cast<const T*>(a.A) + er.coef + (int64_t)d * m * m * nn + tid, nn);
                     }
                     __syncthreads();
                     for (int i = valid ? tid : 2 * n2 * m; i < 2 * n2 * m; i += NT) {

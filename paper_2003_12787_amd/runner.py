@@ -7,6 +7,7 @@ import numpy as np
 import torch
 
 from . import stp
+from . import workloads as W
 from .workloads import GENERIC
 
 
@@ -39,8 +40,8 @@ class DeviceBatch:
         up = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
         self.Q = up(b.Q)
         self.params = up(b.params)
-        self.A = up(b.A)
-        self.B = up(b.B)
+        self.A = up(W.coef_abi(b.A, b.coef_per_element))
+        self.B = up(W.coef_abi(b.B, b.coef_per_element))
         self.src = up(b.src)
         self.qavg = torch.empty((E, n ** 3, b.m), device=device, dtype=dt)
         self.favg = torch.empty((E, n ** 3, b.m) if favg_sum else (E, 3, n ** 3, b.m), device=device, dtype=dt)

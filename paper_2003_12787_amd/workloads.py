@@ -45,6 +45,14 @@ class Batch:
         return self.Q.shape[0]
 
 
+def coef_abi(M: np.ndarray | None, per_element: bool) -> np.ndarray | None:
+    """Per-node coefficient matrices [E, 3, n^3, m, m] (the generators' and the oracle's layout) in the
+    library's layout [E, 3, m, m, n^3] (node fastest); per-element matrices [E, 3, m, m] are unchanged."""
+    if M is None or per_element:
+        return M
+    return np.ascontiguousarray(np.moveaxis(M, 2, -1))
+
+
 def _node_positions(n: int) -> np.ndarray:
     """Gauss-Legendre points on [0, 1] from numpy's library routine (used only to sample waves)."""
     x, _ = np.polynomial.legendre.leggauss(n)
@@ -188,7 +196,8 @@ class HeteroBatch:
 
     classes: list of (N, m, physics, flags); cls[e] is the class of element e; off_q / off_coef /
     off_face are per-element offsets (in values) into Q / B (or params) / qface; `parts` holds the
-    uniform sub-batch of each class with `members[c]` the element ids of class c."""
+    uniform sub-batch of each class with `members[c]` the element ids of class c. `coef` holds the
+    per-node B in the library's node-fastest layout (coef_abi)."""
     classes: list
     cls: np.ndarray
     off_q: np.ndarray
@@ -237,7 +246,7 @@ def hetero_generic_batch(nelem: int, seed: int, orders=None, nquants=None, h: fl
         p = parts[c]
         for j, e in enumerate(ids):
             Q[off_q[e]:off_q[e] + sq[e]] = p.Q[j].ravel()
-            coef[off_coef[e]:off_coef[e] + sc[e]] = p.B[j].ravel()
+            coef[off_coef[e]:off_coef[e] + sc[e]] = np.moveaxis(p.B[j], 1, -1).ravel()
             dt[e] = p.dt[j]
     return HeteroBatch(classes, cls, off_q, off_coef, off_face, Q, coef, dt, hh, parts, members,
                        int(sq.sum()), int(sf.sum()))
@@ -250,7 +259,8 @@ class MixedBatch:
     Element e of class cls[e] reads Q at off_q[e], its coefficients at off_coef[e] (into `params` for a
     preset class, into `B` and `A` for a generic one; A shares B's offsets), its source at off_src[e];
     its faces go to off_face[e] and its time-averaged fluxes to 3 * off_q[e]. `members[c]` are the
-    element ids of class c in the order of `parts[c]`."""
+    element ids of class c in the order of `parts[c]`. Per-node A and B are in the library's node-fastest
+    layout (coef_abi)."""
     classes: list
     cls: np.ndarray
     off_q: np.ndarray
@@ -303,9 +313,10 @@ def interleave(parts, classes, seed: int) -> MixedBatch:
         if p.physics != GENERIC:
             params[off_coef[e]:off_coef[e] + sp[e]] = p.params[j].ravel()
         else:
-            B[off_coef[e]:off_coef[e] + sb[e]] = p.B[j].ravel()
+            lay = (lambda M: M.ravel()) if p.coef_per_element else (lambda M: np.moveaxis(M, 1, -1).ravel())
+            B[off_coef[e]:off_coef[e] + sb[e]] = lay(p.B[j])
             if p.A is not None:
-                A[off_coef[e]:off_coef[e] + sb[e]] = p.A[j].ravel()
+                A[off_coef[e]:off_coef[e] + sb[e]] = lay(p.A[j])
         if p.src is not None:
             src[off_src[e]:off_src[e] + ss[e]] = p.src[j].ravel()
         dt[e], hh[e] = p.dt[j], p.h[j]
@@ -357,9 +368,9 @@ def c4_device(nelem: int = 16384, seed: int = SEED0 + 3, device="cuda", h: float
         if k == 0:
             continue
         s0 = int(oc_s[first[c]])
-        blk = B[s0:s0 + k * int(sc_c[c])].view(k, 3 * int(n3[c]), m, m)
+        blk = B[s0:s0 + k * int(sc_c[c])].view(k, 3, m, m, int(n3[c]))  # node-fastest library layout
         blk.mul_(1.0 / math.sqrt(m))
-        cmax = torch.linalg.matrix_norm(blk.double()).amax(dim=1).cpu().numpy()
+        cmax = torch.linalg.matrix_norm(blk.double(), dim=(2, 3)).amax(dim=(1, 2)).cpu().numpy()
         dt[order[first[c]:first[c] + k]] = [cfl_dt(N, h, ci) for ci in cmax]
     to = lambda a, t: torch.from_numpy(np.ascontiguousarray(a)).to(device, t)
     return dict(classes=classes, counts=counts, class_ranges=ranges, order=order, nelem=nelem,

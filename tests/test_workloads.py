@@ -49,6 +49,16 @@ def test_generic_and_hetero():
     assert sz.min() >= 1 and sz.max() <= 4096
 
 
+def test_coef_abi_is_node_fastest():
+    g = W.generic_batch(2, 3, 2, 5, with_A=True)
+    L = W.coef_abi(g.B, False)
+    assert L.shape == (2, 3, 3, 3, 27)
+    e, d, node, s, r = 1, 2, 13, 0, 2
+    assert L.ravel()[(((e * 3 + d) * 3 + s) * 3 + r) * 27 + node] == g.B[e, d, node, s, r]
+    pe = W.generic_batch(2, 3, 2, 5, per_node=False)
+    assert W.coef_abi(pe.B, True) is pe.B
+
+
 def test_interleave_offsets_round_trip():
     parts = [W.elastic_batch(2, 5, 1), W.acoustic_batch(3, 4, 2, per_node=False),
              W.generic_batch(2, 3, 6, 3, with_A=True)]
@@ -61,12 +71,13 @@ def test_interleave_offsets_round_trip():
             assert mb.cls[e] == c
             n = p.Q[j].size
             assert np.array_equal(mb.Q[mb.off_q[e]:mb.off_q[e] + n], p.Q[j].ravel())
-            coef = p.params if p.physics != W.GENERIC else p.B
+            coef = p.params if p.physics != W.GENERIC else W.coef_abi(p.B, p.coef_per_element)
             arr = mb.params if p.physics != W.GENERIC else mb.B
             k = coef[j].size
             assert np.array_equal(arr[mb.off_coef[e]:mb.off_coef[e] + k], coef[j].ravel())
             if p.A is not None:
-                assert np.array_equal(mb.A[mb.off_coef[e]:mb.off_coef[e] + k], p.A[j].ravel())
+                A = W.coef_abi(p.A, p.coef_per_element)
+                assert np.array_equal(mb.A[mb.off_coef[e]:mb.off_coef[e] + k], A[j].ravel())
             if p.src is not None:
                 s = p.src[j].size
                 assert np.array_equal(mb.src[mb.off_src[e]:mb.off_src[e] + s], p.src[j].ravel())
