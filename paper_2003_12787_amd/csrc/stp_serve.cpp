@@ -1,12 +1,15 @@
 // stp_serve.cpp -- serving runtime behind stp_submit / stp_poll / stp_drain.
 //
-// A plan created with serve_mem_budget > 0 owns one HIP stream (default priority) and two host threads:
+// A plan created with serve_mem_budget > 0 owns kLanes serving lanes (a HIP stream at default priority, its
+// own heterogeneous scratch and a completion thread each) and one dispatcher thread:
 //   dispatcher : takes submitted batches in arrival order and admits one when the bytes of its outputs
-//                plus heterogeneous scratch fit the budget next to the batches still in flight; it then
-//                queues the launches on the serving stream and records a completion event;
-//   completer  : waits for the in-flight events in launch order (one stream, so they finish in order),
-//                stamps the completion time and releases the batch's bytes.
-// Tickets carry host monotonic timestamps (submit, launch, completion) for latency statistics.
+//                plus heterogeneous scratch fit the budget next to the batches still in flight; it queues the
+//                launches on the lane with the fewest batches in flight and records a completion event;
+//   completers : one per lane, wait for that lane's events in launch order (one stream, so they finish in
+//                order), stamp the completion time and release the batch's bytes.
+// Small batches cannot fill the GPU and a batch takes at least as long as its slowest element, so several
+// lanes let independent batches overlap. Tickets carry host monotonic timestamps (submit, launch, completion)
+// for latency statistics.
 #include <chrono>
 
 #include "stp_plan.hpp"
@@ -20,6 +23,8 @@ double now_seconds()
 }
 
 namespace {
+
+constexpr int kLanes = 4;
 
 struct Pending {
     uint64_t ticket;
@@ -38,21 +43,30 @@ struct TicketRec {
     stp_ticket_info info;
 };
 
+struct Lane {
+    hipStream_t stream = nullptr;
+    HeteroScratch scratch;
+    std::deque<InFlight> inflight;
+    std::condition_variable cv;
+    std::thread completer;
+};
+
 }  // namespace
 
 struct ServeState {
-    hipStream_t stream = nullptr;
-    HeteroScratch scratch;
+    Lane lanes[kLanes];
     std::mutex mu;
-    std::condition_variable cv_dispatch, cv_complete, cv_idle;
+    std::condition_variable cv_dispatch, cv_idle;
     std::deque<Pending> queue;
-    std::deque<InFlight> inflight;
     std::unordered_map<uint64_t, TicketRec> tickets;
     size_t inflight_bytes = 0;
+    int inflight_count = 0;
     int launching = 0;  // batches popped by the dispatcher whose launch is being queued
     uint64_t next_ticket = 1;
     bool stop = false;
-    std::thread dispatcher, completer;
+    std::thread dispatcher;
+
+    bool idle() const { return queue.empty() && inflight_count == 0 && launching == 0; }
 };
 
 namespace {
@@ -88,18 +102,22 @@ void dispatcher_main(stp_plan_s* p)
         s->queue.pop_front();
         s->inflight_bytes += job.bytes;
         ++s->launching;
-        auto& rec = s->tickets[job.ticket];
-        rec.info.t_start = now_seconds();
+        int li = 0;
+        for (int l = 1; l < kLanes; ++l)
+            if (s->lanes[l].inflight.size() < s->lanes[li].inflight.size()) li = l;
+        Lane& lane = s->lanes[li];
+        s->tickets[job.ticket].info.t_start = now_seconds();
         lk.unlock();
         if (job.batch.dt_h_scalar) {
             job.batch.dt = &job.dt_s;
             job.batch.h = &job.h_s;
         }
-        stp_status st = launch_batch(p, &job.batch, s->stream, &s->scratch);
+        // Only this thread launches on a lane, so its scratch is not shared by overlapping launches.
+        stp_status st = launch_batch(p, &job.batch, lane.stream, &lane.scratch);
         hipEvent_t ev = nullptr;
         if (st == STP_OK) {
             hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-            if (e == hipSuccess) e = hipEventRecord(ev, s->stream);
+            if (e == hipSuccess) e = hipEventRecord(ev, lane.stream);
             if (e != hipSuccess) st = STP_E_DEVICE;
         }
         lk.lock();
@@ -110,39 +128,39 @@ void dispatcher_main(stp_plan_s* p)
             r.info.status = st;
             r.info.t_done = now_seconds();
             s->inflight_bytes -= job.bytes;
-            s->cv_complete.notify_one();
-            if (s->queue.empty() && s->inflight.empty() && s->launching == 0) s->cv_idle.notify_all();
+            if (s->idle()) s->cv_idle.notify_all();
             continue;
         }
-        s->inflight.push_back({job.ticket, ev, job.bytes});
-        s->cv_complete.notify_one();
+        lane.inflight.push_back({job.ticket, ev, job.bytes});
+        ++s->inflight_count;
+        lane.cv.notify_one();
     }
-    s->cv_complete.notify_all();
+    for (auto& l : s->lanes) l.cv.notify_all();
 }
 
-void completer_main(stp_plan_s* p)
+void completer_main(stp_plan_s* p, int li)
 {
     ServeState* s = p->serve;
+    Lane& lane = s->lanes[li];
     (void)hipSetDevice(p->device);
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
-        s->cv_complete.wait(lk, [&] {
-            return !s->inflight.empty() || (s->stop && s->queue.empty() && s->launching == 0);
-        });
-        if (s->inflight.empty()) break;  // stopping and everything has completed
-        InFlight f = s->inflight.front();
+        lane.cv.wait(lk, [&] { return !lane.inflight.empty() || (s->stop && s->queue.empty() && s->launching == 0); });
+        if (lane.inflight.empty()) break;  // stopping and everything of this lane has completed
+        InFlight f = lane.inflight.front();
         lk.unlock();
         hipError_t e = hipEventSynchronize(f.ev);
         double t = now_seconds();
         (void)hipEventDestroy(f.ev);
         lk.lock();
-        s->inflight.pop_front();
+        lane.inflight.pop_front();
+        --s->inflight_count;
         auto& r = s->tickets[f.ticket];
         r.info.t_done = t;
         r.info.status = e == hipSuccess ? STP_OK : STP_E_DEVICE;
         s->inflight_bytes -= f.bytes;
         s->cv_dispatch.notify_one();
-        if (s->queue.empty() && s->inflight.empty() && s->launching == 0) s->cv_idle.notify_all();
+        if (s->idle()) s->cv_idle.notify_all();
     }
 }
 
@@ -152,14 +170,18 @@ stp_status serve_start(stp_plan_s* p)
 {
     auto* s = new (std::nothrow) ServeState();
     if (!s) return fail(STP_E_NOMEM, "out of host memory");
-    hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-        delete s;
-        return hip_fail(e, "hipStreamCreate(serving)");
+    for (auto& l : s->lanes) {
+        hipError_t e = hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            for (auto& m : s->lanes)
+                if (m.stream) (void)hipStreamDestroy(m.stream);
+            delete s;
+            return hip_fail(e, "hipStreamCreate(serving)");
+        }
     }
     p->serve = s;
     s->dispatcher = std::thread(dispatcher_main, p);
-    s->completer = std::thread(completer_main, p);
+    for (int l = 0; l < kLanes; ++l) s->lanes[l].completer = std::thread(completer_main, p, l);
     return STP_OK;
 }
 
@@ -172,13 +194,19 @@ void serve_stop(stp_plan_s* p)
         s->stop = true;
     }
     s->cv_dispatch.notify_all();
-    s->cv_complete.notify_all();
     if (s->dispatcher.joinable()) s->dispatcher.join();
-    s->cv_complete.notify_all();
-    if (s->completer.joinable()) s->completer.join();
-    (void)hipStreamSynchronize(s->stream);
-    (void)hipStreamDestroy(s->stream);
-    free_scratch(s->scratch);
+    for (auto& l : s->lanes) {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            l.cv.notify_all();
+        }
+        if (l.completer.joinable()) l.completer.join();
+    }
+    for (auto& l : s->lanes) {
+        (void)hipStreamSynchronize(l.stream);
+        (void)hipStreamDestroy(l.stream);
+        free_scratch(l.scratch);
+    }
     delete s;
     p->serve = nullptr;
 }
@@ -248,7 +276,7 @@ stp_status stp_drain(stp_plan_t p)
     if (!p->serve) return STP_OK;
     ServeState* s = p->serve;
     std::unique_lock<std::mutex> lk(s->mu);
-    s->cv_idle.wait(lk, [&] { return s->queue.empty() && s->inflight.empty() && s->launching == 0; });
+    s->cv_idle.wait(lk, [&] { return s->idle(); });
     return STP_OK;
 }
 
