@@ -135,7 +135,10 @@ def bench_hetero(args, torch, stp, W):
     log("[bench] heterogeneous: generating 16384 generic elements on the device")
     d = W.c4_device(16384)
     E = d["nelem"]
-    plan = stp.Plan(d["classes"], prec=stp.FP32)
+    plan = stp.Plan(d["classes"], prec=stp.FP32, autotune=1)  # tuned (or cached) grid and tile sizes
+    tuned = plan.describe()
+    log(f"[bench] heterogeneous: tuned grid {tuned['hetero_grid_per_cu']}/CU, "
+        f"tile LDS budget {tuned['hetero_lds_budget'] // 1024} KB")
     plan.reserve(E)
     qavg = torch.empty(d["size_q"], device="cuda")
     favg = torch.empty(3 * d["size_q"], device="cuda")
@@ -174,7 +177,10 @@ def bench_hetero(args, torch, stp, W):
            "algorithmic_bytes": bytes_tot, "hbm_gbs_algorithmic": bytes_tot / (ms * 1e-3) / 1e9,
            "hbm_frac": bytes_tot / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
            "gflops": flops_tot / (ms * 1e-3) / 1e9,
-           "ms_one_launch_per_class_sum": float(sum(per_class))}
+           "ms_one_launch_per_class_sum": float(sum(per_class)),
+           "tuned": {"grid_per_cu": tuned["hetero_grid_per_cu"], "tile_lds_budget": tuned["hetero_lds_budget"],
+                     "elements_per_tile": {f"N{c['order']}m{c['nquant']}": c["elements_per_tile"]
+                                           for c in tuned["classes"] if c["tiled"]}}}
     log(f"[bench] heterogeneous: eager {ms:.3f} ms, graph {res['ms_graph']:.3f} ms, "
         f"{res['hbm_gbs_algorithmic']:.0f} GB/s algorithmic; per-class launches sum {sum(per_class):.3f} ms")
     del d, qavg, favg, qface

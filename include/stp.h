@@ -106,6 +106,14 @@ typedef struct {
     int device;                /* HIP device ordinal                                                     */
     int variant;               /* 0 = autotuned choice; otherwise a kernel variant id (STP_VARIANT_*)  */
     size_t serve_mem_budget;   /* bytes of in-flight serving memory for stp_submit; 0 disables serving  */
+    int autotune;              /* with variant = STP_VARIANT_AUTO: 0 = take the kernel variant (single-
+                                  class plans) and the persistent grid and tile LDS budget (heterogeneous
+                                  plans) from the tuning cache, else built-in rules; 1 = also time the
+                                  candidates the cache lacks on a synthetic batch (at plan creation, tens
+                                  of ms per entry) and store them; 2 = retime everything. Cache: the JSON
+                                  file named by STP_TUNE_CACHE, else $HOME/.cache/stp_tune.json, keyed by
+                                  architecture, HIP runtime version, CU count and class. STP_E_INVAL
+                                  outside 0..2.                                                          */
 } stp_plan_desc;
 
 /* Kernel variants selectable through stp_plan_desc.variant (0 = library choice). */
@@ -165,6 +173,12 @@ void stp_plan_free(stp_plan_t plan);
  * scratch is shared, stp_run calls of one heterogeneous plan must not overlap on the device: queue them on
  * one stream, or use one plan per stream. */
 stp_status stp_run(stp_plan_t plan, const stp_batch* batch, void* hip_stream);
+
+/* Describe the plan's choices as a JSON object into buf (NUL-terminated): per class the kernel variant,
+ * whether it is tiled in the persistent heterogeneous launch and its elements per tile, FP64 accumulation;
+ * the persistent grid per CU and the tile LDS budget. STP_E_INVAL for a NULL plan or buffer, or when len
+ * is too small (the message states the size needed). */
+stp_status stp_plan_describe(stp_plan_t plan, char* buf, size_t len);
 
 /* Reserve the device scratch of heterogeneous plans (per-class element lists and tile queues) for batches of
  * up to max_nelem elements, so that later stp_run calls allocate nothing: with a reservation in place stp_run

@@ -168,10 +168,17 @@ stp_status build_class(stp_plan_s* p, ClassState& cs)
     }
     cs.acc64 = p->prec != STP_FP64 && p->acc64_min_order > 0 && cs.cls.order >= p->acc64_min_order;
     const bool hasA = cs.cls.physics == STP_GENERIC && (cs.cls.flags & STP_A_PRESENT);
-    cs.kernel = select_kernel(p, cs);
-    if (!cs.kernel.fn) return fail(STP_E_UNSUPPORTED, "no kernel for N=%d m=%d physics=%d", cs.cls.order,
-                                   cs.cls.nquant, cs.cls.physics);
-    if (cs.kernel.aux == KernelInfo::kAuxEvenOdd) {
+    const KernelInfo chosen = select_kernel(p, cs, &cs.variant);
+    if (!chosen.fn) return fail(STP_E_UNSUPPORTED, "no kernel for N=%d m=%d physics=%d", cs.cls.order,
+                                cs.cls.nquant, cs.cls.physics);
+    cs.cands = p->variant == STP_VARIANT_AUTO ? kernel_candidates(p, cs)
+                                              : std::vector<std::pair<int, KernelInfo>>{{cs.variant, chosen}};
+    bool needEvenOdd = false, needSplit = false;  // tables of every candidate (the tuner may switch)
+    for (auto& c : cs.cands) {
+        needEvenOdd |= c.second.aux == KernelInfo::kAuxEvenOdd;
+        needSplit |= c.second.aux == KernelInfo::kAuxMfmaSplit;
+    }
+    if (needEvenOdd) {
         // even/odd split of D on the symmetric nodes: A = (D[i][j] - D[i][n-1-j])/2, B = (D[i][j] + D[i][n-1-j])/2
         // (i, j < n/2), Cm[i] = D[i][mid], Am[j] = D[mid][j] for odd n
         const int hh = n / 2;
@@ -195,7 +202,7 @@ stp_status build_class(stp_plan_s* p, ClassState& cs)
             if ((st = upload(tf, cnt > 0 ? cnt : 1, &cs.daux)) != STP_OK) return st;
         }
     }
-    if (cs.kernel.aux == KernelInfo::kAuxMfmaSplit) {
+    if (needSplit) {
         // A operands of v_mfma_f32_16x16x16_bf16 for the split contraction: lane l holds row i = l % 16 and
         // K entries k = 4 (l / 16) + t (t = 0..3), which pair with node x = 4 ((l / 16) % 2) + t of the hi
         // (l / 16 < 2) or lo (l / 16 >= 2) part of a line. Matrices: D_hi and D_lo in the top row block
@@ -215,14 +222,8 @@ stp_status build_class(stp_plan_s* p, ClassState& cs)
                 }
         if ((st = upload(&tab[0][0][0], 4 * 64 * 4, &cs.dDsplit)) != STP_OK) return st;
     }
-    cs.lds = cs.kernel.lds(cs.cls.nquant, hasA);
-    if (cs.lds > kMaxLds)
-        return fail(STP_E_UNSUPPORTED, "class N=%d m=%d needs %zu B of LDS (> %zu)", cs.cls.order, cs.cls.nquant,
-                    cs.lds, (size_t)kMaxLds);
-    if (cs.lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(cs.kernel.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cs.lds);
-        if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(LDS)");
-    }
+    (void)hasA;
+    if ((st = set_kernel(p, cs, chosen)) != STP_OK) return st;
     const int io = p->prec == STP_FP64 ? 8 : 4;
     class_cost(cs.cls, io, &cs.bytes, &cs.flops);
     const int64_t n3 = (int64_t)n * n * n, n2 = (int64_t)n * n, m = cs.cls.nquant;
@@ -266,6 +267,7 @@ stp_status stp_plan(const stp_plan_desc* desc, stp_plan_t* out)
     if (desc->acc64_min_order < 0) return fail(STP_E_INVAL, "acc64_min_order < 0");
     if (desc->variant < STP_VARIANT_AUTO || desc->variant > STP_VARIANT_MFMA)
         return fail(STP_E_INVAL, "unknown variant %d", desc->variant);
+    if (desc->autotune < 0 || desc->autotune > 2) return fail(STP_E_INVAL, "autotune=%d outside 0..2", desc->autotune);
     for (int i = 0; i < desc->nclass; ++i) {
         stp_status st = validate_class(desc->classes[i]);
         if (st != STP_OK) return st;
@@ -307,6 +309,15 @@ stp_status stp_plan(const stp_plan_desc* desc, stp_plan_t* out)
             return st;
         }
     }
+    p->autotune = desc->autotune;
+    {
+        stp_status st = autotune_plan(p, desc->autotune);
+        if (st != STP_OK) {
+            free_plan_memory(p);
+            delete p;
+            return st;
+        }
+    }
     if (p->serve_budget > 0) {
         stp_status st = serve_start(p);
         if (st != STP_OK) {
@@ -340,6 +351,32 @@ stp_status stp_reserve(stp_plan_t p, int64_t max_nelem)
     return reserve_scratch(p, p->run_scratch, max_nelem);
 }
 
+stp_status stp_plan_describe(stp_plan_t p, char* buf, size_t len)
+{
+    g_last_error.clear();
+    if (!p) return fail(STP_E_INVAL, "plan is NULL");
+    if (!buf || len == 0) return fail(STP_E_INVAL, "buffer is NULL or empty");
+    static const char* names[] = {"auto", "plain", "fused", "mfma"};
+    std::string out = "{\"classes\": [";
+    char tmp[256];
+    for (size_t c = 0; c < p->classes.size(); ++c) {
+        const ClassState& cs = p->classes[c];
+        std::snprintf(tmp, sizeof tmp,
+                      "%s{\"order\": %d, \"nquant\": %d, \"physics\": %d, \"variant\": \"%s\", \"tiled\": %s, "
+                      "\"elements_per_tile\": %d, \"acc64\": %s}",
+                      c ? ", " : "", cs.cls.order, cs.cls.nquant, cs.cls.physics,
+                      names[cs.variant >= 0 && cs.variant <= 3 ? cs.variant : 0], cs.tiled ? "true" : "false",
+                      cs.tiled ? cs.slots : 1, cs.acc64 ? "true" : "false");
+        out += tmp;
+    }
+    std::snprintf(tmp, sizeof tmp, "], \"hetero_grid_per_cu\": %d, \"hetero_lds_budget\": %zu, \"autotune\": %d}",
+                  p->hetero_grid_per_cu, p->hetero_lds_budget, p->autotune);
+    out += tmp;
+    if (out.size() + 1 > len) return fail(STP_E_INVAL, "buffer of %zu bytes too small (%zu needed)", len, out.size() + 1);
+    std::memcpy(buf, out.c_str(), out.size() + 1);
+    return STP_OK;
+}
+
 stp_status stp_class_cost(stp_plan_t p, int cls, double* bytes, double* flops)
 {
     if (!p) return fail(STP_E_INVAL, "plan is NULL");
@@ -363,6 +400,25 @@ stp_status stp_run(stp_plan_t p, const stp_batch* b, void* stream)
 }  // extern "C"
 
 namespace stp {
+
+stp_status set_kernel(stp_plan_s* p, ClassState& cs, const KernelInfo& k)
+{
+    (void)p;
+    const bool hasA = cs.cls.physics == STP_GENERIC && (cs.cls.flags & STP_A_PRESENT);
+    const size_t lds = k.lds(cs.cls.nquant, hasA);
+    if (lds > kMaxLds)
+        return fail(STP_E_UNSUPPORTED, "class N=%d m=%d needs %zu B of LDS (> %zu)", cs.cls.order, cs.cls.nquant, lds,
+                    (size_t)kMaxLds);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(k.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(LDS)");
+    }
+    cs.kernel = k;
+    cs.lds = lds;
+    for (auto& c : cs.cands)
+        if (c.second.fn == k.fn) cs.variant = c.first;
+    return STP_OK;
+}
 
 stp_status validate_batch(stp_plan_s* p, const stp_batch* b)
 {

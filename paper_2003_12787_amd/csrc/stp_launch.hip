@@ -100,26 +100,50 @@ void free_scratch(HeteroScratch& s)
     s = HeteroScratch{};
 }
 
-KernelInfo select_kernel(stp_plan_s* p, const ClassState& cs)
+namespace {
+
+struct Eligibility {
+    bool fused, mfma;
+};
+
+Eligibility eligible(const stp_plan_s* p, const ClassState& cs)
 {
     const bool preset = cs.cls.physics != STP_GENERIC;
     const bool f32io = p->prec != STP_FP64;
     const bool simple = preset && f32io && !cs.acc64 && !(cs.cls.flags & STP_SRC_POINT);
-    const bool fused_ok = simple && cs.cls.order <= 7;
-    const bool mfma_ok = simple && cs.cls.order == 7 && p->prec == STP_BF16X3;
+    return {simple && cs.cls.order <= 7, simple && cs.cls.order == 7 && p->prec == STP_BF16X3};
+}
+
+}  // namespace
+
+std::vector<std::pair<int, KernelInfo>> kernel_candidates(stp_plan_s* p, const ClassState& cs)
+{
+    const Eligibility el = eligible(p, cs);
+    std::vector<std::pair<int, KernelInfo>> v;
+    v.push_back({STP_VARIANT_PLAIN,
+                 plain_kernel(p->prec == STP_FP64, cs.acc64, cs.cls.order, cs.cls.physics, cs.cls.nquant)});
+    if (el.fused) v.push_back({STP_VARIANT_FUSED, fused_kernel_f32(cs.cls.order, cs.cls.physics)});
+    if (el.mfma) v.push_back({STP_VARIANT_MFMA, mfma_kernel_n7(cs.cls.physics)});
+    return v;
+}
+
+KernelInfo select_kernel(stp_plan_s* p, const ClassState& cs, int* variant)
+{
+    const Eligibility el = eligible(p, cs);
     const KernelInfo plain = plain_kernel(p->prec == STP_FP64, cs.acc64, cs.cls.order, cs.cls.physics, cs.cls.nquant);
-    switch (p->variant) {
+    int v = p->variant;
+    if (v == STP_VARIANT_AUTO)  // built-in rule: matrix cores where a kernel exists, else fused, else plain
+        v = el.mfma ? STP_VARIANT_MFMA : (el.fused ? STP_VARIANT_FUSED : STP_VARIANT_PLAIN);
+    if (variant) *variant = v;
+    switch (v) {
     case STP_VARIANT_PLAIN:
         return plain;
     case STP_VARIANT_FUSED:
-        return fused_ok ? fused_kernel_f32(cs.cls.order, cs.cls.physics) : KernelInfo{};
+        return el.fused ? fused_kernel_f32(cs.cls.order, cs.cls.physics) : KernelInfo{};
     case STP_VARIANT_MFMA:
-        return mfma_ok ? mfma_kernel_n7(cs.cls.physics) : KernelInfo{};
+        return el.mfma ? mfma_kernel_n7(cs.cls.physics) : KernelInfo{};
     default:
-        // split-BF16 plans use the matrix cores where a kernel exists and the FP32 kernels elsewhere
-        if (mfma_ok) return mfma_kernel_n7(cs.cls.physics);
-        if (fused_ok) return fused_kernel_f32(cs.cls.order, cs.cls.physics);
-        return plain;
+        return KernelInfo{};
     }
 }
 
@@ -206,6 +230,12 @@ stp_status launch_batch(stp_plan_s* p, const stp_batch* b, hipStream_t stream, H
 stp_status hetero_prepare(stp_plan_s* p)
 {
     const int nclass = (int)p->classes.size();
+    for (void** q : {&p->d_hcls, (void**)&p->d_slots, (void**)&p->d_orders, (void**)&p->d_bncls})
+        if (*q) {
+            (void)hipFree(*q);
+            *q = nullptr;
+        }
+    const size_t budget = p->hetero_lds_budget;
     p->buckets.assign(kHeteroBuckets, BucketPlan{});
     std::vector<hetero::HClass> hc(nclass);
     std::vector<int32_t> slots(nclass, 1), orders(kHeteroBuckets * kMaxClasses, 0), bncls(kHeteroBuckets, 0);
@@ -219,11 +249,11 @@ stp_status hetero_prepare(stp_plan_s* p)
             const int bk = hetero::bucket_of(cs.cls.physics, cs.cls.nquant);
             const HeteroKernel k = hetero_kernel_f32(bk);
             const size_t sl = k.fn ? k.slot_lds(N, cs.cls.nquant, hasA) : 0;
-            if (k.fn && sl <= kHeteroLdsBudget) {
+            if (k.fn && sl <= budget) {
                 cs.tiled = true;
                 cs.bucket = bk;
                 cs.slot_lds = sl;
-                cs.slots = (int)std::min<size_t>(k.threads / nn, kHeteroLdsBudget / sl);
+                cs.slots = (int)std::min<size_t>(k.threads / nn, budget / sl);
                 p->buckets[bk].kernel = k;
                 p->buckets[bk].order.push_back(c);
             }

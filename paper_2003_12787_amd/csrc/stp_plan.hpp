@@ -33,6 +33,8 @@ struct ClassState {
     void* daux = nullptr;    // even/odd derivative tables in the compute precision (fused variant)
     bool acc64 = false;      // FP64 accumulation of q-bar and faces
     KernelInfo kernel;
+    int variant = 0;                               // STP_VARIANT_* of `kernel`
+    std::vector<std::pair<int, KernelInfo>> cands; // kernels that exist for this class (variant, kernel)
     size_t lds = 0;
     double bytes = 0, flops = 0;  // algorithmic cost per element
     int64_t size_q = 0, size_face = 0, size_coef = 0, size_src = 0;  // values per element
@@ -82,6 +84,8 @@ struct stp_plan_s {
     int32_t* d_orders = nullptr;  // [kHeteroBuckets][kMaxClasses]
     int32_t* d_bncls = nullptr;   // [kHeteroBuckets]
     int hetero_grid_per_cu = 4;   // persistent workgroups per CU
+    size_t hetero_lds_budget = stp::kHeteroLdsBudget;  // LDS of one persistent workgroup (sets tile sizes)
+    int autotune = 0;
     stp::ServeState* serve = nullptr;
 };
 
@@ -91,7 +95,13 @@ stp_status fail(stp_status st, const char* fmt, ...);
 stp_status hip_fail(hipError_t e, const char* what);
 void class_cost(const stp_class& c, int io_bytes, double* bytes, double* flops);
 stp_status validate_batch(stp_plan_s* p, const stp_batch* b);
-KernelInfo select_kernel(stp_plan_s* p, const ClassState& cs);
+KernelInfo select_kernel(stp_plan_s* p, const ClassState& cs, int* variant = nullptr);
+// Kernels that exist for the class under the plan's precision (variant id, kernel).
+std::vector<std::pair<int, KernelInfo>> kernel_candidates(stp_plan_s* p, const ClassState& cs);
+// Make `k` the class's kernel (LDS size and attribute).
+stp_status set_kernel(stp_plan_s* p, ClassState& cs, const KernelInfo& k);
+// Plan-time autotuning with the JSON cache (mode: 0 cache only, 1 tune what is missing, 2 retune).
+stp_status autotune_plan(stp_plan_s* p, int mode);
 // Queue the kernels of a validated, non-empty batch on `stream`, using `scratch` for heterogeneous lists.
 stp_status launch_batch(stp_plan_s* p, const stp_batch* b, hipStream_t stream, HeteroScratch* scratch = nullptr);
 // Plan-time set-up of the heterogeneous path (class tiling, buckets, device descriptors).

@@ -23,7 +23,7 @@ VARIANT_AUTO, VARIANT_PLAIN, VARIANT_FUSED, VARIANT_MFMA = 0, 1, 2, 3
 
 # Exported symbols declared in include/stp.h.
 SYMBOLS = ("stp_plan", "stp_plan_free", "stp_run", "stp_reserve", "stp_submit", "stp_poll", "stp_drain",
-           "stp_class_cost", "stp_last_error")
+           "stp_class_cost", "stp_plan_describe", "stp_last_error")
 
 
 class StpError(RuntimeError):
@@ -39,7 +39,7 @@ class Class(C.Structure):
 class PlanDesc(C.Structure):
     _fields_ = [("nclass", C.c_int), ("classes", C.POINTER(Class)), ("prec", C.c_int),
                 ("acc64_min_order", C.c_int), ("device", C.c_int), ("variant", C.c_int),
-                ("serve_mem_budget", C.c_size_t)]
+                ("serve_mem_budget", C.c_size_t), ("autotune", C.c_int)]
 
 
 class Batch(C.Structure):
@@ -78,9 +78,11 @@ def lib():
         L.stp_drain.argtypes = [C.c_void_p]
         L.stp_class_cost.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.stp_reserve.argtypes = [C.c_void_p, C.c_int64]
+        L.stp_plan_describe.argtypes = [C.c_void_p, C.c_char_p, C.c_size_t]
         L.stp_last_error.argtypes = []
         L.stp_last_error.restype = C.c_char_p
-        for f in ("stp_plan", "stp_run", "stp_reserve", "stp_submit", "stp_poll", "stp_drain", "stp_class_cost"):
+        for f in ("stp_plan", "stp_run", "stp_reserve", "stp_submit", "stp_poll", "stp_drain", "stp_class_cost",
+                  "stp_plan_describe"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -108,11 +110,11 @@ class Plan:
     """A predictor plan (owns its device tables). classes: list of (order, nquant, physics, flags)."""
 
     def __init__(self, classes, prec=FP32, acc64_min_order=0, device=0, variant=VARIANT_AUTO,
-                 serve_mem_budget=0):
+                 serve_mem_budget=0, autotune=0):
         arr = (Class * len(classes))(*[Class(*c) for c in classes])
         self.classes = [tuple(c) for c in classes]
         self.prec = prec
-        desc = PlanDesc(len(classes), arr, prec, acc64_min_order, device, variant, serve_mem_budget)
+        desc = PlanDesc(len(classes), arr, prec, acc64_min_order, device, variant, serve_mem_budget, autotune)
         h = C.c_void_p()
         _check(lib().stp_plan(C.byref(desc), C.byref(h)))
         self.handle = h
@@ -131,6 +133,13 @@ class Plan:
     def reserve(self, max_nelem):
         """Preallocate heterogeneous scratch so that run() allocates nothing (graph capture)."""
         _check(lib().stp_reserve(self.handle, int(max_nelem)))
+
+    def describe(self):
+        """The plan's kernel choices (variant per class, tiling, persistent grid) as a dict."""
+        import json
+        buf = C.create_string_buffer(1 << 16)
+        _check(lib().stp_plan_describe(self.handle, buf, len(buf)))
+        return json.loads(buf.value.decode())
 
     def cost(self, cls=0):
         """Algorithmic (bytes, flops) of one element of class `cls`."""

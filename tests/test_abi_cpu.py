@@ -58,6 +58,15 @@ def test_plan_rejects_invalid_classes_on_host(L, classes, prec, expect):
     d = _desc(classes, prec)
     h = C.c_void_p()
     assert L.stp_plan(C.byref(d), C.byref(h)) == expect
+
+
+@pytest.mark.parametrize("mode", [-1, 3])
+def test_plan_rejects_unknown_autotune_mode(L, mode):
+    d = _desc([(3, 9, stp.ELASTIC, 0)])
+    d.autotune = mode
+    h = C.c_void_p()
+    assert L.stp_plan(C.byref(d), C.byref(h)) == stp.E_INVAL
+    assert "autotune" in stp.last_error()
     assert h.value is None
     assert stp.last_error() != ""
 
@@ -83,6 +92,7 @@ def test_null_plan_entry_points(L):
     assert L.stp_poll(None, 1, None) == stp.E_INVAL
     assert L.stp_drain(None) == stp.E_INVAL
     assert L.stp_reserve(None, 10) == stp.E_INVAL
+    assert L.stp_plan_describe(None, None, 0) == stp.E_INVAL
     assert L.stp_class_cost(None, 0, None, None) == stp.E_INVAL
     L.stp_plan_free(None)  # no-op
     assert "NULL" in stp.last_error()

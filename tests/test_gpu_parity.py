@@ -424,6 +424,56 @@ def test_uniform_graph_capture_replays():
         plan.close()
 
 
+# ------------------------------------------------------------------------------------------------ autotuner
+def test_autotune_single_class_variant_is_cached_and_correct(tmp_path, monkeypatch):
+    import json
+    from paper_2003_12787_amd import runner
+    monkeypatch.setenv("STP_TUNE_CACHE", str(tmp_path / "tune.json"))
+    b = W.c3_elastic_n7(512)
+    cls = runner.class_of(b)
+    say("[tune] elastic N=7 BF16X3, autotune=1")
+    plan = stp.Plan([cls], prec=stp.BF16X3, autotune=1)
+    d = plan.describe()
+    say(f"[tune]   chose {d['classes'][0]['variant']}")
+    assert d["classes"][0]["variant"] in ("plain", "fused", "mfma")
+    cache = json.load(open(tmp_path / "tune.json"))
+    entry = [v for k, v in cache.items() if "|class|N7,m9,p1" in k]
+    assert len(entry) == 1 and entry[0]["us_per_elem"] > 0
+    got = runner.run(plan, b)
+    ref = oracle_run(runner.rounded(b, stp.BF16X3))
+    err = max_rel_err(got, ref, runner.rounded(b, stp.BF16X3).Q, b.h)
+    assert max(err.values()) < TOL[stp.BF16X3], err
+    plan.close()
+    again = stp.Plan([cls], prec=stp.BF16X3, autotune=0)  # from the cache
+    assert again.describe()["classes"][0]["variant"] == d["classes"][0]["variant"]
+    again.close()
+
+
+def test_autotune_heterogeneous_grid_and_tiles(tmp_path, monkeypatch):
+    import json
+    monkeypatch.setenv("STP_TUNE_CACHE", str(tmp_path / "tune.json"))
+    mb = mixed_batch()
+    say(f"[tune] mixed physics classes={len(mb.classes)} autotune=1")
+    plan = stp.Plan(mb.classes, prec=stp.FP32, autotune=1)
+    d = plan.describe()
+    say(f"[tune]   grid/CU {d['hetero_grid_per_cu']} LDS budget {d['hetero_lds_budget']}")
+    assert d["hetero_grid_per_cu"] in (2, 4, 8)
+    assert d["hetero_lds_budget"] in (48 * 1024, 80 * 1024, 128 * 1024)
+    for c, (N, m, phys, flags) in zip(d["classes"], mb.classes):
+        assert c["tiled"] == (N <= 7), c
+        if c["tiled"]:
+            assert 1 <= c["elements_per_tile"] <= 512 // (N + 1) ** 3
+    cache = json.load(open(tmp_path / "tune.json"))
+    assert any("|hetero|" in k for k in cache)
+    got = run_mixed(plan, mb, stp.FP32)
+    check_mixed(mb, stp.FP32, got)
+    plan.close()
+    again = stp.Plan(mb.classes, prec=stp.FP32, autotune=0)
+    d2 = again.describe()
+    assert (d2["hetero_grid_per_cu"], d2["hetero_lds_budget"]) == (d["hetero_grid_per_cu"], d["hetero_lds_budget"])
+    again.close()
+
+
 # ------------------------------------------------------------------------------------------------ edges
 def test_empty_batch_is_noop():
     from paper_2003_12787_amd import runner
