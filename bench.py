@@ -128,6 +128,28 @@ def time_launches(fn, steps, warmup, stream, torch):
     return np.array([a.elapsed_time(b) for a, b in ev])
 
 
+def bench_acoustic(args, torch, stp, W, runner):
+    """Acoustic plane wave, N = 5 (6^3 nodes), m = 4, 32768 elements, rho = 1, K per element: the plain
+    FP64 predictor against the fused FP32 kernel (their accuracy against the oracle is a parity test)."""
+    log("[bench] acoustic N=5 plane wave, 32768 elements")
+    b = W.c2_acoustic_n5()
+    out = {"workload": "acoustic plane wave N=5 (6^3 nodes), m=4, 32768 elements, rho=1, K~U[1,2] per element"}
+    for name, prec, var in (("fp64_plain", stp.FP64, stp.VARIANT_PLAIN), ("fp32_fused", stp.FP32, stp.VARIANT_FUSED)):
+        plan = stp.Plan([runner.class_of(b)], prec=prec, variant=var)
+        db = runner.DeviceBatch(plan, b)
+        ms = float(np.median(time_launches(lambda st: plan.run(db.cbatch, st), args.steps, args.warmup,
+                                           torch.cuda.Stream(), torch)))
+        bytes_el = plan.cost(0)[0]
+        out[name] = {"ms": ms, "elements_per_s": b.nelem / (ms * 1e-3),
+                     "hbm_gbs_algorithmic": bytes_el * b.nelem / (ms * 1e-3) / 1e9}
+        log(f"[bench] acoustic {name}: {ms:.3f} ms")
+        del db
+        plan.close()
+    torch.cuda.empty_cache()
+    out["speedup_fp32_fused_vs_fp64_plain"] = out["fp64_plain"]["ms"] / out["fp32_fused"]["ms"]
+    return out
+
+
 def bench_hetero(args, torch, stp, W):
     """Mixed orders and quantity counts in one batch: 16384 generic elements, N ~ U{2..9}, m ~ U{4, 9},
     dense per-node B_d, FP32. Times the heterogeneous stp_run (eager and replayed from a captured HIP graph)
@@ -292,7 +314,10 @@ def main():
     torch.cuda.set_device(0)
     E = args.nelem
     log(f"[bench] generating elastic N=7 workload, {E} elements")
-    b = W.c3_elastic_n7(nelem=E)
+    # inputs rounded to FP32 once: every variant (FP64 included) and the oracle see the same values
+    b = runner.rounded(W.c3_elastic_n7(nelem=E), stp.FP32)
+    err_ids = np.linspace(0, E - 1, min(E, 2048)).astype(np.int64)  # elements checked against the oracle
+    sampled = {}
     cls = runner.class_of(b)
     results = {}
     variants = args.variants.split(",")
@@ -307,6 +332,9 @@ def main():
         plan = stp.Plan([cls], prec=prec, variant=var)
         db = runner.DeviceBatch(plan, b)
         r = time_variant(name, plan, db, args.steps, args.warmup, torch)
+        idx = torch.from_numpy(err_ids).cuda()
+        sampled[name] = {k: v.index_select(0, idx).double().cpu().numpy() for k, v in
+                         (("qavg", db.qavg), ("favg", db.favg), ("qface", db.qface))}
         bytes_el, flops_el = plan.cost(0)
         r["elements_per_s"] = E / (r["ms_median"] * 1e-3)
         r["gflops"] = flops_el * E / (r["ms_median"] * 1e-3) / 1e9
@@ -339,6 +367,7 @@ def main():
     if args.copy_gib > 0:
         copy = copy_bandwidth(args.copy_gib, torch)
 
+    acoustic = None if args.no_hetero else bench_acoustic(args, torch, stp, W, runner)
     hetero = None if args.no_hetero else bench_hetero(args, torch, stp, W)
     serving = None if args.no_serve else bench_serving(args, torch, stp, W)
 
@@ -353,11 +382,24 @@ def main():
         oracle.stp(b.N, b.physics, b.Q[probe], b.dt[probe], b.h[probe], params=b.params[probe], nthreads=threads)
         rate = len(probe) / (time.perf_counter() - t0)
         k = int(min(E, max(threads, rate * args.cpu_seconds)))
-        ids = np.linspace(0, E - 1, k).astype(np.int64)
+        ids = np.unique(np.concatenate([np.linspace(0, E - 1, k).astype(np.int64), err_ids]))
+        k = len(ids)
         log(f"[bench] CPU oracle on {k} elements, {threads} threads")
         t0 = time.perf_counter()
-        oracle.stp(b.N, b.physics, b.Q[ids], b.dt[ids], b.h[ids], params=b.params[ids], nthreads=threads)
+        ref = oracle.stp(b.N, b.physics, b.Q[ids], b.dt[ids], b.h[ids], params=b.params[ids], nthreads=threads)
         t = time.perf_counter() - t0
+        # per-output max-relative error of every variant on the checked elements (a subset of the sample)
+        pos = np.searchsorted(ids, err_ids)
+        for name, got in sampled.items():
+            errs = {}
+            for key in ("qavg", "favg", "qface"):
+                y = ref[key][pos].reshape(len(pos), -1)
+                x = got[key].reshape(len(pos), -1)
+                errs[key] = float((np.abs(x - y).max(axis=1) / np.abs(y).max(axis=1)).max())
+            results[name]["max_rel_err_vs_oracle"] = errs
+            results[name]["checked_elements"] = int(len(pos))
+            log(f"[bench] {name}: max rel err vs oracle {errs}")
+        del ref
         cpu = {"value": k / t, "unit": "element-updates/s", "cores": threads, "kind": "oracle",
                "sample": f"{k} of the {E} elements (evenly spaced), FP64, {t:.1f} s"}
         log(f"[bench] CPU oracle: {k / t:.1f} el/s")
@@ -382,6 +424,7 @@ def main():
         "cpu_baseline": cpu,
         "variants": results,
         "copy_reference": copy,
+        "acoustic_n5": acoustic,
         "heterogeneous": hetero,
         "serving": serving,
         "latency_p50_ms": serving["load_80pct"]["p50_ms"] if serving else None,
