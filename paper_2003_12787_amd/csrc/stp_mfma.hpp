@@ -88,7 +88,7 @@ struct Mfma8 {
     static constexpr int WG = 128;  // one element per workgroup (two waves)
     using S = fused::Sets<PHYS>;
     static constexpr int NPS = S::NPS, NG = S::NG;
-    static constexpr int YS = 8, ZS = 69, SLOT = n * ZS;  // compact tile: 4 elements per CU fit in LDS
+    static constexpr int SLOT = n3;  // one quantity's tile, swizzled (at()): 4 elements per CU fit in LDS
     static constexpr int ELDS = (NPS + NG) * SLOT;
     static constexpr int STAGE = 16 * n * M;  // per-wave staging of 16 lines of an output block (floats)
     static constexpr int LDS_FLOATS = ELDS + 2 * STAGE;
@@ -144,47 +144,88 @@ struct Mfma8 {
         }
     }
 
-    // tile address of node (z, y, x)
-    __device__ static inline int at(int z, int y, int x) { return z * ZS + y * YS + x; }
+    // Tile address of node (z, y, x), an XOR swizzle. The LDS serves 32 lanes at a time from 32 banks, and in
+    // each of the three access patterns (owner lines along x: z in {2j, 2j+1}, all y, x = 4h + t; y-role lines:
+    // y = 4h + t, all x; z-role lines: z = 4h + t, y in {2j, 2j+1}, all x) the 32 lanes of a half-wave vary in
+    // five node bits. The bank bits
+    //   b0 = x0 ^ y0, b1 = x1 ^ y1, b2 = x2, b3 = y0 ^ y2, b4 = z0 ^ z2
+    // are independent over each of those five-bit sets, so every pattern hits 32 distinct banks; the
+    // remaining bits (z1, x0, x1, z0) select one of 16 groups of 32 words. A padded linear layout leaves 2- to
+    // 4-way conflicts.
+    __host__ __device__ static constexpr int at(int z, int y, int x)
+    {
+        const int bank = ((x ^ y) & 3) | (x & 4) | (((y ^ (y >> 2)) & 1) << 3) | (((z ^ (z >> 2)) & 1) << 4);
+        const int group = ((z >> 1) & 1) | ((x & 3) << 1) | ((z & 1) << 3);
+        return 32 * group + bank;
+    }
+
+    static constexpr bool at_is_permutation()
+    {
+        bool seen[n3] = {};
+        for (int z = 0; z < n; ++z)
+            for (int y = 0; y < n; ++y)
+                for (int x = 0; x < n; ++x) {
+                    const int v = at(z, y, x);
+                    if (v < 0 || v >= n3 || seen[v]) return false;
+                    seen[v] = true;
+                }
+        return true;
+    }
+    static_assert(at_is_permutation(), "the swizzled tile covers [0, n^3) once");
+
+    // A lane's tile offsets for its four nodes t = 0..3 in the owner, y-role and z-role patterns (fixed for
+    // the kernel's lifetime: the lane's line never changes).
+    struct Offs {
+        int o[4], y[4], z[4];
+    };
+    __device__ static inline Offs offsets(int la, int lb, int h)
+    {
+        Offs f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            f.o[t] = at(la, lb, 4 * h + t);
+            f.y[t] = at(la, 4 * h + t, lb);
+            f.z[t] = at(4 * h + t, la, lb);
+        }
+        return f;
+    }
 
     // y- or z-role: lines (a, b) = (z, x) resp. (y, x), nodes 4h..4h+3 along the line
     template <int D>
-    __device__ static inline void transposed(const AOps& A, const float* P0, float* G0, int a, int b, int h)
+    __device__ static inline void transposed(const AOps& A, const float* P0, float* G0, const Offs& f)
     {
         const int z0 = opaque_zero();
         const float* P = P0 + z0;
         float* G = G0 + z0;
+        const int(&off)[4] = D == 1 ? f.y : f.z;
 #pragma unroll
         for (int k = 0; k < NG; ++k) {
             const int s = S::slot(S::dq(D, k));
             float u[4], g[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) u[t] = D == 1 ? P[s * SLOT + at(a, 4 * h + t, b)] : P[s * SLOT + at(4 * h + t, a, b)];
+            for (int t = 0; t < 4; ++t) u[t] = P[s * SLOT + off[t]];
             deriv_mfma(A, u, g);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                if (D == 1) G[k * SLOT + at(a, 4 * h + t, b)] = g[t];
-                else G[k * SLOT + at(4 * h + t, a, b)] = g[t];
-            }
+            for (int t = 0; t < 4; ++t) G[k * SLOT + off[t]] = g[t];
             __builtin_amdgcn_sched_barrier(0);
         }
     }
 
     template <int D, int K = 0>
-    __device__ static inline void gather(const float* G0, int z, int y, int h, const Material<float, PHYS> (&mt)[4],
+    __device__ static inline void gather(const float* G0, const Offs& f, const Material<float, PHYS> (&mt)[4],
                                          float (&r)[M][4])
     {
         const float* G = G0 + (K == 0 ? opaque_zero() : 0);
         if constexpr (K < NG) {
             float g[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) g[t] = G[K * SLOT + at(z, y, 4 * h + t)];
+            for (int t = 0; t < 4; ++t) g[t] = G[K * SLOT + f.o[t]];
             ncp<D, K>(mt, g, r);
-            gather<D, K + 1>(G, z, y, h, mt, r);
+            gather<D, K + 1>(G, f, mt, r);
         }
     }
 
-    __device__ static inline void write_tile(float* P0, int z, int y, int h, const float (&v)[M][4])
+    __device__ static inline void write_tile(float* P0, const Offs& f, const float (&v)[M][4])
     {
         float* P = P0 + opaque_zero();
 #pragma unroll
@@ -192,7 +233,7 @@ struct Mfma8 {
             const int s = S::slot(q);
             if (s < 0) continue;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) P[s * SLOT + at(z, y, 4 * h + t)] = v[q][t];
+            for (int t = 0; t < 4; ++t) P[s * SLOT + f.o[t]] = v[q][t];
         }
     }
 
@@ -270,6 +311,7 @@ struct Mfma8 {
         const int c = l & 15, h = (l >> 4) & 1, g = l >> 5;
         const int line = 32 * wv + 16 * g + c;
         const int la = line >> 3, lb = line & 7;  // owner (z, y); y-role (z, x); z-role (y, x)
+        const Offs off = offsets(la, lb, h);
         float* P = reinterpret_cast<float*>(smem);
         float* G = P + NPS * SLOT;
         float* Sw = P + ELDS + wv * STAGE;  // this wave's staging area
@@ -307,21 +349,21 @@ struct Mfma8 {
             const float dt = (float)er.dt;
 #pragma unroll 1
             for (int o = 1; o <= N; ++o) {
-                write_tile(P, la, lb, h, p);
+                write_tile(P, off, p);
                 __syncthreads();
                 float r[M][4];
 #pragma unroll
                 for (int q = 0; q < M; ++q)
 #pragma unroll
                     for (int t = 0; t < 4; ++t) r[q][t] = 0.f;
-                transposed<1>(A, P, G, la, lb, h);
+                transposed<1>(A, P, G, off);
                 xpass(A, mt, p, r);
                 __syncthreads();
-                gather<1>(G, la, lb, h, mt, r);
+                gather<1>(G, off, mt, r);
                 __syncthreads();
-                transposed<2>(A, P, G, la, lb, h);
+                transposed<2>(A, P, G, off);
                 __syncthreads();
-                gather<2>(G, la, lb, h, mt, r);
+                gather<2>(G, off, mt, r);
                 w = w * dt / (float)(o + 1);
 #pragma unroll
                 for (int q = 0; q < M; ++q)
@@ -338,7 +380,7 @@ struct Mfma8 {
             const bool al = (er.q & 3) == 0;  // 16-byte aligned element blocks (float offsets)
             const int64_t wbase = (int64_t)32 * wv * n * M;  // first float of this wave's lines in a block
             store_block(Sw, static_cast<float*>(a.qavg) + er.q + wbase, qb, l, g, c, h, al);
-            write_tile(P, la, lb, h, qb);
+            write_tile(P, off, qb);
             __syncthreads();
             {
                 float fx[M][4];
@@ -346,7 +388,7 @@ struct Mfma8 {
                 for (int q = 0; q < M; ++q)
 #pragma unroll
                     for (int t = 0; t < 4; ++t) fx[q][t] = 0.f;
-                transposed<1>(A, P, G, la, lb, h);
+                transposed<1>(A, P, G, off);
                 xpass(A, mt, qb, fx);
                 float* fav = static_cast<float*>(a.favg) + (fsum ? er.q : 3 * er.q) + wbase;
                 if (!fsum) {
@@ -357,7 +399,7 @@ struct Mfma8 {
                         for (int t = 0; t < 4; ++t) fx[q][t] = 0.f;
                 }
                 __syncthreads();
-                gather<1>(G, la, lb, h, mt, fx);
+                gather<1>(G, off, mt, fx);
                 if (!fsum) {
                     store_block(Sw, fav + (int64_t)n3 * M, fx, l, g, c, h, al);
 #pragma unroll
@@ -366,9 +408,9 @@ struct Mfma8 {
                         for (int t = 0; t < 4; ++t) fx[q][t] = 0.f;
                 }
                 __syncthreads();
-                transposed<2>(A, P, G, la, lb, h);
+                transposed<2>(A, P, G, off);
                 __syncthreads();
-                gather<2>(G, la, lb, h, mt, fx);
+                gather<2>(G, off, mt, fx);
                 store_block(Sw, fsum ? fav : fav + 2 * (int64_t)n3 * M, fx, l, g, c, h, al);
             }
             // faces: partial sums over the lane's 4 nodes, completed with the other half-line (lane ^ 16); the
@@ -384,7 +426,7 @@ struct Mfma8 {
 #pragma unroll
             for (int q = 0; q < M; ++q)
 #pragma unroll
-                for (int t = 0; t < 4; ++t) P[q * SLOT + at(la, lb, 4 * h + t)] = qb[q][t];
+                for (int t = 0; t < 4; ++t) P[q * SLOT + off.o[t]] = qb[q][t];
 #pragma unroll
             for (int q = 0; q < M; ++q) {
                 float s0 = 0.f, s1 = 0.f;
@@ -403,8 +445,8 @@ struct Mfma8 {
                 float y0 = 0.f, y1 = 0.f, z0 = 0.f, z1 = 0.f;
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const float vy = P[q * SLOT + at(la, 4 * h + t, lb)];  // y-role (z, x)
-                    const float vz = P[q * SLOT + at(4 * h + t, la, lb)];  // z-role (y, x)
+                    const float vy = P[q * SLOT + off.y[t]];  // y-role (z, x)
+                    const float vz = P[q * SLOT + off.z[t]];  // z-role (y, x)
                     y0 = fma(e0[t], vy, y0);
                     y1 = fma(e1[t], vy, y1);
                     z0 = fma(e0[t], vz, z0);
