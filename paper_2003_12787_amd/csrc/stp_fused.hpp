@@ -57,12 +57,44 @@ struct Fused {
     static constexpr int NP = PhysTraits<PHYS>::np;
     static constexpr int WG = wg_size(n);
     static constexpr int EPB = WG / n2;  // elements per workgroup
-    static constexpr int YS = n, ZS = zstride(n), SLOT = n * ZS;
+    // n = 8: a 512-word XOR-swizzled tile (at()); other orders: padded linear tile, y-stride n, z-stride ZS
+    static constexpr bool kSwz = n == 8;
+    static constexpr int YS = n, ZS = zstride(n), SLOT = kSwz ? n3 : n * ZS;
     using S = Sets<PHYS>;
     static constexpr int NPS = S::NPS, NG = S::NG;
     static constexpr int ELDS = (NPS + NG) * SLOT;  // words of LDS per element
     static_assert(NPS + NG >= M, "face pass reuses the tile for all quantities");
     static_assert(n2 <= 64, "fused kernel covers n <= 8");
+
+    // Tile address of node (z, y, x). For n = 8 the address is Lz(z) ^ Ly(y) ^ x, which puts the bank bits at
+    //   b0 = x0 ^ z0, b1 = x1 ^ z1, b2 = x2 ^ y2, b3 = y0 ^ z0, b4 = y1 ^ z1
+    // and z0, z1, z2, y2 in the four group bits. The 32 lanes of a half-wave vary in z0, z1, y0, y1, y2
+    // (owner lines), z0, z1 and x (y-role lines) or y0, y1 and x (z-role lines), and the bank bits are
+    // independent over each of these sets, so every access pattern hits 32 distinct banks. The padded linear
+    // layout leaves 2-way conflicts.
+    __host__ __device__ static constexpr int at(int z, int y, int x)
+    {
+        if constexpr (kSwz) {
+            const int lz = (z & 1) * (1 | 8 | 32) ^ ((z >> 1) & 1) * (2 | 16 | 64) ^ ((z >> 2) & 1) * 128;
+            const int ly = (y & 3) * 8 ^ ((y >> 2) & 1) * (4 | 256);
+            return lz ^ ly ^ x;
+        } else {
+            return z * ZS + y * YS + x;
+        }
+    }
+    static constexpr bool at_is_permutation()
+    {
+        bool seen[n * n * n] = {};
+        for (int z = 0; z < n; ++z)
+            for (int y = 0; y < n; ++y)
+                for (int x = 0; x < n; ++x) {
+                    const int v = at(z, y, x);
+                    if (v < 0 || v >= n3 || seen[v]) return false;
+                    seen[v] = true;
+                }
+        return true;
+    }
+    static_assert(!kSwz || at_is_permutation(), "the swizzled tile covers [0, n^3) once");
 
     // even/odd derivative tables: A[i][j], B[i][j] (i, j < h), Cm[i] (odd n), Am[j] (odd n)
     struct Tab {
@@ -165,12 +197,12 @@ struct Fused {
             T u[n], g[n];
 #pragma unroll
             for (int j = 0; j < n; ++j)
-                u[j] = D == 1 ? P[s * SLOT + a * ZS + j * YS + b] : P[s * SLOT + j * ZS + a * YS + b];
+                u[j] = D == 1 ? P[s * SLOT + at(a, j, b)] : P[s * SLOT + at(j, a, b)];
             deriv(tb, u, g);
 #pragma unroll
             for (int i = 0; i < n; ++i) {
-                if (D == 1) G[k * SLOT + a * ZS + i * YS + b] = g[i];
-                else G[k * SLOT + i * ZS + a * YS + b] = g[i];
+                if (D == 1) G[k * SLOT + at(a, i, b)] = g[i];
+                else G[k * SLOT + at(i, a, b)] = g[i];
             }
         }
     }
@@ -181,7 +213,7 @@ struct Fused {
         if constexpr (K < NG) {
             T g[n];
 #pragma unroll
-            for (int x = 0; x < n; ++x) g[x] = G[K * SLOT + z * ZS + y * YS + x];
+            for (int x = 0; x < n; ++x) g[x] = G[K * SLOT + at(z, y, x)];
             ncp<D, K>(mt, g, r);
             gather<D, K + 1>(G, z, y, mt, r);
         }
@@ -212,7 +244,7 @@ struct Fused {
             const int s = S::slot(q);
             if (s < 0) continue;
 #pragma unroll
-            for (int x = 0; x < n; ++x) P[s * SLOT + z * ZS + y * YS + x] = v[q][x];
+            for (int x = 0; x < n; ++x) P[s * SLOT + at(z, y, x)] = v[q][x];
         }
     }
 
@@ -413,7 +445,7 @@ struct Fused {
 #pragma unroll
                 for (int q = 0; q < M; ++q)
 #pragma unroll
-                    for (int x = 0; x < n; ++x) P[q * SLOT + la * ZS + lb * YS + x] = qb[q][x];
+                    for (int x = 0; x < n; ++x) P[q * SLOT + at(la, lb, x)] = qb[q][x];
             }
             __syncthreads();
             if (act) {
@@ -422,8 +454,8 @@ struct Fused {
                     T y0 = 0, y1 = 0, z0 = 0, z1 = 0;
 #pragma unroll
                     for (int j = 0; j < n; ++j) {
-                        const T vy = P[q * SLOT + la * ZS + j * YS + lb];  // y-role (z, x)
-                        const T vz = P[q * SLOT + j * ZS + la * YS + lb];  // z-role (y, x)
+                        const T vy = P[q * SLOT + at(la, j, lb)];  // y-role (z, x)
+                        const T vz = P[q * SLOT + at(j, la, lb)];  // z-role (y, x)
                         y0 = fma(e0[j], vy, y0);
                         y1 = fma(e1[j], vy, y1);
                         z0 = fma(e0[j], vz, z0);
