@@ -26,6 +26,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 # VALU peaks from the unit counts: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz.
 # FP32 without packed instructions runs at the FP64 rate (packed FP32 is not used by this build).
 ALU_PEAK_TFS = {"f64": 78.6, "f32": 78.6}
+MFMA_BF16_PEAK_TFS = 2500.0    # dense BF16 matrix-core peak
 
 
 def log(*a):
@@ -350,13 +351,23 @@ def main():
     fp32_names = [k for k in results if results[k]["dtype"] == "f32"]
     head = max(fp32_names, key=lambda k: results[k]["elements_per_s"]) if fp32_names else variants[0]
     h = results[head]
-    # roofline of the dominant (only) kernel of a step: which ceiling binds at the algorithmic counts
+    # Roofline of the dominant (only) kernel of a step: which ceiling binds at the algorithmic counts. The
+    # derivative contractions are 2 n n^3 q_d flops per direction and application (q_d = 6 quantities read
+    # by the elastic B_d), N+1 applications; on the split-BF16x3 variant they run on the matrix cores as
+    # three BF16 products (dense BF16 peak), the rest of its flops on the VALU.
+    n = b.N + 1
+    contr = (b.N + 1) * 3 * 2 * n * n ** 3 * 6
     t_hbm = h["bytes_per_element"] / (HBM_PEAK_GBS * 1e9)
-    t_alu = h["flops_per_element"] / (ALU_PEAK_TFS[h["dtype"]] * 1e12)
-    if t_hbm >= t_alu:
+    if head == "bf16x3_mfma":
+        t_cmp = 3 * contr / (MFMA_BF16_PEAK_TFS * 1e12) + (h["flops_per_element"] - contr) / (ALU_PEAK_TFS["f32"] * 1e12)
+    else:
+        t_cmp = h["flops_per_element"] / (ALU_PEAK_TFS[h["dtype"]] * 1e12)
+    if t_hbm >= t_cmp:
         roof = {"bound": "hbm", "achieved": h["hbm_gbs_algorithmic"], "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     else:
         roof = {"bound": "alu", "achieved": h["gflops"] / 1e3, "peak": ALU_PEAK_TFS[h["dtype"]], "unit": "TFLOP/s"}
+    roof["t_hbm_ns_per_element"] = t_hbm * 1e9
+    roof["t_compute_ns_per_element"] = t_cmp * 1e9
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"], roof["traffic_over_algorithmic"] = measured_traffic(head, h["bytes_per_element"] * E)
     roof["kernel"] = head
