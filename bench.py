@@ -342,37 +342,39 @@ def main():
         r["hbm_gbs_algorithmic"] = bytes_el * E / (r["ms_median"] * 1e-3) / 1e9
         r["bytes_per_element"] = bytes_el
         r["flops_per_element"] = flops_el
-        r["dtype"] = "f64" if prec == stp.FP64 else "f32"
+        # arithmetic of the path: FP64, FP32, or split-BF16x3 contractions with FP32 accumulation and FP32 VALU
+        r["dtype"] = {stp.FP64: "f64", stp.FP32: "f32", stp.BF16X3: "bf16x3"}[prec]
         results[name] = r
         del db
         plan.close()
         torch.cuda.empty_cache()
 
-    fp32_names = [k for k in results if results[k]["dtype"] == "f32"]
+    fp32_names = [k for k in results if results[k]["dtype"] != "f64"]  # FP32 I/O variants
     head = max(fp32_names, key=lambda k: results[k]["elements_per_s"]) if fp32_names else variants[0]
     h = results[head]
     # Roofline of the dominant (only) kernel of a step: which ceiling binds at the algorithmic counts. The
     # derivative contractions are 2 n n^3 q_d flops per direction and application (q_d = 6 quantities read
     # by the elastic B_d), N+1 applications; on the split-BF16x3 variant they run on the matrix cores as
     # three BF16 products (dense BF16 peak), the rest of its flops on the VALU.
+    valu = "f64" if h["dtype"] == "f64" else "f32"  # the VALU type of the non-contraction work
     n = b.N + 1
     contr = (b.N + 1) * 3 * 2 * n * n ** 3 * 6
     t_hbm = h["bytes_per_element"] / (HBM_PEAK_GBS * 1e9)
     if head == "bf16x3_mfma":
         t_cmp = 3 * contr / (MFMA_BF16_PEAK_TFS * 1e12) + (h["flops_per_element"] - contr) / (ALU_PEAK_TFS["f32"] * 1e12)
     else:
-        t_cmp = h["flops_per_element"] / (ALU_PEAK_TFS[h["dtype"]] * 1e12)
+        t_cmp = h["flops_per_element"] / (ALU_PEAK_TFS[valu] * 1e12)
     if t_hbm >= t_cmp:
         roof = {"bound": "hbm", "achieved": h["hbm_gbs_algorithmic"], "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     else:
-        roof = {"bound": "alu", "achieved": h["gflops"] / 1e3, "peak": ALU_PEAK_TFS[h["dtype"]], "unit": "TFLOP/s"}
+        roof = {"bound": "alu", "achieved": h["gflops"] / 1e3, "peak": ALU_PEAK_TFS[valu], "unit": "TFLOP/s"}
     roof["t_hbm_ns_per_element"] = t_hbm * 1e9
     roof["t_compute_ns_per_element"] = t_cmp * 1e9
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"], roof["traffic_over_algorithmic"] = measured_traffic(head, h["bytes_per_element"] * E)
     roof["kernel"] = head
     roof["hbm_frac"] = h["hbm_gbs_algorithmic"] / HBM_PEAK_GBS
-    roof["alu_frac"] = h["gflops"] / 1e3 / ALU_PEAK_TFS[h["dtype"]]
+    roof["alu_frac"] = h["gflops"] / 1e3 / ALU_PEAK_TFS[valu]
 
     copy = None
     if args.copy_gib > 0:
