@@ -1,6 +1,7 @@
 // stp_launch.hip -- kernel selection and launch of a batch: one launch for a uniform batch, or for a
-// heterogeneous batch a device-side bucketing pass (element lists per class, no host synchronisation)
-// followed by one persistent-grid launch per class, all on the caller's stream.
+// heterogeneous batch a device-side bucketing pass (element lists per class, tile queues per bucket, no host
+// synchronisation) followed by one persistent launch per physics bucket on the caller's stream, with the
+// classes that have their own launch forked onto side streams and joined back with events.
 #include <algorithm>
 
 #include "stp_hetero.hpp"
@@ -97,6 +98,11 @@ void free_scratch(HeteroScratch& s)
 {
     for (void* q : {(void*)s.lists, (void*)s.counts, (void*)s.tile_start, (void*)s.heads})
         if (q) (void)hipFree(q);
+    for (int i = 0; i < kSideStreams; ++i) {
+        if (s.side[i]) (void)hipStreamDestroy(s.side[i]);
+        if (s.join[i]) (void)hipEventDestroy(s.join[i]);
+    }
+    if (s.fork) (void)hipEventDestroy(s.fork);
     s = HeteroScratch{};
 }
 
@@ -160,6 +166,13 @@ stp_status reserve_scratch(stp_plan_s* p, HeteroScratch& s, int64_t nelem)
     if ((e = hipMalloc(&s.tile_start, sizeof(int32_t) * kHeteroBuckets * (kMaxClasses + 1))) != hipSuccess)
         return hip_fail(e, "hipMalloc(tile_start)");
     if ((e = hipMalloc(&s.heads, sizeof(int32_t) * kHeteroBuckets)) != hipSuccess) return hip_fail(e, "hipMalloc(heads)");
+    if ((e = hipEventCreateWithFlags(&s.fork, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    for (int i = 0; i < kSideStreams; ++i) {
+        if ((e = hipStreamCreateWithFlags(&s.side[i], hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "hipStreamCreate(side)");
+        if ((e = hipEventCreateWithFlags(&s.join[i], hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(e, "hipEventCreate");
+    }
     s.cap = (int64_t)cap;
     return STP_OK;
 }
@@ -195,13 +208,24 @@ stp_status launch_batch(stp_plan_s* p, const stp_batch* b, hipStream_t stream, H
     for (int c = 0; c < nclass; ++c)
         if (!p->classes[c].tiled) order.push_back(c);
     std::sort(order.begin(), order.end(), [&](int x, int y) { return p->classes[x].flops > p->classes[y].flops; });
-    for (int c : order) {
+    bool anyTiled = false;
+    for (auto& bp : p->buckets) anyTiled |= !bp.order.empty();
+    // with tiled classes present, the own-launch classes go to the side streams (fork after the setup pass)
+    const bool fork = anyTiled && !order.empty();
+    const int nside = fork ? std::min<int>(kSideStreams, (int)order.size()) : 0;
+    if (fork) {
+        if ((e = hipEventRecord(s->fork, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord(fork)");
+        for (int i = 0; i < nside; ++i)
+            if ((e = hipStreamWaitEvent(s->side[i], s->fork, 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+    }
+    for (size_t k = 0; k < order.size(); ++k) {
+        const int c = order[k];
         const ClassState& cs = p->classes[c];
         StpArgs a = base_args(p, cs, b);
         a.list = s->lists + (int64_t)c * s->cap;
         a.count = s->counts + c;
         const int64_t grid = std::min<int64_t>(b->nelem, (int64_t)p->num_cus * 8);
-        stp_status st = launch_one(cs, a, grid, stream);
+        stp_status st = launch_one(cs, a, grid, fork ? s->side[k % nside] : stream);
         if (st != STP_OK) return st;
     }
     // one persistent launch per physics bucket for the tiled classes
@@ -223,6 +247,10 @@ stp_status launch_batch(stp_plan_s* p, const stp_batch* b, hipStream_t stream, H
         const int grid = (int)std::min<int64_t>((int64_t)p->num_cus * p->hetero_grid_per_cu, b->nelem);
         e = hipLaunchKernel(bp.kernel.fn, dim3(grid), dim3(bp.kernel.threads), args, bp.lds, stream);
         if (e != hipSuccess) return hip_fail(e, "hipLaunchKernel(heterogeneous)");
+    }
+    for (int i = 0; i < nside; ++i) {  // join: the caller's stream waits for the side streams
+        if ((e = hipEventRecord(s->join[i], s->side[i])) != hipSuccess) return hip_fail(e, "hipEventRecord(join)");
+        if ((e = hipStreamWaitEvent(stream, s->join[i], 0)) != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
     }
     return STP_OK;
 }

@@ -53,12 +53,19 @@ struct BucketPlan {
 };
 
 // Device scratch of heterogeneous launches: per-class element lists and counts.
+constexpr int kSideStreams = 2;
+
 struct HeteroScratch {
     int32_t* lists = nullptr;       // [nclass][cap]
     int32_t* counts = nullptr;      // [kMaxClasses]
     int32_t* tile_start = nullptr;  // [kHeteroBuckets][kMaxClasses + 1]
     int32_t* heads = nullptr;       // [kHeteroBuckets]
     int64_t cap = 0;
+    // Classes with their own launch run on side streams, forked from and joined back into the caller's
+    // stream with events, concurrently with the persistent launches (their tails overlap).
+    hipStream_t side[kSideStreams] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kSideStreams] = {};
 };
 
 struct ServeState;
