@@ -53,7 +53,7 @@ struct BucketPlan {
 };
 
 // Device scratch of heterogeneous launches: per-class element lists and counts.
-constexpr int kSideStreams = 2;
+constexpr int kSideStreams = 4;
 
 struct HeteroScratch {
     int32_t* lists = nullptr;       // [nclass][cap]
