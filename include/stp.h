@@ -188,7 +188,8 @@ stp_status stp_plan_describe(stp_plan_t plan, char* buf, size_t len);
 stp_status stp_reserve(stp_plan_t plan, int64_t max_nelem);
 
 /* Serving: enqueue a batch for the plan's dispatcher thread. The batch descriptor is copied; its device
- * buffers must stay valid until stp_poll reports completion. Admission: the batch's output+scratch bytes
+ * buffers must stay valid until stp_poll reports completion. The serving streams do not wait for any other
+ * stream: work that produces the inputs (or touches the outputs) must be complete before stp_submit. Admission: the batch's output+scratch bytes
  * must fit serve_mem_budget (STP_E_NOMEM if it never can); batches wait while the in-flight total would
  * exceed it. Returns STP_E_BUSY when the queue holds 65536 pending tickets. */
 stp_status stp_submit(stp_plan_t plan, const stp_batch* batch, uint64_t* ticket);

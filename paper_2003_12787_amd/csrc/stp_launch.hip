@@ -210,8 +210,10 @@ stp_status launch_batch(stp_plan_s* p, const stp_batch* b, hipStream_t stream, H
     std::sort(order.begin(), order.end(), [&](int x, int y) { return p->classes[x].flops > p->classes[y].flops; });
     bool anyTiled = false;
     for (auto& bp : p->buckets) anyTiled |= !bp.order.empty();
-    // with tiled classes present, the own-launch classes go to the side streams (fork after the setup pass)
-    const bool fork = anyTiled && !order.empty();
+    // With tiled classes present, the own-launch classes go to the side streams (fork after the setup pass).
+    // Small batches stay on one stream: there the fork and join cost more than the overlap gains (serving
+    // batches of a few hundred elements lost half their throughput).
+    const bool fork = anyTiled && !order.empty() && b->nelem >= kForkMinElements;
     const int nside = fork ? std::min<int>(kSideStreams, (int)order.size()) : 0;
     if (fork) {
         if ((e = hipEventRecord(s->fork, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord(fork)");

@@ -54,6 +54,7 @@ struct BucketPlan {
 
 // Device scratch of heterogeneous launches: per-class element lists and counts.
 constexpr int kSideStreams = 4;
+constexpr int64_t kForkMinElements = 8192;  // heterogeneous batches at least this large use the side streams
 
 struct HeteroScratch {
     int32_t* lists = nullptr;       // [nclass][cap]

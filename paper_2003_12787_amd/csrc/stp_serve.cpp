@@ -179,6 +179,24 @@ stp_status serve_start(stp_plan_s* p)
             return hip_fail(e, "hipStreamCreate(serving)");
         }
     }
+    if (p->classes.size() > 1) {
+        // Heterogeneous scratch sized up front for the largest batch the budget admits (at most 64 Ki elements),
+        // so that the dispatcher does not synchronise the device to grow it in the common case.
+        stp_batch one{};
+        one.nelem = 1;
+        const int64_t cap = std::min<int64_t>(65536, std::max<int64_t>(1, (int64_t)(p->serve_budget / batch_bytes(p, &one))));
+        for (auto& l : s->lanes) {
+            stp_status st = reserve_scratch(p, l.scratch, cap);
+            if (st != STP_OK) {
+                for (auto& m : s->lanes) {
+                    free_scratch(m.scratch);
+                    if (m.stream) (void)hipStreamDestroy(m.stream);
+                }
+                delete s;
+                return st;
+            }
+        }
+    }
     p->serve = s;
     s->dispatcher = std::thread(dispatcher_main, p);
     for (int l = 0; l < kLanes; ++l) s->lanes[l].completer = std::thread(completer_main, p, l);

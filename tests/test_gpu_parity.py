@@ -398,6 +398,18 @@ def test_heterogeneous_graph_capture_replays():
     plan.close()
 
 
+def test_heterogeneous_graph_capture_replays_with_side_streams():
+    """A batch large enough (>= 8192 elements) that the own-launch classes fork onto side streams: the
+    captured fork/join replays bit for bit and matches the oracle on a sample."""
+    mb = mixed_batch(E_scale=40, seed=908)
+    assert len(mb.cls) >= 8192
+    say(f"[graph] mixed physics E={len(mb.cls)} (side streams) captured after stp_reserve")
+    plan = stp.Plan(mb.classes, prec=stp.FP32)
+    got = run_mixed(plan, mb, stp.FP32, graph_replays=3)
+    check_mixed(mb, stp.FP32, got, sample_per_class=6)
+    plan.close()
+
+
 def test_uniform_graph_capture_replays():
     import torch
     from paper_2003_12787_amd import runner
@@ -422,6 +434,39 @@ def test_uniform_graph_capture_replays():
                 assert np.array_equal(out[k], ref[k]), (prec, r, k)
         del g
         plan.close()
+
+
+def test_serving_heterogeneous_batches_match_run():
+    """Mixed-physics batches through the serving lanes (each with its own scratch) equal stp_run's output."""
+    import torch
+    mb = mixed_batch(seed=907)
+    plan = stp.Plan(mb.classes, prec=stp.FP32, serve_mem_budget=256 << 20)
+    ref = run_mixed(plan, mb, stp.FP32)
+    to = lambda a, t: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", t)
+    ins = dict(Q=to(mb.Q, torch.float32), params=to(mb.params, torch.float32), B=to(mb.B, torch.float32),
+               A=to(mb.A, torch.float32), src=to(mb.src, torch.float32))
+    idx = dict(cls=to(mb.cls, torch.int32), off_q=to(mb.off_q, torch.int64), off_coef=to(mb.off_coef, torch.int64),
+               off_face=to(mb.off_face, torch.int64), off_src=to(mb.off_src, torch.int64))
+    dts, hs = to(mb.dt, torch.float64), to(mb.h, torch.float64)
+    outs, tickets = [], []
+    say(f"[serve] mixed physics E={len(mb.cls)} x 8 submissions")
+    for _ in range(8):
+        o = dict(qavg=torch.zeros(mb.size_q, device="cuda"), favg=torch.zeros(3 * mb.size_q, device="cuda"),
+                 qface=torch.zeros(mb.size_face, device="cuda"), fface=torch.zeros(mb.size_face, device="cuda"))
+        b = plan.batch(len(mb.cls), ins["Q"], o["qavg"], o["favg"], o["qface"], dts, hs, params=ins["params"],
+                       A=ins["A"], B=ins["B"], src=ins["src"], fface=o["fface"], **idx)
+        outs.append((o, b))
+    torch.cuda.synchronize()  # the serving streams do not wait for the caller's streams (the zero fills)
+    for _, b in outs:
+        tickets.append(plan.submit(b))
+    plan.drain()
+    for t in tickets:
+        st, _ = plan.poll(t)
+        assert st == stp.OK
+    for o, _ in outs:
+        for k, v in o.items():
+            assert np.array_equal(v.double().cpu().numpy(), ref[k]), k
+    plan.close()
 
 
 # ------------------------------------------------------------------------------------------------ autotuner
