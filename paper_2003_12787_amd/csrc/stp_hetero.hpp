@@ -20,7 +20,7 @@ namespace hetero {
 
 constexpr int kThreads = 512;
 constexpr int kMaxOrder = 7;
-constexpr int kBuckets = 7;
+constexpr int kBuckets = 4;
 
 // Device descriptor of one class.
 struct HClass {
@@ -48,21 +48,22 @@ struct HArgs {
     int ncls;
 };
 
-// Buckets: 0 acoustic, 1 elastic, 2 generic m == 4, 3 generic m == 9, 4 generic m < 4, 5 generic m <= 9,
-// 6 generic m <= 16 (the last three with the quantity count at run time).
+// Buckets: 0 acoustic, 1 elastic, 2 generic m == 4, 3 generic m == 9; -1 (no tiling: the class keeps its own
+// launch) for generic classes with another quantity count, whose run-time-m element routines would cost
+// minutes of compile time per bucket for classes that are rare in practice.
 __host__ __device__ inline int bucket_of(int physics, int m)
 {
     if (physics == kAcoustic) return 0;
     if (physics == kElastic) return 1;
     if (m == 4) return 2;
     if (m == 9) return 3;
-    return m < 4 ? 4 : (m <= 9 ? 5 : 6);
+    return -1;
 }
 
 template <int B>
 struct BucketTraits {
     static constexpr int PHYS = B == 0 ? kAcoustic : (B == 1 ? kElastic : kGeneric);
-    static constexpr int MB = (B == 0 || B == 2 || B == 4) ? 4 : ((B == 1 || B == 3 || B == 5) ? 9 : 16);
+    static constexpr int MB = (B == 0 || B == 2) ? 4 : 9;
     static constexpr bool EX = B == 2 || B == 3;
 };
 

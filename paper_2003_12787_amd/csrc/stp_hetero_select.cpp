@@ -7,9 +7,6 @@ HeteroKernel hetero_kernel_f32_b0();
 HeteroKernel hetero_kernel_f32_b1();
 HeteroKernel hetero_kernel_f32_b2();
 HeteroKernel hetero_kernel_f32_b3();
-HeteroKernel hetero_kernel_f32_b4();
-HeteroKernel hetero_kernel_f32_b5();
-HeteroKernel hetero_kernel_f32_b6();
 
 HeteroKernel hetero_kernel_f32(int bucket)
 {
@@ -18,9 +15,6 @@ HeteroKernel hetero_kernel_f32(int bucket)
     case 1: return hetero_kernel_f32_b1();
     case 2: return hetero_kernel_f32_b2();
     case 3: return hetero_kernel_f32_b3();
-    case 4: return hetero_kernel_f32_b4();
-    case 5: return hetero_kernel_f32_b5();
-    case 6: return hetero_kernel_f32_b6();
     default: return HeteroKernel{};
     }
 }

@@ -20,6 +20,16 @@ struct KernelInfo {
 KernelInfo plain_kernel_f64(int N, int physics, int m);
 KernelInfo plain_kernel_f32(int N, int physics, int m);
 KernelInfo plain_kernel_f32acc64(int N, int physics, int m);
+// generic classes with a run-time quantity count, bounded by 4, 9 or 16
+KernelInfo plain_kernel_f64_rt4(int N);
+KernelInfo plain_kernel_f64_rt9(int N);
+KernelInfo plain_kernel_f64_rt16(int N);
+KernelInfo plain_kernel_f32_rt4(int N);
+KernelInfo plain_kernel_f32_rt9(int N);
+KernelInfo plain_kernel_f32_rt16(int N);
+KernelInfo plain_kernel_f32acc64_rt4(int N);
+KernelInfo plain_kernel_f32acc64_rt9(int N);
+KernelInfo plain_kernel_f32acc64_rt16(int N);
 // Fused kernel (presets, FP32, N <= 7): lanes own x-lines, even/odd derivatives, LDS transposes.
 KernelInfo fused_kernel_f32(int N, int physics);
 

@@ -18,7 +18,7 @@
 namespace stp {
 
 constexpr int kMaxClasses = 64;
-constexpr int kHeteroBuckets = 7;
+constexpr int kHeteroBuckets = 4;
 constexpr size_t kHeteroLdsBudget = 80 * 1024;  // per workgroup of the persistent kernel (two per CU)
 constexpr size_t kMaxLds = 160 * 1024;
 
