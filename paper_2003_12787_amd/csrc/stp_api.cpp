@@ -244,7 +244,7 @@ void free_plan_memory(stp_plan_s* p)
         for (void* q : {cs.dD, cs.de0, cs.de1, cs.de0_64, cs.de1_64, cs.dDsplit, cs.daux})
             if (q) (void)hipFree(q);
     }
-    for (void* q : {p->d_lists, p->d_counts, p->d_hcls, (void*)p->d_slots, (void*)p->d_orders, (void*)p->d_bncls})
+    for (void* q : {p->d_hcls, (void*)p->d_slots, (void*)p->d_orders, (void*)p->d_bncls})
         if (q) (void)hipFree(q);
     free_scratch(p->run_scratch);
 }

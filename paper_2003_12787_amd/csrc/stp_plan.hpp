@@ -81,8 +81,6 @@ struct stp_plan_s {
     int num_cus = 256;
     size_t serve_budget = 0;
     std::vector<stp::ClassState> classes;
-    void* d_lists = nullptr;   // unused (kept for layout stability of free_plan_memory)
-    void* d_counts = nullptr;
     std::mutex run_mu;         // guards `run_scratch` growth
     stp::HeteroScratch run_scratch;
     // heterogeneous plans
