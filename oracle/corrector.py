@@ -1,0 +1,124 @@
+"""Oracle of the ADER-DG corrector step on a periodic Cartesian mesh (test infrastructure only).
+
+Only tests/, the package's smoke check and the benchmark's CPU leg use this module; the product never
+imports it. Plain numpy in FP64, written from the paper's scheme (Sec. II-A): the time-integrated
+semi-discrete update of Eq. (5) -- the corrector -- uses the predictor's outputs (the time-averaged DOFs
+q-bar, their face projections and the face projections of the conservative flux) and a numerical flux that
+is linear in the face states. The paper leaves that flux open; this oracle takes the reading (R22 in the
+design notes):
+
+  strong form, Gauss-Legendre collocation, diagonal mass matrix h^3 w_k1 w_k2 w_k3 (w: weights on [0,1]);
+  for the face f of an element with outward normal n = s e_d (s = -1 for the lower face, +1 for the upper)
+  and the states q- (own face projection of q-bar), q+ (the neighbour's projection on the same face),
+  F-/F+ (the face projections of A_d q-bar), the face correction entering the element is
+
+      C_f = 1/2 alpha (q+ - q-) - 1/2 s (F+ - F-) - 1/2 s Bbar_d (q+ - q-),
+
+  Bbar_d = (B_d(e) + B_d(neighbour)) / 2, alpha = max(alpha(e), alpha(neighbour)) (Rusanov), with alpha the
+  fastest wave speed of the element: sqrt(K/rho) acoustic, sqrt((lambda+2 mu)/rho) elastic, and for generic
+  coefficients the bound max_d ||A_d + B_d||_inf (maximum absolute row sum).
+
+  q(t_{n+1})_k = q(t_n)_k + dt sum_d favg[d]_k + dt sum_f l_{k_d}(x_f) / (h w_{k_d}) C_f(k_a, k_b)
+
+  where favg[d] = V_d(q-bar) is the predictor's time-averaged volume term, l_j(x_f) the Lagrange basis at the
+  face (0 or 1 along d) and (k_a, k_b) the face node of k. For a single linear wave with speed a > 0 along
+  x this reduces to the upwind flux (the lower face receives a (q+ - q-), the upper face nothing).
+
+Elements are numbered e = (iz * ny + iy) * nx + ix; the mesh is periodic in all three directions. Material
+or coefficients are per element: presets [E, np] (rho, K) or (rho, lambda, mu); generic A, B [E, 3, m, m].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+ACOUSTIC, ELASTIC, GENERIC = 0, 1, 2
+
+
+def gl_weights01(n: int) -> np.ndarray:
+    """Gauss-Legendre weights on [0, 1] (the oracle's quadrature)."""
+    return oracle.gl_nodes(n)[1]
+
+
+def element_B(physics: int, params=None, B=None):
+    """B_d [E, 3, m, m] per element: presets from the material (same matrices as the predictor), generic as
+    given."""
+    if physics == GENERIC:
+        return np.asarray(B, dtype=np.float64)
+    params = np.asarray(params, dtype=np.float64)
+    return np.stack([oracle.preset_B(physics, p) for p in params])
+
+
+def wave_speed(physics: int, params=None, A=None, B=None) -> np.ndarray:
+    """alpha per element (see the module docstring)."""
+    if physics == ACOUSTIC:
+        return np.sqrt(params[:, 1] / params[:, 0])
+    if physics == ELASTIC:
+        return np.sqrt((params[:, 1] + 2 * params[:, 2]) / params[:, 0])
+    M = np.asarray(B, dtype=np.float64) + (0.0 if A is None else np.asarray(A, dtype=np.float64))
+    return np.abs(M).sum(axis=-1).max(axis=(1, 2))
+
+
+def neighbour(e: int, d: int, s: int, nx: int, ny: int, nz: int) -> int:
+    """The periodic neighbour of element e across its face along d on side s (-1 lower, +1 upper)."""
+    ix, iy, iz = e % nx, (e // nx) % ny, e // (nx * ny)
+    if d == 0:
+        ix = (ix + s) % nx
+    elif d == 1:
+        iy = (iy + s) % ny
+    else:
+        iz = (iz + s) % nz
+    return (iz * ny + iy) * nx + ix
+
+
+def correct(N: int, physics: int, grid, Q, favg, qface, dt: float, h: float, params=None, A=None, B=None,
+            fface=None, favg_sum: bool = False):
+    """q(t_{n+1}) [E, n^3, m] from q(t_n) and the predictor outputs of every element of the mesh.
+
+    Q [E, n^3, m]; favg [E, 3, n^3, m] (or [E, n^3, m] with favg_sum); qface, fface [E, 6, n^2, m] with the
+    faces ordered x-, x+, y-, y+, z-, z+ and the face nodes (a, b) = the two other axes, slower first."""
+    nx, ny, nz = grid
+    n = N + 1
+    E = nx * ny * nz
+    Q = np.asarray(Q, dtype=np.float64).reshape(E, n, n, n, -1)  # [e][z][y][x][s]
+    m = Q.shape[-1]
+    fa = np.asarray(favg, dtype=np.float64)
+    vol = fa.reshape(E, n ** 3, m) if favg_sum else fa.reshape(E, 3, n ** 3, m).sum(axis=1)
+    qf = np.asarray(qface, dtype=np.float64).reshape(E, 6, n, n, m)
+    ff = None if fface is None else np.asarray(fface, dtype=np.float64).reshape(E, 6, n, n, m)
+    Bd = element_B(physics, params, B)
+    alpha = wave_speed(physics, params, A, B)
+    w = gl_weights01(n)
+    l0 = oracle.lagrange_at(n, 0.0)
+    l1 = oracle.lagrange_at(n, 1.0)
+    out = Q + dt * vol.reshape(E, n, n, n, m)
+    for e in range(E):
+        for d in range(3):
+            for side, s in ((0, -1), (1, 1)):
+                f = 2 * d + side
+                nb = neighbour(e, d, s, nx, ny, nz)
+                fo = 2 * d + (1 - side)  # the neighbour's face on the shared plane
+                jump = qf[nb, fo] - qf[e, f]  # [a][b][m]
+                Bbar = 0.5 * (Bd[e, d] + Bd[nb, d])
+                a = max(alpha[e], alpha[nb])
+                C = 0.5 * a * jump - 0.5 * s * jump @ Bbar.T
+                if ff is not None:
+                    C -= 0.5 * s * (ff[nb, fo] - ff[e, f])
+                lift = (l1 if side else l0) / (h * w)  # [k_d]
+                # face node (a, b) = the two other axes, slower first; scatter along the normal axis
+                if d == 0:    # (a, b) = (z, y), normal x
+                    out[e] += dt * lift[None, None, :, None] * C[:, :, None, :]
+                elif d == 1:  # (a, b) = (z, x), normal y
+                    out[e] += dt * lift[None, :, None, None] * C[:, None, :, :]
+                else:         # (a, b) = (y, x), normal z
+                    out[e] += dt * lift[:, None, None, None] * C[None, :, :, :]
+    return out.reshape(E, n ** 3, m)
+
+
+def ader_step(N: int, physics: int, grid, Q, dt: float, h: float, params=None, A=None, B=None):
+    """One full ADER-DG step: the oracle predictor on every element, then the corrector. Per-element
+    coefficients (params [E, np] or A, B [E, 3, m, m])."""
+    pred = oracle.stp(N, physics, Q, dt, h, params=params, A=A, B=B, coef_per_element=True)
+    return correct(N, physics, grid, Q, pred["favg"], pred["qface"], dt, h, params=params, A=A, B=B,
+                   fface=pred.get("fface"))

@@ -1,0 +1,112 @@
+"""Pins of the corrector oracle (the ADER-DG step on a periodic Cartesian mesh), against what the scheme and
+the mathematics fix: steady constant states, the upwind flux for a scalar wave, and the convergence order of
+a full space-time step on smooth plane waves."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import corrector as OC
+
+ACOUSTIC, ELASTIC, GENERIC = 0, 1, 2
+
+
+def node_x(N, nx, h):
+    """x coordinate of every node [E, n^3] of a nx x 1 x 1 mesh (elements along x)."""
+    n = N + 1
+    xi, _ = oracle.gl_nodes(n)
+    x = np.zeros((nx, n, n, n))
+    for e in range(nx):
+        x[e] = (e + xi)[None, None, :] * h
+    return x.reshape(nx, n ** 3)
+
+
+def full_step_dt(N, h, c):
+    """Stable time step of the full 3D step: half the predictor workloads' rule 0.4 h / ((2N+1) c). At the
+    full rule, transverse modes seeded by rounding grow on a 1-element-wide periodic mesh at N = 3."""
+    return 0.2 * h / ((2 * N + 1) * c)
+
+
+def test_constant_state_is_steady_with_jumps_in_material():
+    rng = np.random.default_rng(1)
+    N, grid = 2, (3, 2, 2)
+    E, n3 = 12, 27
+    params = np.stack([rng.uniform(2, 3, E), rng.uniform(1, 4, E), rng.uniform(1, 3, E)], axis=1)
+    q0 = rng.standard_normal(9)
+    Q = np.broadcast_to(q0, (E, n3, 9)).copy()
+    out = OC.ader_step(N, ELASTIC, grid, Q, 0.01, 0.5, params=params)
+    assert np.abs(out - Q).max() < 1e-13
+
+
+def test_scalar_wave_gets_the_upwind_flux():
+    """q_t + a q_x = 0 (generic m = 1, a > 0): the upper face sees no correction, the lower face a (q+ - q-)."""
+    N, nx = 2, 3
+    n = N + 1
+    a, h, dt = 1.5, 0.5, 0.01
+    B = np.zeros((nx, 3, 1, 1))
+    B[:, 0, 0, 0] = a
+    rng = np.random.default_rng(2)
+    # varying along x only, so that the (self-periodic) y and z faces see no jump
+    Q = np.broadcast_to(rng.standard_normal((nx, 1, 1, n)), (nx, n, n, n)).reshape(nx, n ** 3, 1).copy()
+    pred = oracle.stp(N, GENERIC, Q, dt, h, B=B, coef_per_element=True)
+    out = OC.correct(N, GENERIC, (nx, 1, 1), Q, pred["favg"], pred["qface"], dt, h, B=B)
+    qf = pred["qface"].reshape(nx, 6, n, n)
+    w = OC.gl_weights01(n)
+    l0 = oracle.lagrange_at(n, 0.0)
+    ref = Q.reshape(nx, n, n, n) + dt * pred["favg"].sum(axis=1).reshape(nx, n, n, n)
+    for e in range(nx):
+        up = (e - 1) % nx  # upstream neighbour
+        jump = qf[up, 1] - qf[e, 0]  # its x+ face minus our x- face
+        ref[e] += dt * (l0 / (h * w))[None, None, :] * (a * jump)[:, :, None]
+    assert np.abs(out.reshape(nx, n, n, n) - ref).max() < 1e-13
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_acoustic_plane_wave_converges_at_order_N_plus_1(N):
+    """p = sin(2 pi (x - c t)), v_x = p / (rho c) on [0,1] periodic; error at the nodes after t = 0.2."""
+    rho, K = 1.0, 2.25
+    c = np.sqrt(K / rho)
+    errs = []
+    for nx in (8, 16):
+        h = 1.0 / nx
+        x = node_x(N, nx, h)
+        f = lambda t: np.sin(2 * np.pi * (x - c * t))
+        Q = np.zeros((nx, (N + 1) ** 3, 4))
+        Q[..., 0] = f(0.0)
+        Q[..., 1] = f(0.0) / (rho * c)
+        params = np.tile([rho, K], (nx, 1))
+        T = 0.2
+        steps = int(np.ceil(T / full_step_dt(N, h, c)))
+        dt = T / steps
+        for _ in range(steps):
+            Q = OC.ader_step(N, ACOUSTIC, (nx, 1, 1), Q, dt, h, params=params)
+        err = max(np.abs(Q[..., 0] - f(T)).max(), np.abs(Q[..., 1] - f(T) / (rho * c)).max())
+        assert np.abs(Q[..., 2:]).max() < 1e-12  # no transverse velocity appears
+        errs.append(err)
+    rate = np.log2(errs[0] / errs[1])
+    assert rate > N + 1 - 0.25, (errs, rate)
+
+
+def test_elastic_shear_wave_converges():
+    """An S-wave along x: v_y = sin(2 pi (x - cs t)), s_xy = -rho cs v_y; N = 2, rate >= 2.75 (16 -> 32
+    elements; the Rusanov speed is the P-wave speed, so the S-wave needs the finer pair to be asymptotic)."""
+    N = 2
+    rho, lam, mu = 2.0, 3.0, 1.5
+    cs = np.sqrt(mu / rho)
+    errs = []
+    for nx in (16, 32):
+        h = 1.0 / nx
+        x = node_x(N, nx, h)
+        f = lambda t: np.sin(2 * np.pi * (x - cs * t))
+        Q = np.zeros((nx, (N + 1) ** 3, 9))
+        Q[..., 1] = f(0.0)
+        Q[..., 6] = -rho * cs * f(0.0)
+        params = np.tile([rho, lam, mu], (nx, 1))
+        T = 0.3
+        cp = np.sqrt((lam + 2 * mu) / rho)
+        steps = int(np.ceil(T / full_step_dt(N, h, cp)))
+        dt = T / steps
+        for _ in range(steps):
+            Q = OC.ader_step(N, ELASTIC, (nx, 1, 1), Q, dt, h, params=params)
+        errs.append(max(np.abs(Q[..., 1] - f(T)).max(), np.abs(Q[..., 6] + rho * cs * f(T)).max()))
+    rate = np.log2(errs[0] / errs[1])
+    assert rate > 2.75, (errs, rate)
