@@ -174,6 +174,34 @@ void stp_plan_free(stp_plan_t plan);
  * one stream, or use one plan per stream. */
 stp_status stp_run(stp_plan_t plan, const stp_batch* batch, void* hip_stream);
 
+/* One corrector step on a periodic Cartesian mesh (the update of Sec. II-A, Eq. (5)): from q(t_n) and the
+ * predictor's outputs of every element, q(t_{n+1}) = q(t_n) + dt sum_d favg[d] + dt (face terms). The
+ * numerical flux is linear (a Rusanov flux in fluctuation form, upwind for a single wave): at the face of an
+ * element with outward normal s e_d and states q-/F- (own face projections of q-bar and A_d q-bar) and q+/F+
+ * (the neighbour's), the correction is C = 1/2 alpha (q+ - q-) - 1/2 s (F+ - F-) - 1/2 s Bbar_d (q+ - q-),
+ * Bbar_d the mean of both elements' B_d and alpha the larger fastest wave speed (acoustic sqrt(K/rho),
+ * elastic sqrt((lambda + 2 mu)/rho), generic max_d ||A_d + B_d||_inf). Node k receives
+ * dt l_{k_d}(face) / (h w_{k_d}) C at its face node (Gauss-Legendre collocation, diagonal mass matrix).
+ * Elements e = (iz * ny + iy) * nx + ix, uniform size h, periodic in x, y and z; layouts as in stp_batch,
+ * contiguous (element e at e * size). Stability of the full step needs dt <= about 0.2 h / ((2N+1) c_max). */
+typedef struct {
+    int nx, ny, nz;       /* elements per direction (nx * ny * nz <= 2^31 - 1)                               */
+    double dt, h;         /* time step (>= 0) and element size (> 0)                                          */
+    const void* Q;        /* q(t_n) [e][n^3][m]                                                               */
+    const void* params;   /* presets: [e][np] (the class must have STP_PARAM_PER_ELEMENT)                    */
+    const void* A;        /* generic: [e][d][m][m] (STP_COEF_PER_ELEMENT); NULL without STP_A_PRESENT         */
+    const void* B;        /* generic: [e][d][m][m]                                                            */
+    const void* favg;     /* stp_run outputs of the same elements with the same dt and h                      */
+    const void* qface;
+    const void* fface;    /* with STP_A_PRESENT only                                                          */
+    void* Qnew;           /* q(t_{n+1}) [e][n^3][m]; must not alias Q, favg or qface                          */
+} stp_step;
+
+/* Queue the corrector of one step on `hip_stream`. Needs a single-class plan with per-element coefficients
+ * and no point source (STP_E_UNSUPPORTED otherwise); STP_E_INVAL for NULL or aliasing buffers, a mesh
+ * dimension < 1, h <= 0 or dt < 0. I/O precision as the plan's (double for STP_FP64, else float). */
+stp_status stp_correct(stp_plan_t plan, const stp_step* step, void* hip_stream);
+
 /* Describe the plan's choices as a JSON object into buf (NUL-terminated): per class the kernel variant,
  * whether it is tiled in the persistent heterogeneous launch and its elements per tile, FP64 accumulation;
  * the persistent grid per CU and the tile LDS budget. STP_E_INVAL for a NULL plan or buffer, or when len

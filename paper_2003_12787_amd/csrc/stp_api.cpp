@@ -38,19 +38,6 @@ stp_status hip_fail(hipError_t e, const char* what)
 
 namespace {
 
-struct DeviceGuard {
-    int prev = -1;
-    bool changed = false;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) changed = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard()
-    {
-        if (changed && prev >= 0) (void)hipSetDevice(prev);
-    }
-};
 
 int quantities_read(const stp_class& c, int d)
 {
@@ -152,6 +139,7 @@ stp_status build_class(stp_plan_s* p, ClassState& cs)
         if ((st = upload(D, n * n, &cs.dD)) != STP_OK) return st;
         if ((st = upload(e0, n, &cs.de0)) != STP_OK) return st;
         if ((st = upload(e1, n, &cs.de1)) != STP_OK) return st;
+        if ((st = upload(w, n, &cs.dw)) != STP_OK) return st;
     } else {
         float Df[kMaxNodes * kMaxNodes], e0f[kMaxNodes], e1f[kMaxNodes];
         derivative_matrix_f32(n, D, Df);
@@ -162,6 +150,9 @@ stp_status build_class(stp_plan_s* p, ClassState& cs)
         if ((st = upload(Df, n * n, &cs.dD)) != STP_OK) return st;
         if ((st = upload(e0f, n, &cs.de0)) != STP_OK) return st;
         if ((st = upload(e1f, n, &cs.de1)) != STP_OK) return st;
+        float wf[kMaxNodes];
+        for (int i = 0; i < n; ++i) wf[i] = (float)w[i];
+        if ((st = upload(wf, n, &cs.dw)) != STP_OK) return st;
         // FP64 face vectors for classes that accumulate in FP64
         if ((st = upload(e0, n, &cs.de0_64)) != STP_OK) return st;
         if ((st = upload(e1, n, &cs.de1_64)) != STP_OK) return st;
@@ -241,7 +232,7 @@ stp_status build_class(stp_plan_s* p, ClassState& cs)
 void free_plan_memory(stp_plan_s* p)
 {
     for (auto& cs : p->classes) {
-        for (void* q : {cs.dD, cs.de0, cs.de1, cs.de0_64, cs.de1_64, cs.dDsplit, cs.daux})
+        for (void* q : {cs.dD, cs.de0, cs.de1, cs.de0_64, cs.de1_64, cs.dDsplit, cs.daux, cs.dw})
             if (q) (void)hipFree(q);
     }
     for (void* q : {p->d_hcls, (void*)p->d_slots, (void*)p->d_orders, (void*)p->d_bncls})

@@ -1,0 +1,260 @@
+// stp_correct.hip -- the corrector of the ADER-DG step (Sec. II-A, Eq. (5)) on a periodic Cartesian mesh.
+//
+// Given q(t_n) and the predictor's outputs of every element (time-averaged volume term favg[d] = V_d(q-bar),
+// face projections of q-bar and of A_d q-bar), the corrector adds the time integral of the volume term and
+// of the face terms. The numerical flux is a linear Rusanov flux in fluctuation form: at the face f of an
+// element with outward normal s e_d (s = -1 lower, +1 upper), with q- / F- the element's own face values and
+// q+ / F+ the neighbour's values on the same face,
+//     C_f = 1/2 alpha (q+ - q-) - 1/2 s (F+ - F-) - 1/2 s Bbar_d (q+ - q-),
+// Bbar_d the mean of the two elements' B_d and alpha the larger of their fastest wave speeds (acoustic
+// sqrt(K/rho), elastic sqrt((lambda + 2 mu)/rho), generic max_d ||A_d + B_d||_inf). With Gauss-Legendre
+// collocation and the diagonal mass matrix the node k of the element receives
+//     q(t_{n+1})_k = q(t_n)_k + dt sum_d favg[d]_k + dt sum_f l_{k_d}(x_f) / (h w_{k_d}) C_f(face node of k).
+// One workgroup per element: the face corrections of all six faces go to LDS, then every node is updated.
+// Coefficients are per element (presets: rho, K or rho, lambda, mu; generic: A_d, B_d [3][m][m]).
+#include <algorithm>
+#include <cmath>
+
+#include "stp_plan.hpp"
+
+namespace stp {
+
+namespace {
+
+constexpr int kCorrThreads = 256;
+constexpr int kCorrMaxM = 16;
+
+struct CorrArgs {
+    int nx, ny, nz;
+    int N, m, physics, favg_sum, hasA;
+    double dt, h;
+    const void* Q;
+    const void* coef;  // presets: params [e][np]; generic: B [e][3][m][m]
+    const void* A;     // generic with A: [e][3][m][m]
+    const void* favg;
+    const void* qface;
+    const void* fface;
+    void* Qnew;
+    const void* e0;  // face vectors l_j(0), l_j(1) and quadrature weights on [0, 1] (compute precision)
+    const void* e1;
+    const void* w;
+};
+
+__device__ inline int64_t neighbour_of(const CorrArgs& a, int64_t e, int d, int s)
+{
+    int64_t ix = e % a.nx, iy = (e / a.nx) % a.ny, iz = e / ((int64_t)a.nx * a.ny);
+    if (d == 0) ix = (ix + s + a.nx) % a.nx;
+    else if (d == 1) iy = (iy + s + a.ny) % a.ny;
+    else iz = (iz + s + a.nz) % a.nz;
+    return (iz * a.ny + iy) * a.nx + ix;
+}
+
+// Dense B_d (m x m, row-major) of a preset from its material: the matrices of the volume operator.
+template <typename T>
+__device__ void preset_Bd(int physics, int d, const T* par, T* B, int m)
+{
+    for (int i = 0; i < m * m; ++i) B[i] = 0;
+    if (physics == kAcoustic) {
+        B[0 * 4 + (1 + d)] = par[1];             // p <- K d_d v_d
+        B[(1 + d) * 4 + 0] = (T)1 / par[0];      // v_d <- d_d p / rho
+    } else {
+        const T irho = (T)1 / par[0], lam = par[1], mu = par[2];
+        auto sig = [](int i, int j) { return i == j ? 3 + i : (i + j == 1 ? 6 : (i + j == 3 ? 7 : 8)); };
+        for (int i = 0; i < 3; ++i) B[i * 9 + sig(i, d)] = -irho;                       // v_i <- d_d s_id
+        for (int i = 0; i < 3; ++i) B[(3 + i) * 9 + d] = i == d ? -(lam + 2 * mu) : -lam;  // s_ii <- d_d v_d
+        for (int i = 0; i < 3; ++i)
+            if (i != d) B[sig(d, i) * 9 + i] = -mu;                                     // s_di <- d_d v_i
+    }
+}
+
+template <typename T>
+__device__ T wave_speed(const CorrArgs& a, int64_t e)
+{
+    if (a.physics == kAcoustic) {
+        const T* p = static_cast<const T*>(a.coef) + e * 2;
+        return sqrt(p[1] / p[0]);
+    }
+    if (a.physics == kElastic) {
+        const T* p = static_cast<const T*>(a.coef) + e * 3;
+        return sqrt((p[1] + 2 * p[2]) / p[0]);
+    }
+    const int m = a.m;
+    const T* B = static_cast<const T*>(a.coef) + e * 3 * m * m;
+    const T* A = a.hasA ? static_cast<const T*>(a.A) + e * 3 * m * m : nullptr;
+    T best = 0;
+    for (int d = 0; d < 3; ++d)
+        for (int r = 0; r < m; ++r) {
+            T row = 0;
+            for (int c = 0; c < m; ++c) row += fabs(B[(d * m + r) * m + c] + (A ? A[(d * m + r) * m + c] : T(0)));
+            best = row > best ? row : best;
+        }
+    return best;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kCorrThreads) stp_correct_kernel(CorrArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = a.N + 1, n2 = n * n, n3 = n2 * n, m = a.m;
+    T* Bbar = reinterpret_cast<T*>(smem);  // [6][m][m] mean B_d of the element and its neighbour per face
+    T* Cf = Bbar + 6 * m * m;              // [6][n^2][m] face corrections
+    T* alpha = Cf + 6 * n2 * m;            // [6]
+    T* lift0 = alpha + 8;                  // [n] l_j(0) / (h w_j)
+    T* lift1 = lift0 + n;                  // [n] l_j(1) / (h w_j)
+    const int64_t nelem = (int64_t)a.nx * a.ny * a.nz;
+    for (int64_t e = blockIdx.x; e < nelem; e += gridDim.x) {
+        const int tid = threadIdx.x;
+        // per-face mean coefficients and Rusanov speeds
+        if (tid < 6) {
+            const int d = tid >> 1, s = (tid & 1) ? 1 : -1;
+            const int64_t nb = neighbour_of(a, e, d, s);
+            T* Bf = Bbar + tid * m * m;
+            if (a.physics == kGeneric) {
+                const T* B0 = static_cast<const T*>(a.coef) + (e * 3 + d) * m * m;
+                const T* B1 = static_cast<const T*>(a.coef) + (nb * 3 + d) * m * m;
+                for (int i = 0; i < m * m; ++i) Bf[i] = (T)0.5 * (B0[i] + B1[i]);
+            } else {
+                const int np = a.physics == kAcoustic ? 2 : 3;
+                const T* p0 = static_cast<const T*>(a.coef) + e * np;
+                const T* p1 = static_cast<const T*>(a.coef) + nb * np;
+                T B0[81], B1[81];
+                preset_Bd<T>(a.physics, d, p0, B0, m);
+                preset_Bd<T>(a.physics, d, p1, B1, m);
+                for (int i = 0; i < m * m; ++i) Bf[i] = (T)0.5 * (B0[i] + B1[i]);
+            }
+            const T a0 = wave_speed<T>(a, e), a1 = wave_speed<T>(a, nb);
+            alpha[tid] = a0 > a1 ? a0 : a1;
+        }
+        if (tid < n) {
+            const T* w = static_cast<const T*>(a.w);
+            lift0[tid] = static_cast<const T*>(a.e0)[tid] / ((T)a.h * w[tid]);
+            lift1[tid] = static_cast<const T*>(a.e1)[tid] / ((T)a.h * w[tid]);
+        }
+        __syncthreads();
+        // face corrections: one face point (all quantities) per work item
+        const T* qf = static_cast<const T*>(a.qface);
+        const T* ff = static_cast<const T*>(a.fface);
+        for (int it = tid; it < 6 * n2; it += kCorrThreads) {
+            const int f = it / n2, pt = it - f * n2, d = f >> 1, side = f & 1;
+            const T s = side ? T(1) : T(-1);
+            const int64_t nb = neighbour_of(a, e, d, side ? 1 : -1);
+            const int fo = 2 * d + (1 - side);
+            const T* qm = qf + ((e * 6 + f) * n2 + pt) * m;
+            const T* qp = qf + ((nb * 6 + fo) * n2 + pt) * m;
+            T jump[kCorrMaxM];
+            for (int r = 0; r < m; ++r) jump[r] = qp[r] - qm[r];
+            const T* Bf = Bbar + f * m * m;
+            const T al = alpha[f];
+            for (int r = 0; r < m; ++r) {
+                T bj = 0;
+                for (int c = 0; c < m; ++c) bj = fma(Bf[r * m + c], jump[c], bj);
+                T v = (T)0.5 * al * jump[r] - (T)0.5 * s * bj;
+                if (a.hasA) {
+                    const T Fm = ff[((e * 6 + f) * n2 + pt) * m + r];
+                    const T Fp = ff[((nb * 6 + fo) * n2 + pt) * m + r];
+                    v -= (T)0.5 * s * (Fp - Fm);
+                }
+                Cf[(f * n2 + pt) * m + r] = v;
+            }
+        }
+        __syncthreads();
+        // node updates
+        const T dt = (T)a.dt;
+        const T* Q = static_cast<const T*>(a.Q) + e * n3 * m;
+        const T* fa = static_cast<const T*>(a.favg) + (a.favg_sum ? e * n3 * m : e * 3 * n3 * m);
+        T* out = static_cast<T*>(a.Qnew) + e * n3 * m;
+        for (int it = tid; it < n3 * m; it += kCorrThreads) {
+            const int r = it % m, k = it / m;
+            const int kx = k % n, ky = (k / n) % n, kz = k / n2;
+            T vol = fa[it];
+            if (!a.favg_sum) vol += fa[n3 * m + it] + fa[2 * n3 * m + it];
+            T face = lift0[kx] * Cf[((0 * n2) + kz * n + ky) * m + r] + lift1[kx] * Cf[((1 * n2) + kz * n + ky) * m + r];
+            face += lift0[ky] * Cf[((2 * n2) + kz * n + kx) * m + r] + lift1[ky] * Cf[((3 * n2) + kz * n + kx) * m + r];
+            face += lift0[kz] * Cf[((4 * n2) + ky * n + kx) * m + r] + lift1[kz] * Cf[((5 * n2) + ky * n + kx) * m + r];
+            out[it] = Q[it] + dt * (vol + face);
+        }
+        __syncthreads();
+    }
+}
+
+size_t corr_lds(int N, int m, size_t io)
+{
+    const int n = N + 1;
+    return io * (size_t)(6 * m * m + 6 * n * n * m + 8 + 2 * n);
+}
+
+}  // namespace
+
+}  // namespace stp
+
+using namespace stp;
+
+extern "C" stp_status stp_correct(stp_plan_t p, const stp_step* st, void* stream)
+{
+    if (!p) return fail(STP_E_INVAL, "plan is NULL");
+    if (!st) return fail(STP_E_INVAL, "step is NULL");
+    if (p->classes.size() != 1) return fail(STP_E_UNSUPPORTED, "the corrector takes a single-class plan");
+    const ClassState& cs = p->classes[0];
+    const stp_class& c = cs.cls;
+    const bool generic = c.physics == STP_GENERIC;
+    if (generic ? !(c.flags & STP_COEF_PER_ELEMENT) : !(c.flags & STP_PARAM_PER_ELEMENT))
+        return fail(STP_E_UNSUPPORTED, "the corrector needs per-element coefficients (STP_PARAM_PER_ELEMENT or "
+                                       "STP_COEF_PER_ELEMENT)");
+    if (c.flags & STP_SRC_POINT) return fail(STP_E_UNSUPPORTED, "point sources are not supported by the corrector");
+    if (st->nx < 1 || st->ny < 1 || st->nz < 1) return fail(STP_E_INVAL, "mesh %d x %d x %d", st->nx, st->ny, st->nz);
+    if ((int64_t)st->nx * st->ny * st->nz > (int64_t)INT32_MAX) return fail(STP_E_INVAL, "mesh too large");
+    if (!(st->h > 0) || !std::isfinite(st->h)) return fail(STP_E_INVAL, "h must be > 0 (got %g)", st->h);
+    if (!(st->dt >= 0) || !std::isfinite(st->dt)) return fail(STP_E_INVAL, "dt must be >= 0 (got %g)", st->dt);
+    const bool hasA = generic && (c.flags & STP_A_PRESENT);
+    if (!st->Q || !st->favg || !st->qface || !st->Qnew) return fail(STP_E_INVAL, "Q / favg / qface / Qnew is NULL");
+    if (generic ? !st->B : !st->params) return fail(STP_E_INVAL, "coefficients are NULL");
+    if (hasA && (!st->A || !st->fface)) return fail(STP_E_INVAL, "A / fface is NULL for a class with A present");
+    const int64_t E = (int64_t)st->nx * st->ny * st->nz;
+    const size_t io = p->prec == STP_FP64 ? 8 : 4;
+    {
+        const uintptr_t o0 = (uintptr_t)st->Qnew, o1 = o0 + (size_t)E * cs.size_q * io;
+        const size_t fmul = (c.flags & STP_FAVG_SUM) ? 1 : 3;
+        struct R { const void* q; size_t bytes; const char* name; };
+        const R ins[] = {{st->Q, (size_t)E * cs.size_q * io, "Q"}, {st->favg, (size_t)E * fmul * cs.size_q * io, "favg"},
+                         {st->qface, (size_t)E * cs.size_face * io, "qface"}};
+        for (const R& r : ins) {
+            const uintptr_t a0 = (uintptr_t)r.q, a1 = a0 + r.bytes;
+            if (a0 < o1 && o0 < a1) return fail(STP_E_INVAL, "Qnew aliases %s", r.name);
+        }
+    }
+    if (E == 0) return STP_OK;
+    CorrArgs a{};
+    a.nx = st->nx;
+    a.ny = st->ny;
+    a.nz = st->nz;
+    a.N = c.order;
+    a.m = c.nquant;
+    a.physics = c.physics;
+    a.favg_sum = (c.flags & STP_FAVG_SUM) ? 1 : 0;
+    a.hasA = hasA ? 1 : 0;
+    a.dt = st->dt;
+    a.h = st->h;
+    a.Q = st->Q;
+    a.coef = generic ? st->B : st->params;
+    a.A = st->A;
+    a.favg = st->favg;
+    a.qface = st->qface;
+    a.fface = st->fface;
+    a.Qnew = st->Qnew;
+    a.e0 = cs.de0;
+    a.e1 = cs.de1;
+    a.w = cs.dw;
+    const size_t lds = corr_lds(c.order, c.nquant, io);
+    const void* fn = p->prec == STP_FP64 ? reinterpret_cast<const void*>(&stp_correct_kernel<double>)
+                                         : reinterpret_cast<const void*>(&stp_correct_kernel<float>);
+    DeviceGuard g(p->device);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(corrector LDS)");
+    }
+    const unsigned grid = (unsigned)std::min<int64_t>(E, (int64_t)p->num_cus * 16);
+    void* args[] = {&a};
+    hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kCorrThreads), args, lds, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "hipLaunchKernel(corrector)");
+    return STP_OK;
+}

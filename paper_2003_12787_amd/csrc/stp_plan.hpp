@@ -31,6 +31,7 @@ struct ClassState {
     void* de1_64 = nullptr;
     void* dDsplit = nullptr; // BF16 hi/lo tables (split-BF16x3 variant)
     void* daux = nullptr;    // even/odd derivative tables in the compute precision (fused variant)
+    void* dw = nullptr;      // Gauss-Legendre weights on [0, 1] in the compute precision (corrector)
     bool acc64 = false;      // FP64 accumulation of q-bar and faces
     KernelInfo kernel;
     int variant = 0;                               // STP_VARIANT_* of `kernel`
@@ -96,6 +97,21 @@ struct stp_plan_s {
 };
 
 namespace stp {
+
+// Makes the plan's device current for the scope (restores the previous one if it changed).
+struct DeviceGuard {
+    int prev = -1;
+    bool changed = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) changed = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (changed && prev >= 0) (void)hipSetDevice(prev);
+    }
+};
 
 stp_status fail(stp_status st, const char* fmt, ...);
 stp_status hip_fail(hipError_t e, const char* what);

@@ -23,7 +23,7 @@ VARIANT_AUTO, VARIANT_PLAIN, VARIANT_FUSED, VARIANT_MFMA = 0, 1, 2, 3
 
 # Exported symbols declared in include/stp.h.
 SYMBOLS = ("stp_plan", "stp_plan_free", "stp_run", "stp_reserve", "stp_submit", "stp_poll", "stp_drain",
-           "stp_class_cost", "stp_plan_describe", "stp_last_error")
+           "stp_class_cost", "stp_correct", "stp_plan_describe", "stp_last_error")
 
 
 class StpError(RuntimeError):
@@ -48,6 +48,12 @@ class Batch(C.Structure):
                 ("dt_h_scalar", C.c_int), ("Q", C.c_void_p), ("params", C.c_void_p), ("A", C.c_void_p),
                 ("B", C.c_void_p), ("src", C.c_void_p), ("qavg", C.c_void_p), ("favg", C.c_void_p),
                 ("qface", C.c_void_p), ("fface", C.c_void_p)]
+
+
+class Step(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("dt", C.c_double), ("h", C.c_double),
+                ("Q", C.c_void_p), ("params", C.c_void_p), ("A", C.c_void_p), ("B", C.c_void_p),
+                ("favg", C.c_void_p), ("qface", C.c_void_p), ("fface", C.c_void_p), ("Qnew", C.c_void_p)]
 
 
 class TicketInfo(C.Structure):
@@ -79,10 +85,11 @@ def lib():
         L.stp_class_cost.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.stp_reserve.argtypes = [C.c_void_p, C.c_int64]
         L.stp_plan_describe.argtypes = [C.c_void_p, C.c_char_p, C.c_size_t]
+        L.stp_correct.argtypes = [C.c_void_p, C.POINTER(Step), C.c_void_p]
         L.stp_last_error.argtypes = []
         L.stp_last_error.restype = C.c_char_p
         for f in ("stp_plan", "stp_run", "stp_reserve", "stp_submit", "stp_poll", "stp_drain", "stp_class_cost",
-                  "stp_plan_describe"):
+                  "stp_plan_describe", "stp_correct"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -181,6 +188,21 @@ class Plan:
     def run_status(self, batch, stream=0):
         """stp_run returning the raw status (for error-path tests)."""
         return lib().stp_run(self.handle, C.byref(batch), C.c_void_p(stream))
+
+    def correct(self, grid, dt, h, Q, favg, qface, Qnew, params=None, A=None, B=None, fface=None, stream=None):
+        """Queue the corrector step on a periodic nx x ny x nz mesh (stp_correct); tensors are device tensors."""
+        st = Step(int(grid[0]), int(grid[1]), int(grid[2]), float(dt), float(h), _ptr(Q), _ptr(params), _ptr(A),
+                  _ptr(B), _ptr(favg), _ptr(qface), _ptr(fface), _ptr(Qnew))
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        elif hasattr(stream, "cuda_stream"):
+            stream = stream.cuda_stream
+        return _check(lib().stp_correct(self.handle, C.byref(st), C.c_void_p(stream)))
+
+    def correct_status(self, step, stream=0):
+        """stp_correct returning the raw status (for error-path tests)."""
+        return lib().stp_correct(self.handle, C.byref(step), C.c_void_p(stream))
 
     def submit(self, batch):
         t = C.c_uint64()

@@ -1,0 +1,175 @@
+"""GPU parity of the corrector (stp_correct) and of full ADER-DG steps (stp_run + stp_correct) against the
+oracle on periodic Cartesian meshes, plus end-to-end plane-wave convergence on the GPU."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import corrector as OC
+from paper_2003_12787_amd import stp
+from paper_2003_12787_amd import workloads as W
+from parity import TOL
+
+pytestmark = pytest.mark.gpu
+
+ACOUSTIC, ELASTIC, GENERIC = 0, 1, 2
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build()
+    return torch
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel(x, y):
+    return float(np.abs(x - y).max() / max(np.abs(y).max(), 1e-300))
+
+
+def mesh_inputs(physics, N, grid, seed, m=None, with_A=False):
+    rng = np.random.default_rng(seed)
+    E = grid[0] * grid[1] * grid[2]
+    n3 = (N + 1) ** 3
+    if physics == ELASTIC:
+        params, A, B, m = W.elastic_material(rng, (E,)), None, None, 9
+    elif physics == ACOUSTIC:
+        params, A, B, m = np.stack([rng.uniform(2, 3, E), rng.uniform(1, 2, E)], axis=1), None, None, 4
+    else:
+        params = None
+        B = rng.standard_normal((E, 3, m, m)) / np.sqrt(m)
+        A = rng.standard_normal((E, 3, m, m)) / np.sqrt(m) if with_A else None
+    Q = rng.standard_normal((E, n3, m))
+    return Q, params, A, B, m
+
+
+def flags_of(physics, with_A):
+    if physics == GENERIC:
+        return stp.COEF_PER_ELEMENT | (stp.A_PRESENT if with_A else 0)
+    return stp.PARAM_PER_ELEMENT
+
+
+def gpu_step(plan, prec, physics, N, grid, Q, params, A, B, dt, h, with_A, torch):
+    """stp_run then stp_correct on the device; returns (q_new, predictor outputs) as host arrays."""
+    tdt = torch.float64 if prec == stp.FP64 else torch.float32
+    up = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to("cuda", tdt)
+    E, n3, m = Q.shape
+    n2 = (N + 1) ** 2
+    dQ, dpar, dA, dB = up(Q), up(params), up(A), up(B)
+    qavg = torch.empty((E, n3, m), device="cuda", dtype=tdt)
+    favg = torch.empty((E, 3, n3, m), device="cuda", dtype=tdt)
+    qface = torch.empty((E, 6, n2, m), device="cuda", dtype=tdt)
+    fface = torch.empty((E, 6, n2, m), device="cuda", dtype=tdt) if with_A else None
+    Qn = torch.empty_like(dQ)
+    plan.run(plan.batch(E, dQ, qavg, favg, qface, dt, h, params=dpar, A=dA, B=dB, fface=fface))
+    plan.correct(grid, dt, h, dQ, favg, qface, Qn, params=dpar, A=dA, B=dB, fface=fface)
+    torch.cuda.synchronize()
+    return Qn.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("physics,N,prec,with_A", [(ELASTIC, 3, stp.FP64, False), (ELASTIC, 3, stp.FP32, False),
+                                                   (ACOUSTIC, 5, stp.FP64, False), (GENERIC, 2, stp.FP64, True),
+                                                   (GENERIC, 4, stp.FP32, True)])
+def test_corrector_matches_oracle_on_oracle_predictor_outputs(physics, N, prec, with_A, gpu):
+    """stp_correct alone, fed with the oracle predictor's outputs (rounded to the I/O precision)."""
+    torch = gpu
+    grid = (4, 3, 2)
+    Q, params, A, B, m = mesh_inputs(physics, N, grid, 11 + N, m=3, with_A=with_A)
+    h, dt = 0.5, 0.01
+    rnd = (lambda a: a) if prec == stp.FP64 else (lambda a: None if a is None else a.astype(np.float32).astype(np.float64))
+    Q, params, A, B = rnd(Q), rnd(params), rnd(A), rnd(B)
+    pred = oracle.stp(N, physics, Q, dt, h, params=params, A=A, B=B, coef_per_element=True)
+    favg, qface, fface = rnd(pred["favg"]), rnd(pred["qface"]), rnd(pred.get("fface"))
+    ref = OC.correct(N, physics, grid, Q, favg, qface, dt, h, params=params, A=A, B=B, fface=fface)
+    say(f"[corrector] physics={physics} N={N} m={m} prec={prec} A={with_A} mesh={grid}")
+    plan = stp.Plan([(N, m, physics, flags_of(physics, with_A))], prec=prec)
+    tdt = torch.float64 if prec == stp.FP64 else torch.float32
+    up = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to("cuda", tdt)
+    Qn = torch.empty(Q.shape, device="cuda", dtype=tdt)
+    plan.correct(grid, dt, h, up(Q), up(favg), up(qface), Qn, params=up(params), A=up(A), B=up(B), fface=up(fface))
+    torch.cuda.synchronize()
+    got = Qn.double().cpu().numpy()
+    err = rel(got, ref)
+    say(f"[corrector]   max rel err {err:.2e}")
+    assert err < TOL[prec], err
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", [stp.FP64, stp.FP32])
+def test_full_steps_match_oracle(prec, gpu):
+    """Three ADER-DG steps (predictor + corrector on the GPU) against the oracle's steps."""
+    torch = gpu
+    N, grid = 3, (3, 2, 2)
+    Q, params, _, _, m = mesh_inputs(ELASTIC, N, grid, 21)
+    if prec != stp.FP64:
+        Q, params = Q.astype(np.float32).astype(np.float64), params.astype(np.float32).astype(np.float64)
+    h = 0.5
+    dt = 0.2 * h / ((2 * N + 1) * np.sqrt((params[:, 1] + 2 * params[:, 2]) / params[:, 0]).max())
+    plan = stp.Plan([(N, m, ELASTIC, stp.PARAM_PER_ELEMENT)], prec=prec)
+    qg, qo = Q.copy(), Q.copy()
+    for k in range(3):
+        qg = gpu_step(plan, prec, ELASTIC, N, grid, qg, params, None, None, dt, h, False, torch)
+        qo = OC.ader_step(N, ELASTIC, grid, qo, dt, h, params=params)
+        err = rel(qg, qo)
+        say(f"[full step] prec={prec} step {k}: max rel err {err:.2e}")
+        assert err < 3 * TOL[prec], err
+    plan.close()
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_gpu_plane_wave_converges(N, gpu):
+    """End to end on the GPU (FP64): an acoustic plane wave along x converges at order N + 1."""
+    torch = gpu
+    rho, K = 1.0, 2.25
+    c = np.sqrt(K / rho)
+    errs = []
+    plan = stp.Plan([(N, 4, ACOUSTIC, stp.PARAM_PER_ELEMENT)], prec=stp.FP64)
+    for nx in (8, 16):
+        h = 1.0 / nx
+        xi, _ = oracle.gl_nodes(N + 1)
+        n = N + 1
+        x = np.zeros((nx, n, n, n))
+        for e in range(nx):
+            x[e] = (e + xi)[None, None, :] * h
+        x = x.reshape(nx, n ** 3)
+        f = lambda t: np.sin(2 * np.pi * (x - c * t))
+        Q = np.zeros((nx, n ** 3, 4))
+        Q[..., 0] = f(0.0)
+        Q[..., 1] = f(0.0) / (rho * c)
+        params = np.tile([rho, K], (nx, 1))
+        T = 0.2
+        steps = int(np.ceil(T / (0.2 * h / ((2 * N + 1) * c))))
+        dt = T / steps
+        for _ in range(steps):
+            Q = gpu_step(plan, stp.FP64, ACOUSTIC, N, (nx, 1, 1), Q, params, None, None, dt, h, False, torch)
+        errs.append(max(np.abs(Q[..., 0] - f(T)).max(), np.abs(Q[..., 1] - f(T) / (rho * c)).max()))
+    rate = np.log2(errs[0] / errs[1])
+    say(f"[convergence] N={N} errors {errs} rate {rate:.2f}")
+    assert rate > N + 1 - 0.25, (errs, rate)
+    plan.close()
+
+
+def test_corrector_validation(gpu):
+    torch = gpu
+    plan = stp.Plan([(3, 9, ELASTIC, 0)], prec=stp.FP32)  # per-node material: not supported by the corrector
+    z = torch.zeros(64 * 9 * 8, device="cuda")
+    st = stp.Step(2, 2, 2, 0.01, 0.5, z.data_ptr(), z.data_ptr(), None, None, z.data_ptr(), z.data_ptr(), None,
+                  z.data_ptr())
+    assert plan.correct_status(st) == stp.E_UNSUPPORTED
+    plan.close()
+    plan = stp.Plan([(3, 9, ELASTIC, stp.PARAM_PER_ELEMENT)], prec=stp.FP32)
+    assert plan.correct_status(st) == stp.E_INVAL and "alias" in stp.last_error()
+    out = torch.zeros(8 * 64 * 9, device="cuda")
+    st.Qnew = out.data_ptr()
+    st.h = 0.0
+    assert plan.correct_status(st) == stp.E_INVAL
+    st.h, st.nx = 0.5, 0
+    assert plan.correct_status(st) == stp.E_INVAL
+    plan.close()
+    torch.cuda.synchronize()
