@@ -151,6 +151,52 @@ def bench_acoustic(args, torch, stp, W, runner):
     return out
 
 
+def bench_full_step(args, torch, stp, W):
+    """A full ADER-DG step on a periodic 64 x 32 x 32 mesh (65536 elements): elastic N = 7, per-element
+    material, the split-BF16x3 predictor (stp_run) then the corrector (stp_correct), FP32."""
+    nx, ny, nz = 64, 32, 32
+    E, N, m = nx * ny * nz, 7, 9
+    n3, n2 = (N + 1) ** 3, (N + 1) ** 2
+    log(f"[bench] full step: {nx} x {ny} x {nz} mesh, elastic N=7, per-element material")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(W.SEED0 + 60)
+    Q = torch.randn(E * n3 * m, generator=g, device="cuda")
+    u = torch.rand(E, 3, generator=g, device="cuda")
+    par = (torch.tensor([2.0, 1.0, 1.0], device="cuda") + torch.tensor([1.0, 3.0, 2.0], device="cuda") * u).reshape(-1)
+    h = 1.0 / nx
+    dt = 0.2 * h / ((2 * N + 1) * W.C_MAX[W.ELASTIC])
+    plan = stp.Plan([(N, m, stp.ELASTIC, stp.PARAM_PER_ELEMENT)], prec=stp.BF16X3)
+    qavg = torch.empty(E * n3 * m, device="cuda")
+    favg = torch.empty(3 * E * n3 * m, device="cuda")
+    qface = torch.empty(E * 6 * n2 * m, device="cuda")
+    Qn = torch.empty_like(Q)
+    batch = plan.batch(E, Q, qavg, favg, qface, dt, h, params=par)
+    stream = torch.cuda.Stream()
+    t_pred = time_launches(lambda st: plan.run(batch, st), args.steps, args.warmup, stream, torch)
+    t_corr = time_launches(lambda st: plan.correct((nx, ny, nz), dt, h, Q, favg, qface, Qn, params=par, stream=st),
+                           args.steps, args.warmup, stream, torch)
+
+    def step(st):
+        plan.run(batch, st)
+        plan.correct((nx, ny, nz), dt, h, Q, favg, qface, Qn, params=par, stream=st)
+
+    t_step = time_launches(step, args.steps, args.warmup, stream, torch)
+    plan.close()
+    corr_bytes = 4.0 * (5 * n3 * m + 12 * n2 * m) * E  # Q, favg x3, own and neighbours' faces read; q_new written
+    ms_c = float(np.median(t_corr))
+    res = {"workload": f"periodic {nx}x{ny}x{nz} mesh, elastic N=7, per-element material, split-BF16x3 predictor "
+                       "+ FP32 corrector", "nelem": E,
+           "ms_predictor": float(np.median(t_pred)), "ms_corrector": ms_c, "ms_step": float(np.median(t_step)),
+           "element_steps_per_s": E / (float(np.median(t_step)) * 1e-3),
+           "corrector_hbm_gbs_algorithmic": corr_bytes / (ms_c * 1e-3) / 1e9,
+           "corrector_hbm_frac": corr_bytes / (ms_c * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    log(f"[bench] full step: predictor {res['ms_predictor']:.3f} ms, corrector {ms_c:.3f} ms "
+        f"({res['corrector_hbm_gbs_algorithmic']:.0f} GB/s), step {res['ms_step']:.3f} ms")
+    del Q, qavg, favg, qface, Qn
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_hetero(args, torch, stp, W):
     """Mixed orders and quantity counts in one batch: 16384 generic elements, N ~ U{2..9}, m ~ U{4, 9},
     dense per-node B_d, FP32. Times the heterogeneous stp_run (eager and replayed from a captured HIP graph)
@@ -381,6 +427,7 @@ def main():
         copy = copy_bandwidth(args.copy_gib, torch)
 
     acoustic = None if args.no_hetero else bench_acoustic(args, torch, stp, W, runner)
+    full_step = None if args.no_hetero else bench_full_step(args, torch, stp, W)
     hetero = None if args.no_hetero else bench_hetero(args, torch, stp, W)
     serving = None if args.no_serve else bench_serving(args, torch, stp, W)
 
@@ -438,6 +485,7 @@ def main():
         "variants": results,
         "copy_reference": copy,
         "acoustic_n5": acoustic,
+        "ader_dg_step": full_step,
         "heterogeneous": hetero,
         "serving": serving,
         "latency_p50_ms": serving["load_80pct"]["p50_ms"] if serving else None,

@@ -49,21 +49,21 @@ __device__ inline int64_t neighbour_of(const CorrArgs& a, int64_t e, int d, int 
     return (iz * a.ny + iy) * a.nx + ix;
 }
 
-// Dense B_d (m x m, row-major) of a preset from its material: the matrices of the volume operator.
+// (Bbar_d j) for a preset, from the face's averaged coefficients c = (1/rho, K) or (1/rho, lambda, mu): the
+// entries of the presets' B_d are linear in these, so the mean of two elements' B_d is B_d of the means.
 template <typename T>
-__device__ void preset_Bd(int physics, int d, const T* par, T* B, int m)
+__device__ inline void preset_Bj(int physics, int d, const T* c, const T* j, T* out)
 {
-    for (int i = 0; i < m * m; ++i) B[i] = 0;
     if (physics == kAcoustic) {
-        B[0 * 4 + (1 + d)] = par[1];             // p <- K d_d v_d
-        B[(1 + d) * 4 + 0] = (T)1 / par[0];      // v_d <- d_d p / rho
+        out[0] = c[1] * j[1 + d];  // p <- K d_d v_d
+        for (int i = 0; i < 3; ++i) out[1 + i] = i == d ? c[0] * j[0] : T(0);  // v_d <- d_d p / rho
     } else {
-        const T irho = (T)1 / par[0], lam = par[1], mu = par[2];
-        auto sig = [](int i, int j) { return i == j ? 3 + i : (i + j == 1 ? 6 : (i + j == 3 ? 7 : 8)); };
-        for (int i = 0; i < 3; ++i) B[i * 9 + sig(i, d)] = -irho;                       // v_i <- d_d s_id
-        for (int i = 0; i < 3; ++i) B[(3 + i) * 9 + d] = i == d ? -(lam + 2 * mu) : -lam;  // s_ii <- d_d v_d
+        auto sig = [](int i, int k) { return i == k ? 3 + i : (i + k == 1 ? 6 : (i + k == 3 ? 7 : 8)); };
+        for (int i = 0; i < 3; ++i) out[i] = -c[0] * j[sig(i, d)];                          // v_i <- d_d s_id
+        for (int i = 0; i < 3; ++i) out[3 + i] = i == d ? -(c[1] + 2 * c[2]) * j[d] : -c[1] * j[d];  // s_ii <- v_d
+        out[6] = out[7] = out[8] = 0;
         for (int i = 0; i < 3; ++i)
-            if (i != d) B[sig(d, i) * 9 + i] = -mu;                                     // s_di <- d_d v_i
+            if (i != d) out[sig(d, i)] = -c[2] * j[i];                                       // s_di <- v_i
     }
 }
 
@@ -91,44 +91,50 @@ __device__ T wave_speed(const CorrArgs& a, int64_t e)
     return best;
 }
 
-template <typename T>
+// Instantiated per order and physics, so that the index arithmetic divides by constants (with a run-time
+// order and quantity count, integer divisions dominated the kernel).
+template <typename T, int N, int PHYS>
 __global__ void __launch_bounds__(kCorrThreads) stp_correct_kernel(CorrArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int n = a.N + 1, n2 = n * n, n3 = n2 * n, m = a.m;
-    T* Bbar = reinterpret_cast<T*>(smem);  // [6][m][m] mean B_d of the element and its neighbour per face
-    T* Cf = Bbar + 6 * m * m;              // [6][n^2][m] face corrections
+    constexpr int n = N + 1, n2 = n * n, n3 = n2 * n;
+    const int m = PHYS == kAcoustic ? 4 : (PHYS == kElastic ? 9 : a.m);
+    constexpr bool preset = PHYS != kGeneric;
+    T* Bbar = reinterpret_cast<T*>(smem);  // generic: [6][m][m] mean B_d of the element and its neighbour
+    T* cbar = Bbar + (preset ? 0 : 6 * m * m);  // presets: [6][4] mean (1/rho, K) or (1/rho, lambda, mu)
+    T* Cf = cbar + 24;                     // [6][n^2][m] face corrections
     T* alpha = Cf + 6 * n2 * m;            // [6]
     T* lift0 = alpha + 8;                  // [n] l_j(0) / (h w_j)
     T* lift1 = lift0 + n;                  // [n] l_j(1) / (h w_j)
     const int64_t nelem = (int64_t)a.nx * a.ny * a.nz;
+    const int tid = threadIdx.x;
+    if (tid < n) {
+        const T* w = static_cast<const T*>(a.w);
+        lift0[tid] = static_cast<const T*>(a.e0)[tid] / ((T)a.h * w[tid]);
+        lift1[tid] = static_cast<const T*>(a.e1)[tid] / ((T)a.h * w[tid]);
+    }
     for (int64_t e = blockIdx.x; e < nelem; e += gridDim.x) {
-        const int tid = threadIdx.x;
         // per-face mean coefficients and Rusanov speeds
         if (tid < 6) {
             const int d = tid >> 1, s = (tid & 1) ? 1 : -1;
             const int64_t nb = neighbour_of(a, e, d, s);
-            T* Bf = Bbar + tid * m * m;
-            if (a.physics == kGeneric) {
-                const T* B0 = static_cast<const T*>(a.coef) + (e * 3 + d) * m * m;
-                const T* B1 = static_cast<const T*>(a.coef) + (nb * 3 + d) * m * m;
-                for (int i = 0; i < m * m; ++i) Bf[i] = (T)0.5 * (B0[i] + B1[i]);
-            } else {
-                const int np = a.physics == kAcoustic ? 2 : 3;
+            if constexpr (preset) {
+                const int np = PHYS == kAcoustic ? 2 : 3;
                 const T* p0 = static_cast<const T*>(a.coef) + e * np;
                 const T* p1 = static_cast<const T*>(a.coef) + nb * np;
-                T B0[81], B1[81];
-                preset_Bd<T>(a.physics, d, p0, B0, m);
-                preset_Bd<T>(a.physics, d, p1, B1, m);
-                for (int i = 0; i < m * m; ++i) Bf[i] = (T)0.5 * (B0[i] + B1[i]);
+                cbar[tid * 4 + 0] = (T)0.5 * ((T)1 / p0[0] + (T)1 / p1[0]);
+                for (int i = 1; i < np; ++i) cbar[tid * 4 + i] = (T)0.5 * (p0[i] + p1[i]);
             }
             const T a0 = wave_speed<T>(a, e), a1 = wave_speed<T>(a, nb);
             alpha[tid] = a0 > a1 ? a0 : a1;
         }
-        if (tid < n) {
-            const T* w = static_cast<const T*>(a.w);
-            lift0[tid] = static_cast<const T*>(a.e0)[tid] / ((T)a.h * w[tid]);
-            lift1[tid] = static_cast<const T*>(a.e1)[tid] / ((T)a.h * w[tid]);
+        if constexpr (!preset) {
+            for (int i = tid; i < 6 * m * m; i += kCorrThreads) {
+                const int f = i / (m * m), r = i - f * m * m, d = f >> 1;
+                const int64_t nb = neighbour_of(a, e, d, (f & 1) ? 1 : -1);
+                const T* B = static_cast<const T*>(a.coef);
+                Bbar[i] = (T)0.5 * (B[(e * 3 + d) * m * m + r] + B[(nb * 3 + d) * m * m + r]);
+            }
         }
         __syncthreads();
         // face corrections: one face point (all quantities) per work item
@@ -141,14 +147,21 @@ __global__ void __launch_bounds__(kCorrThreads) stp_correct_kernel(CorrArgs a)
             const int fo = 2 * d + (1 - side);
             const T* qm = qf + ((e * 6 + f) * n2 + pt) * m;
             const T* qp = qf + ((nb * 6 + fo) * n2 + pt) * m;
-            T jump[kCorrMaxM];
+            T jump[kCorrMaxM], bj[kCorrMaxM];
             for (int r = 0; r < m; ++r) jump[r] = qp[r] - qm[r];
-            const T* Bf = Bbar + f * m * m;
+            if constexpr (preset) {
+                preset_Bj<T>(PHYS, d, cbar + f * 4, jump, bj);
+            } else {
+                const T* Bf = Bbar + f * m * m;
+                for (int r = 0; r < m; ++r) {
+                    T acc = 0;
+                    for (int c = 0; c < m; ++c) acc = fma(Bf[r * m + c], jump[c], acc);
+                    bj[r] = acc;
+                }
+            }
             const T al = alpha[f];
             for (int r = 0; r < m; ++r) {
-                T bj = 0;
-                for (int c = 0; c < m; ++c) bj = fma(Bf[r * m + c], jump[c], bj);
-                T v = (T)0.5 * al * jump[r] - (T)0.5 * s * bj;
+                T v = (T)0.5 * al * jump[r] - (T)0.5 * s * bj[r];
                 if (a.hasA) {
                     const T Fm = ff[((e * 6 + f) * n2 + pt) * m + r];
                     const T Fp = ff[((nb * 6 + fo) * n2 + pt) * m + r];
@@ -177,10 +190,34 @@ __global__ void __launch_bounds__(kCorrThreads) stp_correct_kernel(CorrArgs a)
     }
 }
 
+template <typename T, int PHYS>
+const void* corr_kernel_by_order(int N)
+{
+    switch (N) {
+    case 1: return reinterpret_cast<const void*>(&stp_correct_kernel<T, 1, PHYS>);
+    case 2: return reinterpret_cast<const void*>(&stp_correct_kernel<T, 2, PHYS>);
+    case 3: return reinterpret_cast<const void*>(&stp_correct_kernel<T, 3, PHYS>);
+    case 4: return reinterpret_cast<const void*>(&stp_correct_kernel<T, 4, PHYS>);
+    case 5: return reinterpret_cast<const void*>(&stp_correct_kernel<T, 5, PHYS>);
+    case 6: return reinterpret_cast<const void*>(&stp_correct_kernel<T, 6, PHYS>);
+    case 7: return reinterpret_cast<const void*>(&stp_correct_kernel<T, 7, PHYS>);
+    case 8: return reinterpret_cast<const void*>(&stp_correct_kernel<T, 8, PHYS>);
+    default: return reinterpret_cast<const void*>(&stp_correct_kernel<T, 9, PHYS>);
+    }
+}
+
+template <typename T>
+const void* corr_kernel(int N, int physics)
+{
+    if (physics == kAcoustic) return corr_kernel_by_order<T, kAcoustic>(N);
+    if (physics == kElastic) return corr_kernel_by_order<T, kElastic>(N);
+    return corr_kernel_by_order<T, kGeneric>(N);
+}
+
 size_t corr_lds(int N, int m, size_t io)
 {
     const int n = N + 1;
-    return io * (size_t)(6 * m * m + 6 * n * n * m + 8 + 2 * n);
+    return io * (size_t)(6 * m * m + 24 + 6 * n * n * m + 8 + 2 * n);
 }
 
 }  // namespace
@@ -245,14 +282,13 @@ extern "C" stp_status stp_correct(stp_plan_t p, const stp_step* st, void* stream
     a.e1 = cs.de1;
     a.w = cs.dw;
     const size_t lds = corr_lds(c.order, c.nquant, io);
-    const void* fn = p->prec == STP_FP64 ? reinterpret_cast<const void*>(&stp_correct_kernel<double>)
-                                         : reinterpret_cast<const void*>(&stp_correct_kernel<float>);
+    const void* fn = p->prec == STP_FP64 ? corr_kernel<double>(c.order, c.physics) : corr_kernel<float>(c.order, c.physics);
     DeviceGuard g(p->device);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return hip_fail(e, "hipFuncSetAttribute(corrector LDS)");
     }
-    const unsigned grid = (unsigned)std::min<int64_t>(E, (int64_t)p->num_cus * 16);
+    const unsigned grid = (unsigned)E;  // one workgroup per element: the hardware overlaps their phases
     void* args[] = {&a};
     hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kCorrThreads), args, lds, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "hipLaunchKernel(corrector)");
