@@ -42,7 +42,7 @@ class _Args(C.Structure):
         ("Q", C.c_void_p), ("params", C.c_void_p), ("A", C.c_void_p), ("B", C.c_void_p),
         ("src", C.c_void_p), ("dt", C.c_void_p), ("h", C.c_void_p),
         ("qavg", C.c_void_p), ("favg", C.c_void_p), ("qface", C.c_void_p), ("fface", C.c_void_p),
-        ("favg_fig5", C.c_void_p), ("nthreads", C.c_int),
+        ("favg_fig5", C.c_void_p), ("nthreads", C.c_int), ("nodes", C.c_int),
     ]
 
 
@@ -57,10 +57,11 @@ def _load(path):
     L.oracle_lagrange_at.argtypes = [C.c_int, dp, C.c_double, dp]
     L.oracle_contract.argtypes = [C.c_int, C.c_int, dp, C.c_int, dp, dp]
     L.oracle_preset_B.argtypes = [C.c_int, C.c_int, dp, dp]
+    L.oracle_gll_nodes.argtypes = [C.c_int, dp, dp]
     L.oracle_apply_Vd.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_void_p, dp, dp, dp]
     L.oracle_stp.argtypes = [C.POINTER(_Args)]
     L.oracle_default_threads.argtypes = []
-    for f in ("oracle_gl_nodes", "oracle_dmatrix", "oracle_lagrange_at", "oracle_contract",
+    for f in ("oracle_gl_nodes", "oracle_gll_nodes", "oracle_dmatrix", "oracle_lagrange_at", "oracle_contract",
               "oracle_preset_B", "oracle_apply_Vd", "oracle_stp", "oracle_default_threads"):
         getattr(L, f).restype = C.c_int
     return L
@@ -104,6 +105,18 @@ def _f64(a):
 def _check(rc, what):
     if rc != 0:
         raise ValueError(f"oracle: {what} failed with status {rc}")
+
+
+def gll_nodes(n: int):
+    """Gauss-Lobatto nodes (ascending, including 0 and 1) and weights on [0, 1]; n >= 2."""
+    xi, w = np.zeros(n), np.zeros(n)
+    _check(lib().oracle_gll_nodes(n, _p(xi), _p(w)), "gll_nodes")
+    return xi, w
+
+
+def nodes_of(n: int, family: int = 0):
+    """Nodes and weights of the family: 0 Gauss-Legendre, 1 Gauss-Lobatto."""
+    return gll_nodes(n) if family == 1 else gl_nodes(n)
 
 
 def gl_nodes(n: int):
@@ -162,7 +175,7 @@ def apply_Vd(N: int, h: float, d: int, B3, u, A3=None):
 
 
 def stp(N: int, physics: int, Q, dt, h, params=None, A=None, B=None, src=None,
-        coef_per_element: bool = False, fig5: bool = False, nthreads: int = 0):
+        coef_per_element: bool = False, fig5: bool = False, nthreads: int = 0, nodes: int = 0):
     """Batched FP64 STP. Q is [E, n^3, m] (any shape with that size). dt and h are scalars or [E].
 
     Returns a dict with qavg [E, n^3, m], favg [E, 3, n^3, m], qface [E, 6, n^2, m], and fface
@@ -203,6 +216,7 @@ def stp(N: int, physics: int, Q, dt, h, params=None, A=None, B=None, src=None,
         out["favg_fig5"] = np.zeros((E, 3, nn, m))
         a.favg_fig5 = out["favg_fig5"].ctypes.data
     a.nthreads = int(nthreads)
+    a.nodes = int(nodes)  # 0 Gauss-Legendre, 1 Gauss-Lobatto
     _check(lib().oracle_stp(C.byref(a)), "stp")
     del keep
     return out

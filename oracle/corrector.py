@@ -36,9 +36,9 @@ import oracle
 ACOUSTIC, ELASTIC, GENERIC = 0, 1, 2
 
 
-def gl_weights01(n: int) -> np.ndarray:
-    """Gauss-Legendre weights on [0, 1] (the oracle's quadrature)."""
-    return oracle.gl_nodes(n)[1]
+def gl_weights01(n: int, nodes: int = 0) -> np.ndarray:
+    """Quadrature weights on [0, 1] of the node family (0 Gauss-Legendre, 1 Gauss-Lobatto)."""
+    return oracle.nodes_of(n, nodes)[1]
 
 
 def element_B(physics: int, params=None, B=None):
@@ -60,6 +60,12 @@ def wave_speed(physics: int, params=None, A=None, B=None) -> np.ndarray:
     return np.abs(M).sum(axis=-1).max(axis=(1, 2))
 
 
+def lagrange(xi, x: float) -> np.ndarray:
+    """l_j(x) for the nodes xi (product formula)."""
+    n = len(xi)
+    return np.array([np.prod([(x - xi[k]) / (xi[j] - xi[k]) for k in range(n) if k != j]) for j in range(n)])
+
+
 def neighbour(e: int, d: int, s: int, nx: int, ny: int, nz: int) -> int:
     """The periodic neighbour of element e across its face along d on side s (-1 lower, +1 upper)."""
     ix, iy, iz = e % nx, (e // nx) % ny, e // (nx * ny)
@@ -73,7 +79,7 @@ def neighbour(e: int, d: int, s: int, nx: int, ny: int, nz: int) -> int:
 
 
 def correct(N: int, physics: int, grid, Q, favg, qface, dt: float, h: float, params=None, A=None, B=None,
-            fface=None, favg_sum: bool = False):
+            fface=None, favg_sum: bool = False, nodes: int = 0):
     """q(t_{n+1}) [E, n^3, m] from q(t_n) and the predictor outputs of every element of the mesh.
 
     Q [E, n^3, m]; favg [E, 3, n^3, m] (or [E, n^3, m] with favg_sum); qface, fface [E, 6, n^2, m] with the
@@ -89,9 +95,9 @@ def correct(N: int, physics: int, grid, Q, favg, qface, dt: float, h: float, par
     ff = None if fface is None else np.asarray(fface, dtype=np.float64).reshape(E, 6, n, n, m)
     Bd = element_B(physics, params, B)
     alpha = wave_speed(physics, params, A, B)
-    w = gl_weights01(n)
-    l0 = oracle.lagrange_at(n, 0.0)
-    l1 = oracle.lagrange_at(n, 1.0)
+    xi, w = oracle.nodes_of(n, nodes)
+    l0 = lagrange(xi, 0.0)
+    l1 = lagrange(xi, 1.0)
     out = Q + dt * vol.reshape(E, n, n, n, m)
     for e in range(E):
         for d in range(3):
@@ -116,9 +122,9 @@ def correct(N: int, physics: int, grid, Q, favg, qface, dt: float, h: float, par
     return out.reshape(E, n ** 3, m)
 
 
-def ader_step(N: int, physics: int, grid, Q, dt: float, h: float, params=None, A=None, B=None):
+def ader_step(N: int, physics: int, grid, Q, dt: float, h: float, params=None, A=None, B=None, nodes: int = 0):
     """One full ADER-DG step: the oracle predictor on every element, then the corrector. Per-element
-    coefficients (params [E, np] or A, B [E, 3, m, m])."""
-    pred = oracle.stp(N, physics, Q, dt, h, params=params, A=A, B=B, coef_per_element=True)
+    coefficients (params [E, np] or A, B [E, 3, m, m]); nodes 0 Gauss-Legendre, 1 Gauss-Lobatto."""
+    pred = oracle.stp(N, physics, Q, dt, h, params=params, A=A, B=B, coef_per_element=True, nodes=nodes)
     return correct(N, physics, grid, Q, pred["favg"], pred["qface"], dt, h, params=params, A=A, B=B,
-                   fface=pred.get("fface"))
+                   fface=pred.get("fface"), nodes=nodes)

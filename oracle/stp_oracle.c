@@ -84,6 +84,44 @@ int oracle_gl_nodes(int n, double* xi, double* w)
     return OR_OK;
 }
 
+/* n >= 2 Gauss-Lobatto nodes on [0,1] (ascending: 0, the roots of P'_{n-1} mapped from [-1,1], 1) and their
+ * weights 2 / (N (N+1) P_N(x)^2) on [-1,1] (N = n - 1), halved for [0,1]. Newton on P'_N, with P''_N from
+ * the Legendre equation (1 - x^2) P'' = 2 x P' - N (N+1) P, from the Chebyshev-Lobatto points. */
+int oracle_gll_nodes(int n, double* xi, double* w)
+{
+    if (n < 2 || n > 64 || !xi || !w) return OR_EINVAL;
+    const int N = n - 1;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    long double x[64];
+    x[0] = -1.0L;
+    x[N] = 1.0L;
+    for (int i = 1; i < N; ++i) {
+        long double t = -cosl(pi * (long double)i / (long double)N);
+        for (int it = 0; it < 100; ++it) {
+            long double pn = 0, dpn = 1;
+            legendre_eval(N, t, &pn, &dpn);
+            const long double d2 = (2.0L * t * dpn - (long double)N * (N + 1) * pn) / (1.0L - t * t);
+            const long double dx = dpn / d2;
+            t -= dx;
+            if (fabsl(dx) < 1e-19L) break;
+        }
+        x[i] = t;
+    }
+    for (int i = 0; i <= N; ++i) {
+        /* P_N at the node by the three-term recurrence (valid at the endpoints too) */
+        long double p0 = 1.0L, p1 = x[i];
+        for (int k = 2; k <= N; ++k) {
+            const long double p2 = ((2.0L * k - 1.0L) * x[i] * p1 - (k - 1.0L) * p0) / (long double)k;
+            p0 = p1;
+            p1 = p2;
+        }
+        const long double pN = N == 0 ? 1.0L : p1;
+        xi[i] = (double)((1.0L + x[i]) * 0.5L);
+        w[i] = (double)(1.0L / ((long double)N * (N + 1) * pN * pN));  /* (2 / (N(N+1) P_N^2)) / 2 */
+    }
+    return OR_OK;
+}
+
 /* Lagrange basis l_j(x) for the nodes xi, evaluated at x, by the product formula. */
 int oracle_lagrange_at(int n, const double* xi, double x, double* l)
 {
@@ -265,6 +303,7 @@ typedef struct {
     double* fface;        /* [e][6][n^2][m]  (only if has_A; may be NULL otherwise)                   */
     double* favg_fig5;    /* optional [e][3][n^3][m]: V_d(q-bar) (Fig. 5 recompute); may be NULL      */
     int nthreads;         /* 0 = all online cores                                                     */
+    int nodes;            /* 0 Gauss-Legendre, 1 Gauss-Lobatto (Sec. II-A: either family)             */
 } oracle_args;
 
 typedef struct {
@@ -436,7 +475,11 @@ int oracle_stp(const oracle_args* a)
 
     const int n = a->N + 1;
     double xi[64], w[64], D[64 * 64], e0v[64], e1v[64];
-    oracle_gl_nodes(n, xi, w);
+    if (a->nodes == 1) {
+        if (oracle_gll_nodes(n, xi, w) != OR_OK) return OR_EINVAL;
+    } else {
+        oracle_gl_nodes(n, xi, w);
+    }
     oracle_dmatrix(n, xi, D);
     oracle_lagrange_at(n, xi, 0.0, e0v);
     oracle_lagrange_at(n, xi, 1.0, e1v);

@@ -110,3 +110,32 @@ def test_elastic_shear_wave_converges():
         errs.append(max(np.abs(Q[..., 1] - f(T)).max(), np.abs(Q[..., 6] + rho * cs * f(T)).max()))
     rate = np.log2(errs[0] / errs[1])
     assert rate > 2.75, (errs, rate)
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_gauss_lobatto_plane_wave_converges(N):
+    """The same acoustic plane wave with Gauss-Lobatto nodes (collocated boundary nodes, lumped mass)."""
+    rho, K = 1.0, 2.25
+    c = np.sqrt(K / rho)
+    errs = []
+    n = N + 1
+    xi, _ = oracle.gll_nodes(n)
+    for nx in (8, 16):
+        h = 1.0 / nx
+        x = np.zeros((nx, n, n, n))
+        for e in range(nx):
+            x[e] = (e + xi)[None, None, :] * h
+        x = x.reshape(nx, n ** 3)
+        f = lambda t: np.sin(2 * np.pi * (x - c * t))
+        Q = np.zeros((nx, n ** 3, 4))
+        Q[..., 0] = f(0.0)
+        Q[..., 1] = f(0.0) / (rho * c)
+        params = np.tile([rho, K], (nx, 1))
+        T = 0.2
+        steps = int(np.ceil(T / full_step_dt(N, h, c)))
+        dt = T / steps
+        for _ in range(steps):
+            Q = OC.ader_step(N, ACOUSTIC, (nx, 1, 1), Q, dt, h, params=params, nodes=1)
+        errs.append(max(np.abs(Q[..., 0] - f(T)).max(), np.abs(Q[..., 1] - f(T) / (rho * c)).max()))
+    rate = np.log2(errs[0] / errs[1])
+    assert rate > N + 1 - 0.5, (errs, rate)

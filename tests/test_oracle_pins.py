@@ -488,3 +488,63 @@ def test_empty_batch(oracle_mod):
     b = W.elastic_batch(3, 0, 1)
     out = run_oracle(oracle_mod, b)
     assert out["qavg"].shape == (0, 64, 9)
+
+
+# ------------------------------------------------------------------------------------------------ Gauss-Lobatto
+def test_gll_nodes_closed_forms(oracle_mod):
+    """Lobatto rules on [0, 1]: n = 3 is Simpson's rule; n = 4 has the nodes 1/2 -+ sqrt(5)/10 with weights
+    1/12, 5/12; n = 5 has 1/2 -+ sqrt(21)/14 and the weights 1/20, 49/180, 16/45."""
+    x, w = oracle_mod.gll_nodes(3)
+    assert np.allclose(x, [0, 0.5, 1], atol=1e-15) and np.allclose(w, [1 / 6, 2 / 3, 1 / 6], atol=1e-15)
+    x, w = oracle_mod.gll_nodes(4)
+    s5 = math.sqrt(5) / 10
+    assert np.allclose(x, [0, 0.5 - s5, 0.5 + s5, 1], atol=1e-15)
+    assert np.allclose(w, [1 / 12, 5 / 12, 5 / 12, 1 / 12], atol=1e-15)
+    x, w = oracle_mod.gll_nodes(5)
+    s21 = math.sqrt(21) / 14
+    assert np.allclose(x, [0, 0.5 - s21, 0.5, 0.5 + s21, 1], atol=1e-15)
+    assert np.allclose(w, [1 / 20, 49 / 180, 16 / 45, 49 / 180, 1 / 20], atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 6, 8, 10])
+def test_gll_quadrature_degree_is_2n_minus_3(oracle_mod, n):
+    x, w = oracle_mod.gll_nodes(n)
+    for p in range(2 * n - 2):
+        assert abs(np.dot(w, x ** p) - 1.0 / (p + 1)) < 1e-14, p
+    # one degree higher the rule errs by exactly the Lobatto remainder term (f^(2n-2) is constant here):
+    # n (n-1)^3 2^(2n-1) ((n-2)!)^4 / ((2n-1) ((2n-2)!)^3) times f^(2n-2) of x^(2n-2) mapped to [-1, 1]
+    f = math.factorial
+    rem = n * (n - 1) ** 3 * 2 ** (2 * n - 1) * f(n - 2) ** 4 / ((2 * n - 1) * f(2 * n - 2) ** 3)
+    rem *= 0.5 * f(2 * n - 2) / 2 ** (2 * n - 2)
+    err = np.dot(w, x ** (2 * n - 2)) - 1.0 / (2 * n - 1)
+    assert abs(err / rem - 1.0) < 1e-5, (err, rem)
+
+
+@pytest.mark.parametrize("N", [1, 3, 7])
+def test_gll_predictor_matches_dense_series(oracle_mod, N):
+    """With Gauss-Lobatto nodes the predictor is the truncated series of the dense operator built from the
+    Lobatto derivative matrix (numpy's polynomial routines on the oracle's Lobatto nodes)."""
+    n, m = N + 1, 9
+    xi, _ = oracle_mod.gll_nodes(n)
+    D = np.zeros((n, n))
+    for j in range(n):
+        others = np.delete(xi, j)
+        coef = np.poly(others) / np.prod(xi[j] - others)
+        D[:, j] = np.polyval(np.polyder(coef), xi)
+    rng = np.random.default_rng(40 + N)
+    par = np.array([2.4, 2.1, 1.3])
+    Q = rng.standard_normal((1, n ** 3, m))
+    h, dt = 0.7, 0.01
+    out = oracle_mod.stp(N, ELASTIC, Q, dt, h, params=par[None], coef_per_element=True, nodes=1)
+    B3 = np.broadcast_to(oracle_mod.preset_B(ELASTIC, par)[:, None], (3, n ** 3, m, m))
+    Vds = [dense.dense_Vd(N, m, h, d, B3, None, D) for d in range(3)]
+    V = sum(Vds)
+    terms = [Q[0].ravel()]
+    for o in range(1, N + 1):
+        terms.append(V @ terms[-1])
+    qbar = sum(dt ** o / math.factorial(o + 1) * t for o, t in enumerate(terms))
+    assert np.abs(out["qavg"][0].ravel() - qbar).max() < 1e-12 * np.abs(qbar).max()
+    # Lobatto faces are the boundary nodes themselves
+    q = out["qavg"][0].reshape(n, n, n, m)
+    assert np.array_equal(out["qface"][0, 0].reshape(n, n, m), q[:, :, 0])
+    assert np.array_equal(out["qface"][0, 5].reshape(n, n, m), q[n - 1])
