@@ -8,7 +8,8 @@
  *   PDE        q_t + sum_d (A_d q)_{x_d} + B_d dq/dx_d = 0           (Eq. (1), material absorbed in B_d)
  *   operator   V(u) = sum_d V_d(u),
  *              V_d(u) = -(1/h) [ D x_d (A_d o u) + B_d o (D x_d u) ]  (Sec. II-A volume term)
- *              D[i][j] = l_j'(xi_i) on the n = N+1 Gauss-Legendre nodes of [0,1]; "D x_d" contracts
+ *              D[i][j] = l_j'(xi_i) on the n = N+1 Gauss-Legendre (or Gauss-Lobatto, stp_plan_desc.nodes)
+ *              nodes of [0,1]; "D x_d" contracts
  *              spatial axis d; "o" is the nodewise m x m product.
  *   Taylor     p_0 = Q, p_{o+1} = V p_o (+ S_o), o = 0..N-1          (Cauchy-Kowalewsky, Eq. (4))
  *   outputs    qavg    = sum_{o=0..N} dt^o/(o+1)! p_o                 time AVERAGE (Eq. (4) / dt)
@@ -114,6 +115,10 @@ typedef struct {
                                   file named by STP_TUNE_CACHE, else $HOME/.cache/stp_tune.json, keyed by
                                   architecture, HIP runtime version, CU count and class. STP_E_INVAL
                                   outside 0..2.                                                          */
+    int nodes;                 /* interpolation nodes of the nodal basis (Sec. II-A allows both): 0 =
+                                  Gauss-Legendre, 1 = Gauss-Lobatto (the faces are then boundary nodes and
+                                  the corrector's mass matrix is the Lobatto quadrature). STP_E_INVAL
+                                  outside 0..1.                                                          */
 } stp_plan_desc;
 
 /* Kernel variants selectable through stp_plan_desc.variant (0 = library choice). */

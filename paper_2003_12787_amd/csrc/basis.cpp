@@ -67,6 +67,34 @@ void gauss_legendre_01(int n, double* xi, double* w)
     }
 }
 
+void gauss_lobatto_01(int n, double* xi, double* w)
+{
+    // The n = N + 1 Lobatto points of [-1, 1] are the zeros of P_{N+1} - P_{N-1} (which is (2N+1)/(N(N+1))
+    // times -(1 - x^2) P_N'), with derivative (2N+1) P_N. Newton from the Chebyshev-Lobatto points; the end
+    // points are exact. Weights 2 / (N (N+1) P_N(x)^2) on [-1, 1], halved for [0, 1].
+    const int N = n - 1;
+    auto P = [](int k, long double x, long double* out) {  // out[0..k] = P_0..P_k
+        out[0] = 1.0L;
+        if (k > 0) out[1] = x;
+        for (int j = 2; j <= k; ++j) out[j] = ((2.0L * j - 1.0L) * x * out[j - 1] - (j - 1.0L) * out[j - 2]) / j;
+    };
+    const long double pi = 3.141592653589793238462643383279502884L;
+    long double v[kMaxNodes + 2];
+    for (int i = 0; i <= N; ++i) {
+        long double x = i == 0 ? -1.0L : (i == N ? 1.0L : -cosl(pi * i / N));
+        if (i > 0 && i < N)
+            for (int it = 0; it < 60; ++it) {
+                P(N + 1, x, v);
+                const long double dx = (v[N + 1] - v[N - 1]) / ((2.0L * N + 1.0L) * v[N]);
+                x -= dx;
+                if (fabsl(dx) < 1e-20L) break;
+            }
+        P(N, x, v);
+        xi[i] = (double)(0.5L * (1.0L + x));
+        w[i] = (double)(1.0L / ((long double)N * (N + 1) * v[N] * v[N]));
+    }
+}
+
 void lagrange_values(int n, const double* xi, double x, double* l)
 {
     for (int j = 0; j < n; ++j) {

@@ -9,6 +9,8 @@ constexpr int kMaxNodes = kMaxOrder + 1;  // n = N + 1
 
 // n Gauss-Legendre nodes on [0,1], ascending, and weights summing to 1.
 void gauss_legendre_01(int n, double* xi, double* w);
+// n >= 2 Gauss-Lobatto nodes on [0,1] (0 and 1 included), ascending, and weights summing to 1.
+void gauss_lobatto_01(int n, double* xi, double* w);
 // Lagrange basis values l_j(x), j = 0..n-1.
 void lagrange_values(int n, const double* xi, double x, double* l);
 // D[i*n + j] = l_j'(xi_i).

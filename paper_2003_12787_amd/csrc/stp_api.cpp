@@ -130,7 +130,10 @@ stp_status build_class(stp_plan_s* p, ClassState& cs)
 {
     const int n = cs.cls.order + 1;
     double xi[kMaxNodes], w[kMaxNodes], D[kMaxNodes * kMaxNodes], e0[kMaxNodes], e1[kMaxNodes];
-    gauss_legendre_01(n, xi, w);
+    if (p->nodes == 1)
+        gauss_lobatto_01(n, xi, w);
+    else
+        gauss_legendre_01(n, xi, w);
     derivative_matrix(n, xi, D);
     lagrange_values(n, xi, 0.0, e0);
     lagrange_values(n, xi, 1.0, e1);
@@ -259,6 +262,7 @@ stp_status stp_plan(const stp_plan_desc* desc, stp_plan_t* out)
     if (desc->variant < STP_VARIANT_AUTO || desc->variant > STP_VARIANT_MFMA)
         return fail(STP_E_INVAL, "unknown variant %d", desc->variant);
     if (desc->autotune < 0 || desc->autotune > 2) return fail(STP_E_INVAL, "autotune=%d outside 0..2", desc->autotune);
+    if (desc->nodes < 0 || desc->nodes > 1) return fail(STP_E_INVAL, "nodes=%d outside 0..1", desc->nodes);
     for (int i = 0; i < desc->nclass; ++i) {
         stp_status st = validate_class(desc->classes[i]);
         if (st != STP_OK) return st;
@@ -276,6 +280,7 @@ stp_status stp_plan(const stp_plan_desc* desc, stp_plan_t* out)
     p->acc64_min_order = desc->acc64_min_order;
     p->variant = desc->variant;
     p->serve_budget = desc->serve_mem_budget;
+    p->nodes = desc->nodes;
     hipDeviceProp_t prop;
     if ((e = hipGetDeviceProperties(&prop, desc->device)) != hipSuccess) {
         delete p;
@@ -360,8 +365,9 @@ stp_status stp_plan_describe(stp_plan_t p, char* buf, size_t len)
                       cs.tiled ? cs.slots : 1, cs.acc64 ? "true" : "false");
         out += tmp;
     }
-    std::snprintf(tmp, sizeof tmp, "], \"hetero_grid_per_cu\": %d, \"hetero_lds_budget\": %zu, \"autotune\": %d}",
-                  p->hetero_grid_per_cu, p->hetero_lds_budget, p->autotune);
+    std::snprintf(tmp, sizeof tmp,
+                  "], \"hetero_grid_per_cu\": %d, \"hetero_lds_budget\": %zu, \"autotune\": %d, \"nodes\": \"%s\"}",
+                  p->hetero_grid_per_cu, p->hetero_lds_budget, p->autotune, p->nodes ? "lobatto" : "legendre");
     out += tmp;
     if (out.size() + 1 > len) return fail(STP_E_INVAL, "buffer of %zu bytes too small (%zu needed)", len, out.size() + 1);
     std::memcpy(buf, out.c_str(), out.size() + 1);

@@ -93,6 +93,7 @@ struct stp_plan_s {
     int hetero_grid_per_cu = 4;   // persistent workgroups per CU
     size_t hetero_lds_budget = stp::kHeteroLdsBudget;  // LDS of one persistent workgroup (sets tile sizes)
     int autotune = 0;
+    int nodes = 0;  // 0 Gauss-Legendre, 1 Gauss-Lobatto
     stp::ServeState* serve = nullptr;
 };
 

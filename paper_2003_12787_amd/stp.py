@@ -18,6 +18,8 @@ ACOUSTIC, ELASTIC, GENERIC = 0, 1, 2
 FP64, FP32, BF16X3 = 0, 1, 2
 # class flags
 PARAM_PER_ELEMENT, A_PRESENT, COEF_PER_ELEMENT, FAVG_SUM, SRC_POINT = 1, 2, 4, 8, 16
+# node families
+GAUSS_LEGENDRE, GAUSS_LOBATTO = 0, 1
 # kernel variants
 VARIANT_AUTO, VARIANT_PLAIN, VARIANT_FUSED, VARIANT_MFMA = 0, 1, 2, 3
 
@@ -39,7 +41,7 @@ class Class(C.Structure):
 class PlanDesc(C.Structure):
     _fields_ = [("nclass", C.c_int), ("classes", C.POINTER(Class)), ("prec", C.c_int),
                 ("acc64_min_order", C.c_int), ("device", C.c_int), ("variant", C.c_int),
-                ("serve_mem_budget", C.c_size_t), ("autotune", C.c_int)]
+                ("serve_mem_budget", C.c_size_t), ("autotune", C.c_int), ("nodes", C.c_int)]
 
 
 class Batch(C.Structure):
@@ -117,11 +119,12 @@ class Plan:
     """A predictor plan (owns its device tables). classes: list of (order, nquant, physics, flags)."""
 
     def __init__(self, classes, prec=FP32, acc64_min_order=0, device=0, variant=VARIANT_AUTO,
-                 serve_mem_budget=0, autotune=0):
+                 serve_mem_budget=0, autotune=0, nodes=GAUSS_LEGENDRE):
         arr = (Class * len(classes))(*[Class(*c) for c in classes])
         self.classes = [tuple(c) for c in classes]
         self.prec = prec
-        desc = PlanDesc(len(classes), arr, prec, acc64_min_order, device, variant, serve_mem_budget, autotune)
+        desc = PlanDesc(len(classes), arr, prec, acc64_min_order, device, variant, serve_mem_budget, autotune,
+                        nodes)
         h = C.c_void_p()
         _check(lib().stp_plan(C.byref(desc), C.byref(h)))
         self.handle = h

@@ -60,6 +60,14 @@ def test_plan_rejects_invalid_classes_on_host(L, classes, prec, expect):
     assert L.stp_plan(C.byref(d), C.byref(h)) == expect
 
 
+def test_plan_rejects_unknown_node_family(L):
+    d = _desc([(3, 9, stp.ELASTIC, 0)])
+    d.nodes = 2
+    h = C.c_void_p()
+    assert L.stp_plan(C.byref(d), C.byref(h)) == stp.E_INVAL
+    assert "nodes" in stp.last_error()
+
+
 @pytest.mark.parametrize("mode", [-1, 3])
 def test_plan_rejects_unknown_autotune_mode(L, mode):
     d = _desc([(3, 9, stp.ELASTIC, 0)])
