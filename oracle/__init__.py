@@ -19,9 +19,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "stp_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-ACOUSTIC, ELASTIC, GENERIC = 0, 1, 2
-NPARAM = {ACOUSTIC: 2, ELASTIC: 3}
-NQUANT = {ACOUSTIC: 4, ELASTIC: 9}
+ACOUSTIC, ELASTIC, GENERIC, ELASTIC_CURV = 0, 1, 2, 3
+NPARAM = {ACOUSTIC: 2, ELASTIC: 3, ELASTIC_CURV: 12}
+NQUANT = {ACOUSTIC: 4, ELASTIC: 9, ELASTIC_CURV: 9}
 
 
 def build(force: bool = False) -> str:

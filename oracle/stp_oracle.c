@@ -28,6 +28,12 @@
  *   - Faces f = x-, x+, y-, y+, z-, z+ (reference coordinate 0 or 1 along the normal); face data
  *     [f][a][b][s] with (a, b) the two remaining axes, slower first: (z,y), (z,x), (y,x).
  *   - qface = q-bar extrapolated to each face; fface = (A_{d_f} o q-bar) extrapolated (only if A present).
+ *   - Curvilinear elastic elements (the benchmark physics of Sec. VI: 9 wave quantities, 3 material
+ *     parameters and 9 geometry parameters per point): the element is the image of the reference cube under
+ *     a map x(xi), and the elastic system q_t + sum_j M_j dq/dx_j = 0 becomes, by the chain rule,
+ *         q_t + sum_d B_d dq/dxi_d / h = 0,   B_d = sum_j G[d][j] M_j,   G[d][j] = h dxi_d/dx_j,
+ *     i.e. a non-conservative system with per-node B_d. The 9 geometry parameters are the metric terms G
+ *     (the inverse Jacobian of the map, scaled by the element size h so that an undeformed cube has G = I).
  */
 #include <math.h>
 #include <pthread.h>
@@ -39,7 +45,7 @@
 #define OR_EINVAL (-1)
 #define OR_ENOMEM (-3)
 
-enum { OR_ACOUSTIC = 0, OR_ELASTIC = 1, OR_GENERIC = 2 };
+enum { OR_ACOUSTIC = 0, OR_ELASTIC = 1, OR_GENERIC = 2, OR_ELASTIC_CURV = 3 };
 
 /* ------------------------------------------------------------------------------------------------ */
 /* 1D basis: Gauss-Legendre nodes on [0,1] (Sec. II-A: nodal Lagrange basis on Gauss-Legendre points). */
@@ -189,7 +195,9 @@ int oracle_contract(int n, int m, const double* M, int axis, const double* u, do
  * matrices; these follow from the textbook first-order systems written as q_t + sum_d B_d q_{x_d} = 0.
  *   acoustic, q = (p, v_x, v_y, v_z), par = (rho, K):   p_t + K div v = 0,  v_t + grad p / rho = 0.
  *   elastic,  q = (v_x, v_y, v_z, s_xx, s_yy, s_zz, s_xy, s_yz, s_xz), par = (rho, lambda, mu):
- *             rho v_t = div sigma,  sigma_t = lambda (div v) I + mu (grad v + grad v^T). */
+ *             rho v_t = div sigma,  sigma_t = lambda (div v) I + mu (grad v + grad v^T).
+ *   curvilinear elastic, same q, par = (rho, lambda, mu, G[0][0], G[0][1], ..., G[2][2]) (row-major):
+ *             B_d = sum_j G[d][j] M_j with M_j the Cartesian elastic B_j of (rho, lambda, mu). */
 static int stress_index(int i, int j)
 {
     if (i == j) return 3 + i;
@@ -225,6 +233,20 @@ int oracle_preset_B(int physics, int m, const double* par, double* B3)
             for (int i = 0; i < 3; ++i)
                 if (i != d) B[stress_index(d, i) * 9 + i] = -mu;                     /* s_di <- d_d v_i */
         }
+        return OR_OK;
+    }
+    if (physics == OR_ELASTIC_CURV) {
+        if (m != 9) return OR_EINVAL;
+        double Mj[3 * 81];
+        int st = oracle_preset_B(OR_ELASTIC, 9, par, Mj);
+        if (st != OR_OK) return st;
+        const double* G = par + 3;
+        for (int d = 0; d < 3; ++d)
+            for (int k = 0; k < 81; ++k) {
+                double acc = 0.0;
+                for (int j = 0; j < 3; ++j) acc += G[d * 3 + j] * Mj[j * 81 + k];
+                B3[d * 81 + k] = acc;
+            }
         return OR_OK;
     }
     return OR_EINVAL;
@@ -291,7 +313,7 @@ typedef struct {
     int has_src;          /* point source present                                                     */
     long nelem;
     const double* Q;      /* [e][n^3][m]                                                              */
-    const double* params; /* presets: [e][n^3][np] (np = 2 acoustic, 3 elastic) or [e][np]            */
+    const double* params; /* presets: [e][n^3][np] (np = 2 acoustic, 3 elastic, 12 curvilinear) or [e][np] */
     const double* A;      /* generic: [e][3][n^3][m][m] or [e][3][m][m]                               */
     const double* B;      /* generic: same layout as A                                                */
     const double* src;    /* [e][n^3 + m + N]: P[node], a[s], sigma^(o)(t_n) for o = 0..N-1           */
@@ -315,7 +337,10 @@ typedef struct {
     int status;
 } worker_t;
 
-static int np_of(int physics) { return physics == OR_ACOUSTIC ? 2 : (physics == OR_ELASTIC ? 3 : 0); }
+static int np_of(int physics)
+{
+    return physics == OR_ACOUSTIC ? 2 : (physics == OR_ELASTIC ? 3 : (physics == OR_ELASTIC_CURV ? 12 : 0));
+}
 
 /* Per-element matrices A_d, B_d at every node ([3][n^3][m][m]). */
 static void element_matrices(const oracle_args* a, long e, int nn, double* A3, double* B3)
@@ -462,9 +487,9 @@ int oracle_stp(const oracle_args* a)
 {
     if (!a || a->N < 0 || a->N > 20 || a->m < 1 || a->m > 16 || a->nelem < 0) return OR_EINVAL;
     if (a->physics == OR_ACOUSTIC && a->m != 4) return OR_EINVAL;
-    if (a->physics == OR_ELASTIC && a->m != 9) return OR_EINVAL;
+    if ((a->physics == OR_ELASTIC || a->physics == OR_ELASTIC_CURV) && a->m != 9) return OR_EINVAL;
     if (a->physics != OR_GENERIC && a->has_A) return OR_EINVAL;
-    if (a->physics < 0 || a->physics > 2) return OR_EINVAL;
+    if (a->physics < 0 || a->physics > 3) return OR_EINVAL;
     if (a->nelem == 0) return OR_OK;
     if (!a->Q || !a->dt || !a->h || !a->qavg || !a->favg || !a->qface) return OR_EINVAL;
     if (a->physics == OR_GENERIC ? (!a->B || (a->has_A && (!a->A || !a->fface))) : !a->params) return OR_EINVAL;

@@ -7,10 +7,12 @@ reduced-precision runs round these values to the I/O dtype and the oracle is the
 values.
 
 The paper's benchmark (LOH1 on a curvilinear mesh, m = 21) is not available; these inputs stand in for
-it with the same physics (first-order elastic velocity-stress, three material parameters per node).
+it with the same physics (first-order elastic velocity-stress, three material parameters per node) and, for
+the curvilinear elements, nine geometry parameters per node from a smooth synthetic mesh deformation.
 
 Quantity order: acoustic (p, v_x, v_y, v_z), params (rho, K); elastic (v_x, v_y, v_z, s_xx, s_yy, s_zz,
-s_xy, s_yz, s_xz), params (rho, lambda, mu). Nodal arrays are [element][z][y][x][quantity].
+s_xy, s_yz, s_xz), params (rho, lambda, mu); curvilinear elastic params (rho, lambda, mu, G[0][0], ...,
+G[2][2]) with G[d][j] = h dxi_d/dx_j. Nodal arrays are [element][z][y][x][quantity].
 """
 from __future__ import annotations
 
@@ -19,9 +21,9 @@ import math
 
 import numpy as np
 
-ACOUSTIC, ELASTIC, GENERIC = 0, 1, 2
-NQUANT = {ACOUSTIC: 4, ELASTIC: 9}
-NPARAM = {ACOUSTIC: 2, ELASTIC: 3}
+ACOUSTIC, ELASTIC, GENERIC, ELASTIC_CURV = 0, 1, 2, 3
+NQUANT = {ACOUSTIC: 4, ELASTIC: 9, ELASTIC_CURV: 9}
+NPARAM = {ACOUSTIC: 2, ELASTIC: 3, ELASTIC_CURV: 12}
 SEED0 = 2003127870
 
 
@@ -82,6 +84,77 @@ def elastic_batch(N: int, nelem: int, seed: int, h: float = 1.0, per_node: bool 
     cp = np.sqrt((par[..., 1] + 2 * par[..., 2]) / par[..., 0]).max() if nelem else 1.0
     dt = np.full(nelem, cfl_dt(N, h, cp))
     return Batch(N, 9, ELASTIC, Q, dt, np.full(nelem, h), params=par, coef_per_element=not per_node)
+
+
+def grid_of(nelem: int):
+    """(nx, ny, nz) of the box the curvilinear workloads tile: nx = 2 ny = 2 nz when nelem = 2 k^3 (65536 ->
+    64 x 32 x 32), else the smallest cube holding nelem elements."""
+    k = round((nelem / 2) ** (1.0 / 3.0))
+    if 2 * k ** 3 == nelem:
+        return 2 * k, k, k
+    g = max(1, int(round(nelem ** (1.0 / 3.0))))
+    while g ** 3 < nelem:
+        g += 1
+    return g, g, g
+
+
+def curved_map(xi, L, eps):
+    """A smooth, periodic deformation of the box [0, L_0] x [0, L_1] x [0, L_2] (xi [..., 3] -> x [..., 3]) and
+    its Jacobian J[..., i, j] = dx_i/dxi_j:
+        x_i = xi_i + eps a prod_{j != i} sin(2 pi xi_j / L_j),   a = min(L) / (2 pi).
+    Each off-diagonal entry of J is at most eps in magnitude, so J is invertible for eps < 1/2."""
+    L = np.asarray(L, dtype=np.float64)
+    a = L.min() / (2 * math.pi)
+    k = 2 * math.pi / L
+    s = np.sin(xi * k)
+    c = np.cos(xi * k)
+    x = xi.copy()
+    J = np.zeros(xi.shape + (3,))
+    for i in range(3):
+        j1, j2 = [j for j in range(3) if j != i]
+        x[..., i] += eps * a * s[..., j1] * s[..., j2]
+        J[..., i, i] = 1.0
+        J[..., i, j1] = eps * a * k[j1] * c[..., j1] * s[..., j2]
+        J[..., i, j2] = eps * a * k[j2] * s[..., j1] * c[..., j2]
+    return x, J
+
+
+def curvilinear_geometry(N: int, grid, h: float, eps: float, elements=None):
+    """Node positions x [E, n^3, 3] and metric terms G [E, n^3, 3, 3] (G[d][j] = h dxi_d/dx_j = the inverse of
+    dx/dxi_global) of the elements of a grid (nx, ny, nz) of cubes of side h under curved_map; element
+    e = (iz ny + iy) nx + ix, nodes (z, y, x) at Gauss-Legendre points."""
+    nx, ny, nz = grid
+    n = N + 1
+    e = np.arange(nx * ny * nz) if elements is None else np.asarray(elements)
+    t = _node_positions(n)
+    Z, Y, X = np.meshgrid(t, t, t, indexing="ij")
+    xi = np.empty((len(e), n ** 3, 3))
+    xi[..., 0] = ((e % nx)[:, None] + X.reshape(1, -1)) * h
+    xi[..., 1] = (((e // nx) % ny)[:, None] + Y.reshape(1, -1)) * h
+    xi[..., 2] = ((e // (nx * ny))[:, None] + Z.reshape(1, -1)) * h
+    x, J = curved_map(xi, (nx * h, ny * h, nz * h), eps)
+    return x, np.linalg.inv(J)
+
+
+def curvilinear_batch(N: int, nelem: int, seed: int, h: float = 1.0, eps: float = 0.2, per_node: bool = True,
+                      q_scale: float = 1.0) -> Batch:
+    """Elastic waves on curvilinear elements (m = 9, 12 parameters per node): the material of elastic_batch,
+    the metric terms of curvilinear_geometry on grid_of(nelem), Q ~ N(0, 1). dt from the fastest P-wave
+    times the largest row sum of |G| in the batch (the fastest reference-space speed). per_node = False
+    keeps the first node's parameters for the whole element (an affine element)."""
+    rng = np.random.default_rng(seed)
+    n3 = (N + 1) ** 3
+    grid = grid_of(nelem)
+    _, G = curvilinear_geometry(N, grid, h, eps, elements=np.arange(nelem))
+    mat = elastic_material(rng, (nelem, n3) if per_node else (nelem,))
+    if not per_node:
+        G = G[:, 0]
+    par = np.concatenate([mat, G.reshape(G.shape[:-2] + (9,))], axis=-1)
+    Q = q_scale * rng.standard_normal((nelem, n3, 9))
+    cp = np.sqrt((mat[..., 1] + 2 * mat[..., 2]) / mat[..., 0]).max() if nelem else 1.0
+    gmax = np.abs(G).sum(axis=-1).max() if nelem else 1.0
+    dt = np.full(nelem, cfl_dt(N, h, cp * gmax))
+    return Batch(N, 9, ELASTIC_CURV, Q, dt, np.full(nelem, h), params=par, coef_per_element=not per_node)
 
 
 def acoustic_plane_wave_batch(N: int, nelem: int, seed: int, h: float = 1.0, noise: float = 1e-2,
