@@ -197,6 +197,49 @@ def bench_full_step(args, torch, stp, W):
     return res
 
 
+def bench_curvilinear(args, torch, stp, W):
+    """Elastic waves on curvilinear elements (the benchmark physics of Sec. VI: 9 wave quantities and 12
+    parameters per node, material and metric terms), N = 7, the elements of a deformed 64 x 32 x 32 box,
+    inputs generated on the device. The FP32 and FP64 plain kernels (the fused and MFMA kernels cover the
+    Cartesian presets). Returns the timings and, for the CPU leg, the inputs and outputs of 256 elements."""
+    N, E, m = 7, args.nelem, 9
+    n3, n2 = (N + 1) ** 3, (N + 1) ** 2
+    log(f"[bench] curvilinear elastic N=7, {E} elements, generating on the device")
+    Q, par, dt = W.curvilinear_device(N, E, W.SEED0 + 7)
+    ids = np.linspace(0, E - 1, min(E, 256)).astype(np.int64)
+    tid = torch.from_numpy(ids).cuda()
+    res = {"workload": f"curvilinear elastic N=7, m=9 + 12 per-node parameters (rho, lambda, mu, 9 metric terms), "
+                       f"{E} elements of a deformed {'x'.join(map(str, W.grid_of(E)))} box, FP32 I/O",
+           "nelem": E, "check": {"ids": ids, "Q": Q.index_select(0, tid).double().cpu().numpy(),
+                                  "params": par.index_select(0, tid).double().cpu().numpy(), "dt": dt}}
+    for name, prec in (("fp32_plain", stp.FP32), ("fp64_plain", stp.FP64)):
+        tdt = torch.float64 if prec == stp.FP64 else torch.float32
+        plan = stp.Plan([(N, m, stp.ELASTIC_CURV, 0)], prec=prec)
+        q, p = Q.to(tdt), par.to(tdt)
+        qavg = torch.empty((E, n3, m), device="cuda", dtype=tdt)
+        favg = torch.empty((E, 3, n3, m), device="cuda", dtype=tdt)
+        qface = torch.empty((E, 6, n2, m), device="cuda", dtype=tdt)
+        batch = plan.batch(E, q, qavg, favg, qface, dt, 1.0, params=p)
+        ms = float(np.median(time_launches(lambda st: plan.run(batch, st), args.steps, args.warmup,
+                                           torch.cuda.Stream(), torch)))
+        bytes_el, flops_el = plan.cost(0)
+        res[name] = {"ms": ms, "elements_per_s": E / (ms * 1e-3),
+                     "hbm_gbs_algorithmic": bytes_el * E / (ms * 1e-3) / 1e9,
+                     "tflops": flops_el * E / (ms * 1e-3) / 1e12,
+                     "alu_frac": flops_el * E / (ms * 1e-3) / 1e12 / ALU_PEAK_TFS["f64" if prec == stp.FP64 else "f32"],
+                     "bytes_per_element": bytes_el, "flops_per_element": flops_el,
+                     "sampled": {k: v.index_select(0, tid).double().cpu().numpy()
+                                 for k, v in (("qavg", qavg), ("favg", favg), ("qface", qface))}}
+        log(f"[bench] curvilinear {name}: {ms:.3f} ms, {res[name]['tflops']:.1f} TFLOP/s "
+            f"({100 * res[name]['alu_frac']:.1f}% of the VALU peak)")
+        del q, p, qavg, favg, qface
+        plan.close()
+    del Q, par
+    torch.cuda.empty_cache()
+    res["speedup_fp32_vs_fp64"] = res["fp64_plain"]["ms"] / res["fp32_plain"]["ms"]
+    return res
+
+
 def bench_hetero(args, torch, stp, W):
     """Mixed orders and quantity counts in one batch: 16384 generic elements, N ~ U{2..9}, m ~ U{4, 9},
     dense per-node B_d, FP32. Times the heterogeneous stp_run (eager and replayed from a captured HIP graph)
@@ -428,6 +471,7 @@ def main():
 
     acoustic = None if args.no_hetero else bench_acoustic(args, torch, stp, W, runner)
     full_step = None if args.no_hetero else bench_full_step(args, torch, stp, W)
+    curv = None if args.no_hetero else bench_curvilinear(args, torch, stp, W)
     hetero = None if args.no_hetero else bench_hetero(args, torch, stp, W)
     serving = None if args.no_serve else bench_serving(args, torch, stp, W)
 
@@ -460,6 +504,20 @@ def main():
             results[name]["checked_elements"] = int(len(pos))
             log(f"[bench] {name}: max rel err vs oracle {errs}")
         del ref
+        if curv is not None:  # sampled parity of the curvilinear workload
+            ck = curv["check"]
+            ref = oracle.stp(7, W.ELASTIC_CURV, ck["Q"], ck["dt"], 1.0, params=ck["params"], nthreads=threads)
+            for name in ("fp32_plain", "fp64_plain"):
+                got = curv[name]["sampled"]
+                errs = {}
+                for key in ("qavg", "favg", "qface"):
+                    y = ref[key].reshape(len(ck["ids"]), -1)
+                    x = got[key].reshape(len(ck["ids"]), -1)
+                    errs[key] = float((np.abs(x - y).max(axis=1) / np.abs(y).max(axis=1)).max())
+                curv[name]["max_rel_err_vs_oracle"] = errs
+                curv[name]["checked_elements"] = int(len(ck["ids"]))
+                log(f"[bench] curvilinear {name}: max rel err vs oracle {errs}")
+            del ref
         cpu = {"value": k / t, "unit": "element-updates/s", "cores": threads, "kind": "oracle",
                "sample": f"{k} of the {E} elements (evenly spaced), FP64, {t:.1f} s"}
         log(f"[bench] CPU oracle: {k / t:.1f} el/s")
@@ -486,6 +544,9 @@ def main():
         "copy_reference": copy,
         "acoustic_n5": acoustic,
         "ader_dg_step": full_step,
+        "curvilinear": None if curv is None else {k: ({kk: vv for kk, vv in v.items() if kk != "sampled"}
+                                                      if isinstance(v, dict) else v)
+                                                  for k, v in curv.items() if k != "check"},
         "heterogeneous": hetero,
         "serving": serving,
         "latency_p50_ms": serving["load_80pct"]["p50_ms"] if serving else None,

@@ -27,7 +27,8 @@
  *                                                     coordinate 0 / 1 along the normal), (a, b) = the two
  *                                                     other axes, slower first: (z,y), (z,x), (y,x)
  *   params (presets)  [e][z][y][x][p] or [e][p] with STP_PARAM_PER_ELEMENT;
- *                     acoustic p = (rho, K), elastic p = (rho, lambda, mu)
+ *                     acoustic p = (rho, K), elastic p = (rho, lambda, mu), curvilinear elastic
+ *                     p = (rho, lambda, mu, G[0][0], G[0][1], ..., G[2][2]) (12 values, G row-major)
  *   A, B (generic)    [e][d][row s][col r][z][y][x] (node fastest, so that the threads of a workgroup, one
  *                     per node, read consecutive words), or [e][d][s][r] with STP_COEF_PER_ELEMENT
  *   src (point src)   [e][n^3 + m + N]: nodal projection P[node], amplitude a[s], time derivatives
@@ -39,6 +40,12 @@
  *   STP_ELASTIC   m = 9 (v_x, v_y, v_z, s_xx, s_yy, s_zz, s_xy, s_yz, s_xz):
  *                 rho v_t = div sigma,  sigma_t = lambda (div v) I + mu (grad v + grad v^T)
  *   STP_GENERIC   any 1 <= m <= 16: dense B_d (and optionally A_d) given per node or per element
+ *   STP_ELASTIC_CURV  m = 9, the elastic system on a curvilinear element (the benchmark physics of Sec. VI:
+ *                 9 wave quantities plus 3 material and 9 geometry parameters per point). The element is
+ *                 the image of the reference cube under a map x(xi); by the chain rule the system becomes
+ *                 q_t + sum_d B_d dq/dxi_d / h = 0 with B_d = sum_j G[d][j] M_j, M_j the Cartesian elastic
+ *                 matrices and G[d][j] = h dxi_d/dx_j the metric terms (the inverse Jacobian of the map
+ *                 scaled by the element size h; an undeformed cube of side h has G = I). No corrector.
  *
  * Precision: STP_FP64 computes and stores in double. STP_FP32 and STP_BF16X3 read and write float; their
  * derivative contractions run in FP32 (VALU) or as three BF16 products with FP32 accumulation (MFMA).
@@ -78,7 +85,7 @@ typedef enum {
     STP_E_BUSY = -5           /* serving queue full                                                  */
 } stp_status;
 
-typedef enum { STP_ACOUSTIC = 0, STP_ELASTIC = 1, STP_GENERIC = 2 } stp_physics;
+typedef enum { STP_ACOUSTIC = 0, STP_ELASTIC = 1, STP_GENERIC = 2, STP_ELASTIC_CURV = 3 } stp_physics;
 typedef enum { STP_FP64 = 0, STP_FP32 = 1, STP_BF16X3 = 2 } stp_prec;
 
 /* stp_class.flags */
@@ -93,7 +100,7 @@ enum {
 /* One element class: polynomial degree N (order; n = N+1 nodes per axis), quantity count m, physics. */
 typedef struct {
     int order;      /* N, 1..9                                                  */
-    int nquant;     /* m: 4 (acoustic), 9 (elastic), 1..16 (generic)            */
+    int nquant;     /* m: 4 (acoustic), 9 (elastic, curvilinear), 1..16 (generic) */
     int physics;    /* stp_physics                                              */
     unsigned flags; /* STP_* class flags                                        */
 } stp_class;

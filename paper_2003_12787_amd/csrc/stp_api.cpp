@@ -39,12 +39,14 @@ stp_status hip_fail(hipError_t e, const char* what)
 namespace {
 
 
+int param_count(int physics) { return physics == STP_ACOUSTIC ? 2 : (physics == STP_ELASTIC ? 3 : 12); }
+
 int quantities_read(const stp_class& c, int d)
 {
     (void)d;
     if (c.physics == STP_ACOUSTIC) return 2;  // p and v_d
     if (c.physics == STP_ELASTIC) return 6;   // three velocities and three stresses s_{d,i}
-    return c.nquant;
+    return c.nquant;                          // generic, curvilinear elastic: every quantity
 }
 
 }  // namespace
@@ -56,8 +58,8 @@ void class_cost(const stp_class& c, int io_bytes, double* bytes, double* flops)
     const bool hasA = c.physics == STP_GENERIC && (c.flags & STP_A_PRESENT);
     const bool src = (c.flags & STP_SRC_POINT) != 0;
     double in = n3 * m;
-    if (c.physics == STP_ACOUSTIC || c.physics == STP_ELASTIC) {
-        const double np = c.physics == STP_ACOUSTIC ? 2 : 3;
+    if (c.physics != STP_GENERIC) {
+        const double np = param_count(c.physics);
         in += (c.flags & STP_PARAM_PER_ELEMENT) ? np : n3 * np;
     } else {
         const double per = (c.flags & STP_COEF_PER_ELEMENT) ? 3 * m * m : 3 * n3 * m * m;
@@ -72,6 +74,7 @@ void class_cost(const stp_class& c, int io_bytes, double* bytes, double* flops)
             contr += 2.0 * n * n3 * quantities_read(c, d);
             if (c.physics == STP_ACOUSTIC) point += 2.0 * 2 * n3;
             else if (c.physics == STP_ELASTIC) point += 2.0 * 8 * n3;
+            else if (c.physics == STP_ELASTIC_CURV) point += 2.0 * 24 * n3;  // the 24 nonzeros of B_d
             else point += 2.0 * m * m * n3;
             if (hasA) {
                 contr += 2.0 * n * n3 * m;
@@ -99,7 +102,7 @@ stp_status validate_class(const stp_class& c)
         return fail(STP_E_UNSUPPORTED, "order N=%d outside 1..%d", c.order, kMaxOrder);
     if (c.physics == STP_ACOUSTIC) {
         if (c.nquant != 4) return fail(STP_E_UNSUPPORTED, "acoustic preset needs m=4 (got %d)", c.nquant);
-    } else if (c.physics == STP_ELASTIC) {
+    } else if (c.physics == STP_ELASTIC || c.physics == STP_ELASTIC_CURV) {
         if (c.nquant != 9) return fail(STP_E_UNSUPPORTED, "elastic preset needs m=9 (got %d)", c.nquant);
     } else if (c.physics == STP_GENERIC) {
         if (c.nquant < 1 || c.nquant > 16)
@@ -227,8 +230,8 @@ stp_status build_class(stp_plan_s* p, ClassState& cs)
     if (cs.cls.physics == STP_GENERIC)
         cs.size_coef = (cs.cls.flags & STP_COEF_PER_ELEMENT) ? 3 * m * m : 3 * n3 * m * m;
     else
-        cs.size_coef = (cs.cls.flags & STP_PARAM_PER_ELEMENT) ? (cs.cls.physics == STP_ACOUSTIC ? 2 : 3)
-                                                               : n3 * (cs.cls.physics == STP_ACOUSTIC ? 2 : 3);
+        cs.size_coef = (cs.cls.flags & STP_PARAM_PER_ELEMENT) ? param_count(cs.cls.physics)
+                                                               : n3 * param_count(cs.cls.physics);
     return STP_OK;
 }
 

@@ -234,6 +234,8 @@ extern "C" stp_status stp_correct(stp_plan_t p, const stp_step* st, void* stream
     const ClassState& cs = p->classes[0];
     const stp_class& c = cs.cls;
     const bool generic = c.physics == STP_GENERIC;
+    if (c.physics == STP_ELASTIC_CURV)
+        return fail(STP_E_UNSUPPORTED, "the corrector covers Cartesian meshes (no curvilinear elements)");
     if (generic ? !(c.flags & STP_COEF_PER_ELEMENT) : !(c.flags & STP_PARAM_PER_ELEMENT))
         return fail(STP_E_UNSUPPORTED, "the corrector needs per-element coefficients (STP_PARAM_PER_ELEMENT or "
                                        "STP_COEF_PER_ELEMENT)");

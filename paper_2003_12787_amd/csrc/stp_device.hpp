@@ -7,7 +7,7 @@
 
 namespace stp {
 
-enum Physics : int { kAcoustic = 0, kElastic = 1, kGeneric = 2 };
+enum Physics : int { kAcoustic = 0, kElastic = 1, kGeneric = 2, kElasticCurv = 3 };
 
 // Class flags (mirror the STP_* flags of stp.h).
 constexpr unsigned kParamPerElement = 1u << 0;
@@ -100,6 +100,14 @@ struct PhysTraits<kElastic> {
     }
 };
 
+// Elastic on a curvilinear element: B_d = sum_j G[d][j] M_j mixes every quantity into every direction.
+template <>
+struct PhysTraits<kElasticCurv> {
+    static constexpr int m = 9;
+    static constexpr int np = 12;  // rho, lambda, mu, G[3][3]
+    __host__ __device__ static constexpr bool needs(int, int) { return true; }
+};
+
 template <>
 struct PhysTraits<kGeneric> {
     static constexpr int m = 0;   // runtime
@@ -130,6 +138,23 @@ struct Material {
     }
 };
 
+// Curvilinear elastic: the elastic coefficients plus the metric terms G[d][j] = h dxi_d/dx_j of the node.
+template <typename T>
+struct Material<T, kElasticCurv> {
+    T c[4];  // as elastic: 1/(rho h), lambda/h, mu/h, (lambda + 2 mu)/h
+    T G[9];
+    __device__ inline void load(const T* par, double inv_h)
+    {
+        double rho = (double)par[0], lam = (double)par[1], mu = (double)par[2];
+        c[0] = (T)(inv_h / rho);
+        c[1] = (T)(lam * inv_h);
+        c[2] = (T)(mu * inv_h);
+        c[3] = (T)((lam + 2.0 * mu) * inv_h);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) G[k] = par[3 + k];
+    }
+};
+
 // r += -(1/h) B_d g  for a preset, with g the reference derivative along d of the quantities B_d reads.
 template <typename T, int PHYS, int D>
 __device__ inline void apply_ncp(const Material<T, PHYS>& mt, const T* g, T* r)
@@ -137,6 +162,32 @@ __device__ inline void apply_ncp(const Material<T, PHYS>& mt, const T* g, T* r)
     if constexpr (PHYS == kAcoustic) {
         r[0] = fma(mt.c[0], g[1 + D], r[0]);  // p_t = -K dv_d/dx_d
         r[1 + D] = fma(mt.c[1], g[0], r[1 + D]);  // v_d,t = -(1/rho) dp/dx_d
+    } else if constexpr (PHYS == kElasticCurv) {
+        // The reference derivative g along xi_d contributes G[d][j] g / h to the physical derivative along
+        // x_j; r += the elastic operator of that gradient (1/h is folded into c).
+        using P = PhysTraits<kElastic>;
+        const T G0 = mt.G[3 * D], G1 = mt.G[3 * D + 1], G2 = mt.G[3 * D + 2];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {  // rho v_i,t = sum_j d s_ij / dx_j
+            T t = G0 * g[P::sig(i, 0)];
+            t = fma(G1, g[P::sig(i, 1)], t);
+            t = fma(G2, g[P::sig(i, 2)], t);
+            r[i] = fma(mt.c[0], t, r[i]);
+        }
+        T dv = G0 * g[0];  // div v
+        dv = fma(G1, g[1], dv);
+        dv = fma(G2, g[2], dv);
+        const T Gd[3] = {G0, G1, G2};
+        const T mu2 = mt.c[3] - mt.c[1];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {  // s_ii,t = lambda div v + 2 mu dv_i/dx_i
+            r[3 + i] = fma(mt.c[1], dv, r[3 + i]);
+            r[3 + i] = fma(mu2 * Gd[i], g[i], r[3 + i]);
+        }
+        // s_ij,t = mu (dv_i/dx_j + dv_j/dx_i) for (i, j) = (x, y), (y, z), (x, z)
+        r[6] = fma(mt.c[2], fma(G1, g[0], G0 * g[1]), r[6]);
+        r[7] = fma(mt.c[2], fma(G2, g[1], G1 * g[2]), r[7]);
+        r[8] = fma(mt.c[2], fma(G2, g[0], G0 * g[2]), r[8]);
     } else {
         using P = PhysTraits<kElastic>;
 #pragma unroll

@@ -55,6 +55,7 @@ __host__ __device__ inline int bucket_of(int physics, int m)
 {
     if (physics == kAcoustic) return 0;
     if (physics == kElastic) return 1;
+    if (physics == kElasticCurv) return -1;
     if (m == 4) return 2;
     if (m == 9) return 3;
     return -1;

@@ -114,7 +114,8 @@ struct Eligibility {
 
 Eligibility eligible(const stp_plan_s* p, const ClassState& cs)
 {
-    const bool preset = cs.cls.physics != STP_GENERIC;
+    // the fused and MFMA kernels implement the Cartesian presets
+    const bool preset = cs.cls.physics == STP_ACOUSTIC || cs.cls.physics == STP_ELASTIC;
     const bool f32io = p->prec != STP_FP64;
     const bool simple = preset && f32io && !cs.acc64 && !(cs.cls.flags & STP_SRC_POINT);
     return {simple && cs.cls.order <= 7, simple && cs.cls.order == 7 && p->prec == STP_BF16X3};

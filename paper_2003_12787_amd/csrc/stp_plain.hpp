@@ -376,7 +376,8 @@ KernelInfo plain_by_order(int N)
     }
 }
 
-// Presets and the generic classes with m = 4 or m = 9 (compiled with m fixed). The generic classes with
+// Presets (acoustic, elastic, curvilinear elastic) and the generic classes with m = 4 or m = 9 (compiled with
+// m fixed). The generic classes with
 // another m use a run-time quantity count bounded by 4, 9 or 16 (plain_generic_rt), instantiated in
 // translation units of their own so that the library builds in parallel.
 template <typename T, typename ACC>
@@ -384,6 +385,7 @@ KernelInfo plain_by_physics(int N, int physics, int m)
 {
     if (physics == kAcoustic) return plain_by_order<T, ACC, kAcoustic, 4>(N);
     if (physics == kElastic) return plain_by_order<T, ACC, kElastic, 9>(N);
+    if (physics == kElasticCurv) return plain_by_order<T, ACC, kElasticCurv, 9>(N);
     if (m == 4) return plain_by_order<T, ACC, kGeneric, 4, true>(N);
     if (m == 9) return plain_by_order<T, ACC, kGeneric, 9, true>(N);
     return KernelInfo{};

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(PKG, "libstp.so")
 # stp_status
 OK, PENDING, E_INVAL, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_BUSY = 0, 1, -1, -2, -3, -4, -5
 # stp_physics / stp_prec
-ACOUSTIC, ELASTIC, GENERIC = 0, 1, 2
+ACOUSTIC, ELASTIC, GENERIC, ELASTIC_CURV = 0, 1, 2, 3
 FP64, FP32, BF16X3 = 0, 1, 2
 # class flags
 PARAM_PER_ELEMENT, A_PRESENT, COEF_PER_ELEMENT, FAVG_SUM, SRC_POINT = 1, 2, 4, 8, 16

@@ -98,25 +98,57 @@ def grid_of(nelem: int):
     return g, g, g
 
 
+def _map_terms(xi, L, eps, sin, cos):
+    """The deformation of curved_map on coordinate arrays xi = [xi_0, xi_1, xi_2] (broadcastable; numpy or
+    torch, with their sin and cos): returns x as a list of 3 arrays and J as nested lists J[i][j]."""
+    a = min(L) / (2 * math.pi)
+    k = [2 * math.pi / Lj for Lj in L]
+    s = [sin(k[j] * xi[j]) for j in range(3)]
+    c = [cos(k[j] * xi[j]) for j in range(3)]
+    x, J = [], [[None] * 3 for _ in range(3)]
+    for i in range(3):
+        j1, j2 = [j for j in range(3) if j != i]
+        x.append(xi[i] + eps * a * s[j1] * s[j2])
+        J[i][i] = 1.0
+        J[i][j1] = eps * a * k[j1] * c[j1] * s[j2]
+        J[i][j2] = eps * a * k[j2] * s[j1] * c[j2]
+    return x, J
+
+
 def curved_map(xi, L, eps):
     """A smooth, periodic deformation of the box [0, L_0] x [0, L_1] x [0, L_2] (xi [..., 3] -> x [..., 3]) and
     its Jacobian J[..., i, j] = dx_i/dxi_j:
         x_i = xi_i + eps a prod_{j != i} sin(2 pi xi_j / L_j),   a = min(L) / (2 pi).
     Each off-diagonal entry of J is at most eps in magnitude, so J is invertible for eps < 1/2."""
-    L = np.asarray(L, dtype=np.float64)
-    a = L.min() / (2 * math.pi)
-    k = 2 * math.pi / L
-    s = np.sin(xi * k)
-    c = np.cos(xi * k)
-    x = xi.copy()
-    J = np.zeros(xi.shape + (3,))
+    x, J = _map_terms([xi[..., j] for j in range(3)], [float(v) for v in L], eps, np.sin, np.cos)
+    Jm = np.zeros(xi.shape + (3,))
     for i in range(3):
-        j1, j2 = [j for j in range(3) if j != i]
-        x[..., i] += eps * a * s[..., j1] * s[..., j2]
-        J[..., i, i] = 1.0
-        J[..., i, j1] = eps * a * k[j1] * c[..., j1] * s[..., j2]
-        J[..., i, j2] = eps * a * k[j2] * s[..., j1] * c[..., j2]
-    return x, J
+        for j in range(3):
+            Jm[..., i, j] = J[i][j]
+    return np.stack(x, axis=-1), Jm
+
+
+def _inverse3(J):
+    """Inverse of 3 x 3 matrices given as nested lists J[i][j] of equally shaped arrays (adjugate / det)."""
+    c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1]
+    c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2]
+    c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0]
+    det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02
+    return [[c00 / det, (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det, (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det],
+            [c01 / det, (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det, (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det],
+            [c02 / det, (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det, (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det]]
+
+
+def _element_coords(N, grid, h, e, t):
+    """Global reference coordinates [xi_0, xi_1, xi_2], each [E, n^3], of the nodes of elements e of the grid;
+    t are the 1D node positions."""
+    nx, ny, _ = grid
+    n = N + 1
+    ix, iy, iz = e % nx, (e // nx) % ny, e // (nx * ny)
+    tz, ty, tx = t.reshape(n, 1, 1), t.reshape(1, n, 1), t.reshape(1, 1, n)
+    zero = 0 * tx * ty * tz
+    node = [(tx + zero).reshape(1, -1), (ty + zero).reshape(1, -1), (tz + zero).reshape(1, -1)]
+    return [(ix[:, None] + node[0]) * h, (iy[:, None] + node[1]) * h, (iz[:, None] + node[2]) * h]
 
 
 def curvilinear_geometry(N: int, grid, h: float, eps: float, elements=None):
@@ -124,16 +156,58 @@ def curvilinear_geometry(N: int, grid, h: float, eps: float, elements=None):
     dx/dxi_global) of the elements of a grid (nx, ny, nz) of cubes of side h under curved_map; element
     e = (iz ny + iy) nx + ix, nodes (z, y, x) at Gauss-Legendre points."""
     nx, ny, nz = grid
-    n = N + 1
     e = np.arange(nx * ny * nz) if elements is None else np.asarray(elements)
-    t = _node_positions(n)
-    Z, Y, X = np.meshgrid(t, t, t, indexing="ij")
-    xi = np.empty((len(e), n ** 3, 3))
-    xi[..., 0] = ((e % nx)[:, None] + X.reshape(1, -1)) * h
-    xi[..., 1] = (((e // nx) % ny)[:, None] + Y.reshape(1, -1)) * h
-    xi[..., 2] = ((e // (nx * ny))[:, None] + Z.reshape(1, -1)) * h
-    x, J = curved_map(xi, (nx * h, ny * h, nz * h), eps)
-    return x, np.linalg.inv(J)
+    xi = _element_coords(N, grid, h, e, _node_positions(N + 1))
+    x, J = _map_terms(xi, (nx * h, ny * h, nz * h), eps, np.sin, np.cos)
+    Gl = _inverse3(J)
+    X = np.stack(x, axis=-1)
+    G = np.empty(X.shape + (3,))
+    for i in range(3):
+        for j in range(3):
+            G[..., i, j] = Gl[i][j]
+    return X, G
+
+
+def curvilinear_device(N: int, nelem: int, seed: int, device="cuda", h: float = 1.0, eps: float = 0.2):
+    """The curvilinear workload of curvilinear_batch generated on the device (torch, FP64 arithmetic, FP32
+    results): the same grid, map and metric; material rho ~ U[2,3], lambda ~ U[1,4], mu ~ U[1,3] and
+    Q ~ N(0, 1) from a torch generator seeded with `seed`. Returns (Q [E, n^3, 9], params [E, n^3, 12], dt)."""
+    import torch
+    grid = grid_of(nelem)
+    n3 = (N + 1) ** 3
+    t = torch.from_numpy(_node_positions(N + 1)).to(device)
+    e = torch.arange(nelem, device=device, dtype=torch.float64)
+    ef = torch.floor
+    nx, ny, nz = grid
+    ix = e - nx * ef(e / nx)
+    iy = ef(e / nx) - ny * ef(e / (nx * ny))
+    iz = ef(e / (nx * ny))
+    tz, ty, tx = t.reshape(-1, 1, 1), t.reshape(1, -1, 1), t.reshape(1, 1, -1)
+    zero = 0 * tx * ty * tz
+    xi = [(ix[:, None] + (tx + zero).reshape(1, -1)) * h, (iy[:, None] + (ty + zero).reshape(1, -1)) * h,
+          (iz[:, None] + (tz + zero).reshape(1, -1)) * h]
+    _, J = _map_terms(xi, (nx * h, ny * h, nz * h), eps, torch.sin, torch.cos)
+    del xi
+    Gl = _inverse3(J)
+    del J
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    u = torch.rand((nelem, n3, 3), generator=g, device=device, dtype=torch.float64)
+    params = torch.empty((nelem, n3, 12), device=device, dtype=torch.float32)
+    params[..., 0] = 2.0 + u[..., 0]
+    params[..., 1] = 1.0 + 3.0 * u[..., 1]
+    params[..., 2] = 1.0 + 2.0 * u[..., 2]
+    gmax = 0.0
+    for d in range(3):
+        gmax = max(gmax, float((Gl[d][0].abs() + Gl[d][1].abs() + Gl[d][2].abs()).max()))
+        for j in range(3):
+            params[..., 3 + 3 * d + j] = Gl[d][j]
+    del Gl, u
+    Q = torch.randn((nelem, n3, 9), generator=g, device=device, dtype=torch.float32)
+    p = params.double()
+    cp = float(torch.sqrt((p[..., 1] + 2 * p[..., 2]) / p[..., 0]).max())
+    del p
+    return Q, params, cfl_dt(N, h, cp * gmax)
 
 
 def curvilinear_batch(N: int, nelem: int, seed: int, h: float = 1.0, eps: float = 0.2, per_node: bool = True,
@@ -152,7 +226,7 @@ def curvilinear_batch(N: int, nelem: int, seed: int, h: float = 1.0, eps: float 
     par = np.concatenate([mat, G.reshape(G.shape[:-2] + (9,))], axis=-1)
     Q = q_scale * rng.standard_normal((nelem, n3, 9))
     cp = np.sqrt((mat[..., 1] + 2 * mat[..., 2]) / mat[..., 0]).max() if nelem else 1.0
-    gmax = np.abs(G).sum(axis=-1).max() if nelem else 1.0
+    gmax = (np.abs(G[..., 0]) + np.abs(G[..., 1]) + np.abs(G[..., 2])).max() if nelem else 1.0
     dt = np.full(nelem, cfl_dt(N, h, cp * gmax))
     return Batch(N, 9, ELASTIC_CURV, Q, dt, np.full(nelem, h), params=par, coef_per_element=not per_node)
 

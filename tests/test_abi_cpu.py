@@ -53,6 +53,8 @@ def _desc(classes, prec=stp.FP32, device=0, variant=0):
     ([(3, 9, stp.ELASTIC, stp.A_PRESENT)], stp.FP32, stp.E_INVAL),  # A only for generic
     ([(3, 4, stp.GENERIC, stp.PARAM_PER_ELEMENT)], stp.FP32, stp.E_INVAL),
     ([(3, 9, stp.ELASTIC, 0)], 7, stp.E_INVAL),                  # unknown precision
+    ([(3, 4, stp.ELASTIC_CURV, 0)], stp.FP32, stp.E_UNSUPPORTED),  # curvilinear elastic needs m = 9
+    ([(3, 9, stp.ELASTIC_CURV, stp.COEF_PER_ELEMENT)], stp.FP32, stp.E_INVAL),  # params, not A/B
 ])
 def test_plan_rejects_invalid_classes_on_host(L, classes, prec, expect):
     d = _desc(classes, prec)

@@ -87,3 +87,29 @@ def test_interleave_offsets_round_trip():
     order = np.argsort(mb.off_q)
     assert np.all(np.diff(mb.off_q[order]) == np.array(sq)[order][:-1])
     assert mb.size_q == sum(sq)
+
+
+def test_curvilinear_geometry_matches_the_map_and_its_inverse_jacobian():
+    """The per-element metric terms are the inverse of the map's Jacobian at the nodes (numpy's inverse),
+    the node positions are the map of the grid points, and the device generator reproduces the metric."""
+    N, grid, h, eps = 3, (4, 3, 2), 0.5, 0.3
+    x, G = W.curvilinear_geometry(N, grid, h, eps)
+    t = W._node_positions(N + 1)
+    e = np.arange(24)
+    Z, Y, X = np.meshgrid(t, t, t, indexing="ij")
+    xi = np.stack([((e % 4)[:, None] + X.reshape(1, -1)) * h, (((e // 4) % 3)[:, None] + Y.reshape(1, -1)) * h,
+                   ((e // 12)[:, None] + Z.reshape(1, -1)) * h], axis=-1)
+    xr, J = W.curved_map(xi, (2.0, 1.5, 1.0), eps)
+    assert np.abs(x - xr).max() < 1e-14
+    assert np.abs(G - np.linalg.inv(J)).max() < 1e-13
+    _, Gs = W.curvilinear_geometry(N, grid, h, eps, elements=[5, 17])
+    assert np.array_equal(Gs, G[[5, 17]])
+    # the map is a periodic deformation: x - xi is periodic, and every J is invertible
+    assert np.linalg.det(J).min() > 0.5
+    import torch
+    Q, par, dt = W.curvilinear_device(N, 16, 7, device="cpu")
+    _, Gg = W.curvilinear_geometry(N, W.grid_of(16), 1.0, 0.2)
+    assert par.shape == (16, 64, 12) and Q.shape == (16, 64, 9) and dt > 0
+    assert np.abs(par[..., 3:].double().numpy() - Gg.reshape(16, 64, 9)).max() < 1e-6
+    p = par.double().numpy()
+    assert p[..., 0].min() >= 2 and p[..., 0].max() <= 3 and p[..., 1].min() >= 1 and p[..., 2].max() <= 3
