@@ -200,8 +200,9 @@ def bench_full_step(args, torch, stp, W):
 def bench_curvilinear(args, torch, stp, W):
     """Elastic waves on curvilinear elements (the benchmark physics of Sec. VI: 9 wave quantities and 12
     parameters per node, material and metric terms), N = 7, the elements of a deformed 64 x 32 x 32 box,
-    inputs generated on the device. The FP32 and FP64 plain kernels (the fused and MFMA kernels cover the
-    Cartesian presets). Returns the timings and, for the CPU leg, the inputs and outputs of 256 elements."""
+    inputs generated on the device. The split-BF16x3 MFMA kernel and the FP32 and FP64 plain kernels (the fused
+    kernel covers the Cartesian presets). Returns the timings and, for the CPU leg, the inputs and outputs of
+    256 elements."""
     N, E, m = 7, args.nelem, 9
     n3, n2 = (N + 1) ** 3, (N + 1) ** 2
     log(f"[bench] curvilinear elastic N=7, {E} elements, generating on the device")
@@ -212,9 +213,10 @@ def bench_curvilinear(args, torch, stp, W):
                        f"{E} elements of a deformed {'x'.join(map(str, W.grid_of(E)))} box, FP32 I/O",
            "nelem": E, "check": {"ids": ids, "Q": Q.index_select(0, tid).double().cpu().numpy(),
                                   "params": par.index_select(0, tid).double().cpu().numpy(), "dt": dt}}
-    for name, prec in (("fp32_plain", stp.FP32), ("fp64_plain", stp.FP64)):
+    for name, prec, var in (("bf16x3_mfma", stp.BF16X3, stp.VARIANT_MFMA), ("fp32_plain", stp.FP32, stp.VARIANT_PLAIN),
+                            ("fp64_plain", stp.FP64, stp.VARIANT_PLAIN)):
         tdt = torch.float64 if prec == stp.FP64 else torch.float32
-        plan = stp.Plan([(N, m, stp.ELASTIC_CURV, 0)], prec=prec)
+        plan = stp.Plan([(N, m, stp.ELASTIC_CURV, 0)], prec=prec, variant=var)
         q, p = Q.to(tdt), par.to(tdt)
         qavg = torch.empty((E, n3, m), device="cuda", dtype=tdt)
         favg = torch.empty((E, 3, n3, m), device="cuda", dtype=tdt)
@@ -227,6 +229,7 @@ def bench_curvilinear(args, torch, stp, W):
                      "hbm_gbs_algorithmic": bytes_el * E / (ms * 1e-3) / 1e9,
                      "tflops": flops_el * E / (ms * 1e-3) / 1e12,
                      "alu_frac": flops_el * E / (ms * 1e-3) / 1e12 / ALU_PEAK_TFS["f64" if prec == stp.FP64 else "f32"],
+                     "hbm_frac": bytes_el * E / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "bytes_per_element": bytes_el, "flops_per_element": flops_el,
                      "sampled": {k: v.index_select(0, tid).double().cpu().numpy()
                                  for k, v in (("qavg", qavg), ("favg", favg), ("qface", qface))}}
@@ -237,6 +240,7 @@ def bench_curvilinear(args, torch, stp, W):
     del Q, par
     torch.cuda.empty_cache()
     res["speedup_fp32_vs_fp64"] = res["fp64_plain"]["ms"] / res["fp32_plain"]["ms"]
+    res["speedup_mfma_vs_fp32_plain"] = res["fp32_plain"]["ms"] / res["bf16x3_mfma"]["ms"]
     return res
 
 
@@ -507,7 +511,7 @@ def main():
         if curv is not None:  # sampled parity of the curvilinear workload
             ck = curv["check"]
             ref = oracle.stp(7, W.ELASTIC_CURV, ck["Q"], ck["dt"], 1.0, params=ck["params"], nthreads=threads)
-            for name in ("fp32_plain", "fp64_plain"):
+            for name in ("bf16x3_mfma", "fp32_plain", "fp64_plain"):
                 got = curv[name]["sampled"]
                 errs = {}
                 for key in ("qavg", "favg", "qface"):

@@ -31,6 +31,15 @@ struct Sets<kElastic> {
     __host__ __device__ static constexpr int dq(int d, int k) { return k < 3 ? k : PhysTraits<kElastic>::sig(d, k - 3); }
 };
 
+// curvilinear elastic: every quantity is differentiated in every direction (used by the MFMA kernel)
+template <>
+struct Sets<kElasticCurv> {
+    static constexpr int NPS = 9;
+    static constexpr int NG = 9;
+    __host__ __device__ static constexpr int slot(int q) { return q; }
+    __host__ __device__ static constexpr int dq(int, int k) { return k; }
+};
+
 template <>
 struct Sets<kAcoustic> {
     static constexpr int NPS = 3;  // p, v_y, v_z

@@ -114,11 +114,13 @@ struct Eligibility {
 
 Eligibility eligible(const stp_plan_s* p, const ClassState& cs)
 {
-    // the fused and MFMA kernels implement the Cartesian presets
-    const bool preset = cs.cls.physics == STP_ACOUSTIC || cs.cls.physics == STP_ELASTIC;
+    // the fused kernel implements the Cartesian presets, the MFMA kernel also curvilinear elastic elements
+    const bool cart = cs.cls.physics == STP_ACOUSTIC || cs.cls.physics == STP_ELASTIC;
+    const bool curv = cs.cls.physics == STP_ELASTIC_CURV;
     const bool f32io = p->prec != STP_FP64;
-    const bool simple = preset && f32io && !cs.acc64 && !(cs.cls.flags & STP_SRC_POINT);
-    return {simple && cs.cls.order <= 7, simple && cs.cls.order == 7 && p->prec == STP_BF16X3};
+    const bool simple = f32io && !cs.acc64 && !(cs.cls.flags & STP_SRC_POINT);
+    return {simple && cart && cs.cls.order <= 7,
+            simple && (cart || curv) && cs.cls.order == 7 && p->prec == STP_BF16X3};
 }
 
 }  // namespace

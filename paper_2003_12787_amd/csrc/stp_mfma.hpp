@@ -1,5 +1,5 @@
 // stp_mfma.hpp -- predictor kernel with the derivative contractions on the matrix cores (MFMA), for the
-// physics presets at order N = 7 (8 nodes per axis), FP32 I/O.
+// physics presets (acoustic, elastic, curvilinear elastic) at order N = 7 (8 nodes per axis), FP32 I/O.
 //
 // Mathematics as in the other kernels (Sec. II-A, Eq. (4), Fig. 5 recompute of favg, Sec. II-B faces). Only
 // the 1D derivative u -> D u (the sum-factorised contraction of Sec. III-B) runs on MFMA, as split-BF16
@@ -88,19 +88,70 @@ struct Mfma8 {
     static constexpr int WG = 128;  // one element per workgroup (two waves)
     using S = fused::Sets<PHYS>;
     static constexpr int NPS = S::NPS, NG = S::NG;
+    // Exchange-buffer slots: the derivatives of one direction come back in chunks of NGX quantities (all of
+    // them at once for the Cartesian presets; 5 + 4 for curvilinear elements, which differentiate all 9
+    // quantities in every direction) so that four elements per CU still fit in LDS.
+    static constexpr int NGX = NG <= 6 ? NG : 5;
+    static constexpr int C1 = NGX;  // end of the first chunk
     static constexpr int SLOT = n3;  // one quantity's tile, swizzled (at()): 4 elements per CU fit in LDS
-    static constexpr int ELDS = (NPS + NG) * SLOT;
+    static constexpr int ELDS = (NPS + NGX) * SLOT;
     static constexpr int STAGE = 16 * n * M;  // per-wave staging of 16 lines of an output block (floats)
     static constexpr int LDS_FLOATS = ELDS + 2 * STAGE;
     static constexpr int FACE_OFF = M * SLOT;  // face staging after the q-bar tile of the face pass
     static_assert(FACE_OFF + 6 * n2 * M <= LDS_FLOATS, "face staging fits the LDS region");
-    static_assert(NPS + NG >= M, "face pass reuses the tile for all quantities");
+    static_assert(NPS + NGX >= M, "face pass reuses the tile for all quantities");
+
+    // Row D of the metric terms at the lane's 4 nodes (curvilinear elements): re-read from the parameter array
+    // for each direction (the laundered offset keeps the loads inside the Taylor loop; L2 holds the element's
+    // parameters) instead of holding 36 registers for the whole kernel.
+    using GRow = float[4][3];
+    template <int D>
+    __device__ static inline void load_grow(const float* gp, int stride, GRow& Gd)
+    {
+        if constexpr (PHYS == kElasticCurv) {
+            const float* q = gp + opaque_zero() + 3 + 3 * D;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) Gd[t][j] = q[t * stride + j];
+        }
+    }
 
     // r[.][t] += contribution of the derivative g (quantity dq(D, K)) at the lane's 4 nodes
     template <int D, int K>
-    __device__ static inline void ncp(const Material<float, PHYS> (&mt)[4], const float (&g)[4], float (&r)[M][4])
+    __device__ static inline void ncp(const Material<float, PHYS> (&mt)[4], const GRow& Gd, const float (&g)[4],
+                                      float (&r)[M][4])
     {
-        if constexpr (PHYS == kElastic) {
+        if constexpr (PHYS == kElasticCurv) {
+            // g = d/dxi_D of quantity K contributes G[D][j] g / h to its derivative along x_j (1/h is in c);
+            // the elastic operator's column K of sum_j G[D][j] M_j:
+            using P = PhysTraits<kElastic>;
+            if constexpr (K < 3) {  // v_K: s_KK <- (lam+2mu) dv_K/dx_K, s_ii <- lam dv_K/dx_K, s_jK <- mu dv_K/dx_j
+                constexpr int j1 = (K + 1) % 3, j2 = (K + 2) % 3;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const float gk = Gd[t][K] * g[t];
+                    const float gm = mt[t].c[2] * g[t];
+                    r[3 + K][t] = fma(mt[t].c[3], gk, r[3 + K][t]);
+                    r[3 + j1][t] = fma(mt[t].c[1], gk, r[3 + j1][t]);
+                    r[3 + j2][t] = fma(mt[t].c[1], gk, r[3 + j2][t]);
+                    r[P::sig(j1, K)][t] = fma(Gd[t][j1], gm, r[P::sig(j1, K)][t]);
+                    r[P::sig(j2, K)][t] = fma(Gd[t][j2], gm, r[P::sig(j2, K)][t]);
+                }
+            } else if constexpr (K < 6) {  // s_aa: v_a <- (1/rho) ds_aa/dx_a
+                constexpr int a = K - 3;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) r[a][t] = fma(mt[t].c[0] * Gd[t][a], g[t], r[a][t]);
+            } else {  // s_ab (a != b): v_a <- (1/rho) ds_ab/dx_b, v_b <- (1/rho) ds_ab/dx_a
+                constexpr int a = K == 6 ? 0 : (K == 7 ? 1 : 0), b = K == 6 ? 1 : 2;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const float gr = mt[t].c[0] * g[t];
+                    r[a][t] = fma(Gd[t][b], gr, r[a][t]);
+                    r[b][t] = fma(Gd[t][a], gr, r[b][t]);
+                }
+            }
+        } else if constexpr (PHYS == kElastic) {
             using P = PhysTraits<kElastic>;
             if constexpr (K < 3) {
                 if constexpr (K == D) {
@@ -132,15 +183,16 @@ struct Mfma8 {
     }
 
     template <int K = 0>
-    __device__ static inline void xpass(const AOps& A, const Material<float, PHYS> (&mt)[4], const float (&p)[M][4],
+    __device__ static inline void xpass(const AOps& A, const Material<float, PHYS> (&mt)[4], const GRow& Gd,
+                                        const float (&p)[M][4],
                                         float (&r)[M][4])
     {
         if constexpr (K < NG) {
             float g[4];
             deriv_mfma(A, p[S::dq(0, K)], g);
-            ncp<0, K>(mt, g, r);
+            ncp<0, K>(mt, Gd, g, r);
             __builtin_amdgcn_sched_barrier(0);  // one quantity at a time: bounds the live registers
-            xpass<K + 1>(A, mt, p, r);
+            xpass<K + 1>(A, mt, Gd, p, r);
         }
     }
 
@@ -190,8 +242,9 @@ struct Mfma8 {
         return f;
     }
 
-    // y- or z-role: lines (a, b) = (z, x) resp. (y, x), nodes 4h..4h+3 along the line
-    template <int D>
+    // y- or z-role: lines (a, b) = (z, x) resp. (y, x), nodes 4h..4h+3 along the line; derivatives of the
+    // quantities dq(D, k), k in [K0, K1), into exchange slots k - K0
+    template <int D, int K0, int K1>
     __device__ static inline void transposed(const AOps& A, const float* P0, float* G0, const Offs& f)
     {
         const int z0 = opaque_zero();
@@ -199,29 +252,48 @@ struct Mfma8 {
         float* G = G0 + z0;
         const int(&off)[4] = D == 1 ? f.y : f.z;
 #pragma unroll
-        for (int k = 0; k < NG; ++k) {
+        for (int k = K0; k < K1; ++k) {
             const int s = S::slot(S::dq(D, k));
             float u[4], g[4];
 #pragma unroll
             for (int t = 0; t < 4; ++t) u[t] = P[s * SLOT + off[t]];
             deriv_mfma(A, u, g);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) G[k * SLOT + off[t]] = g[t];
+            for (int t = 0; t < 4; ++t) G[(k - K0) * SLOT + off[t]] = g[t];
             __builtin_amdgcn_sched_barrier(0);
         }
     }
 
-    template <int D, int K = 0>
+    template <int D, int K0, int K1, int K = K0>
     __device__ static inline void gather(const float* G0, const Offs& f, const Material<float, PHYS> (&mt)[4],
-                                         float (&r)[M][4])
+                                         const GRow& Gd, float (&r)[M][4])
     {
-        const float* G = G0 + (K == 0 ? opaque_zero() : 0);
-        if constexpr (K < NG) {
+        const float* G = G0 + (K == K0 ? opaque_zero() : 0);
+        if constexpr (K < K1) {
             float g[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) g[t] = G[K * SLOT + f.o[t]];
-            ncp<D, K>(mt, g, r);
-            gather<D, K + 1>(G, f, mt, r);
+            for (int t = 0; t < 4; ++t) g[t] = G[(K - K0) * SLOT + f.o[t]];
+            ncp<D, K>(mt, Gd, g, r);
+            gather<D, K0, K1, K + 1>(G, f, mt, Gd, r);
+        }
+    }
+
+    // r += the y- or z-contributions, once every lane has written the first chunk of direction D (transposed
+    // <D, 0, C1>) and passed a barrier; the other chunk, if any, goes through the exchange buffer here. gp, gs:
+    // the lane's first node's parameters and the per-node stride (0 for per-element parameters).
+    template <int D>
+    __device__ static inline void finish_dir(const AOps& A, const float* P, float* G, const Offs& f,
+                                             const Material<float, PHYS> (&mt)[4], const float* gp, int gs,
+                                             float (&r)[M][4])
+    {
+        GRow Gd;
+        load_grow<D>(gp, gs, Gd);
+        gather<D, 0, C1>(G, f, mt, Gd, r);
+        if constexpr (NG > NGX) {
+            __syncthreads();
+            transposed<D, C1, NG>(A, P, G, f);
+            __syncthreads();
+            gather<D, C1, NG>(G, f, mt, Gd, r);
         }
     }
 
@@ -341,6 +413,8 @@ struct Mfma8 {
 #pragma unroll
                 for (int t = 0; t < 4; ++t) mt[t].load(per_elem ? par : par + (node0 + t) * NP, inv_h);
             }
+            const float* gp = static_cast<const float*>(a.params) + er.coef + (per_elem ? 0 : node0 * NP);
+            const int gs = per_elem ? 0 : NP;
 #pragma unroll
             for (int q = 0; q < M; ++q)
 #pragma unroll
@@ -356,14 +430,18 @@ struct Mfma8 {
                 for (int q = 0; q < M; ++q)
 #pragma unroll
                     for (int t = 0; t < 4; ++t) r[q][t] = 0.f;
-                transposed<1>(A, P, G, off);
-                xpass(A, mt, p, r);
+                transposed<1, 0, C1>(A, P, G, off);
+                {
+                    GRow G0;
+                    load_grow<0>(gp, gs, G0);
+                    xpass(A, mt, G0, p, r);
+                }
                 __syncthreads();
-                gather<1>(G, off, mt, r);
+                finish_dir<1>(A, P, G, off, mt, gp, gs, r);
                 __syncthreads();
-                transposed<2>(A, P, G, off);
+                transposed<2, 0, C1>(A, P, G, off);
                 __syncthreads();
-                gather<2>(G, off, mt, r);
+                finish_dir<2>(A, P, G, off, mt, gp, gs, r);
                 w = w * dt / (float)(o + 1);
 #pragma unroll
                 for (int q = 0; q < M; ++q)
@@ -388,8 +466,12 @@ struct Mfma8 {
                 for (int q = 0; q < M; ++q)
 #pragma unroll
                     for (int t = 0; t < 4; ++t) fx[q][t] = 0.f;
-                transposed<1>(A, P, G, off);
-                xpass(A, mt, qb, fx);
+                transposed<1, 0, C1>(A, P, G, off);
+                {
+                    GRow G0;
+                    load_grow<0>(gp, gs, G0);
+                    xpass(A, mt, G0, qb, fx);
+                }
                 float* fav = static_cast<float*>(a.favg) + (fsum ? er.q : 3 * er.q) + wbase;
                 if (!fsum) {
                     store_block(Sw, fav, fx, l, g, c, h, al);
@@ -399,7 +481,7 @@ struct Mfma8 {
                         for (int t = 0; t < 4; ++t) fx[q][t] = 0.f;
                 }
                 __syncthreads();
-                gather<1>(G, off, mt, fx);
+                finish_dir<1>(A, P, G, off, mt, gp, gs, fx);
                 if (!fsum) {
                     store_block(Sw, fav + (int64_t)n3 * M, fx, l, g, c, h, al);
 #pragma unroll
@@ -408,9 +490,9 @@ struct Mfma8 {
                         for (int t = 0; t < 4; ++t) fx[q][t] = 0.f;
                 }
                 __syncthreads();
-                transposed<2>(A, P, G, off);
+                transposed<2, 0, C1>(A, P, G, off);
                 __syncthreads();
-                gather<2>(G, off, mt, fx);
+                finish_dir<2>(A, P, G, off, mt, gp, gs, fx);
                 store_block(Sw, fsum ? fav : fav + 2 * (int64_t)n3 * M, fx, l, g, c, h, al);
             }
             // faces: partial sums over the lane's 4 nodes, completed with the other half-line (lane ^ 16); the

@@ -7,6 +7,7 @@ KernelInfo mfma_kernel_n7(int physics)
 {
     if (physics == kElastic) return mfma::mfma_info<kElastic>();
     if (physics == kAcoustic) return mfma::mfma_info<kAcoustic>();
+    if (physics == kElasticCurv) return mfma::mfma_info<kElasticCurv>();
     return KernelInfo{};
 }
 

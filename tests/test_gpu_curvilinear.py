@@ -1,7 +1,7 @@
 """GPU parity of curvilinear elastic elements (STP_ELASTIC_CURV: material and metric terms per node) against
-the oracle, through the C ABI: every precision of the plain kernel, per-node (curved) and per-element
-(affine) parameters, a heterogeneous batch mixing curvilinear and Cartesian classes, and the
-unsupported combinations."""
+the oracle, through the C ABI: every precision of the plain kernel, the split-BF16x3 MFMA kernel at N = 7,
+per-node (curved) and per-element (affine) parameters, a heterogeneous batch mixing curvilinear and
+Cartesian classes, and the unsupported combinations."""
 import sys
 
 import numpy as np
@@ -30,8 +30,11 @@ def say(*a):
 
 def check(b, prec, acc64_min_order=0, variant=stp.VARIANT_AUTO):
     plan = stp.Plan([runner.class_of(b)], prec=prec, acc64_min_order=acc64_min_order, variant=variant)
+    chosen = plan.describe()["classes"][0]["variant"]
     say(f"[curvilinear] N={b.N} E={b.nelem} per_element={b.coef_per_element} prec={prec} "
-        f"acc64_min_order={acc64_min_order} -> {plan.describe()['classes'][0]['variant']}")
+        f"acc64_min_order={acc64_min_order} -> {chosen}")
+    if prec == stp.BF16X3 and b.N == 7 and variant == stp.VARIANT_AUTO:
+        assert chosen == "mfma", chosen
     got = runner.run(plan, b)
     rb = runner.rounded(b, prec)
     ref = oracle.stp(rb.N, rb.physics, rb.Q, rb.dt, rb.h, params=rb.params, coef_per_element=rb.coef_per_element)
@@ -52,9 +55,21 @@ def test_curvilinear_fp32(N):
     check(W.curvilinear_batch(N, 40, 810 + N), stp.FP32)
 
 
-def test_curvilinear_fp32_acc64_and_bf16x3_plan():
+def test_curvilinear_fp32_acc64():
     check(W.curvilinear_batch(9, 24, 821), stp.FP32, acc64_min_order=8)
-    check(W.curvilinear_batch(7, 24, 822), stp.BF16X3)  # no MFMA kernel: the plan takes the FP32 plain one
+
+
+@pytest.mark.parametrize("per_node", [True, False])
+def test_curvilinear_mfma(per_node):
+    """Split-BF16x3 MFMA kernel (all 9 quantities differentiated per direction, metric rows re-read per
+    direction) against the oracle on the FP32-rounded inputs."""
+    b = W.curvilinear_batch(7, 40, 823 + per_node, per_node=per_node)
+    check(b, stp.BF16X3, variant=stp.VARIANT_MFMA)
+    check(b, stp.BF16X3)  # the automatic choice at N = 7 is the MFMA kernel
+
+
+def test_curvilinear_bf16x3_other_orders_take_plain():
+    check(W.curvilinear_batch(5, 24, 825), stp.BF16X3)
 
 
 @pytest.mark.parametrize("N", [2, 6])
@@ -98,7 +113,7 @@ def test_mixed_batch_with_curvilinear_classes():
 def test_unsupported_combinations(gpu):
     torch = gpu
     cls = [(7, 9, stp.ELASTIC_CURV, 0)]
-    for prec, variant in ((stp.FP32, stp.VARIANT_FUSED), (stp.BF16X3, stp.VARIANT_MFMA)):
+    for prec, variant in ((stp.FP32, stp.VARIANT_FUSED), (stp.FP32, stp.VARIANT_MFMA)):
         with pytest.raises(stp.StpError) as ei:
             stp.Plan(cls, prec=prec, variant=variant)
         assert ei.value.status == stp.E_UNSUPPORTED
@@ -110,3 +125,29 @@ def test_unsupported_combinations(gpu):
     assert plan.correct_status(st) == stp.E_UNSUPPORTED and "curvilinear" in stp.last_error()
     plan.close()
     torch.cuda.synchronize()
+
+
+def test_curvilinear_mfma_full_size_sampled(gpu):
+    """65536 curvilinear N = 7 elements generated on the device (the bench's workload and launch), 24 of them
+    checked against the oracle on the same FP32 inputs."""
+    torch = gpu
+    N, E, n3, n2 = 7, 65536, 512, 64
+    Q, par, dt = W.curvilinear_device(N, E, W.SEED0 + 7)
+    plan = stp.Plan([(N, 9, stp.ELASTIC_CURV, 0)], prec=stp.BF16X3, variant=stp.VARIANT_MFMA)
+    qavg = torch.empty((E, n3, 9), device="cuda")
+    favg = torch.empty((E, 3, n3, 9), device="cuda")
+    qface = torch.empty((E, 6, n2, 9), device="cuda")
+    say(f"[curvilinear] full size E={E} MFMA")
+    plan.run(plan.batch(E, Q, qavg, favg, qface, dt, 1.0, params=par))
+    torch.cuda.synchronize()
+    ids = torch.from_numpy(np.linspace(0, E - 1, 24).astype(np.int64)).cuda()
+    pick = lambda t: t.index_select(0, ids).double().cpu().numpy()
+    ref = oracle.stp(N, W.ELASTIC_CURV, pick(Q), dt, 1.0, params=pick(par))
+    got = {"qavg": pick(qavg), "favg": pick(favg), "qface": pick(qface)}
+    err = max_rel_err(got, ref, pick(Q), np.ones(24))
+    say(f"[curvilinear]   max rel err {err}")
+    for k, v in err.items():
+        assert v < TOL[stp.BF16X3], (k, v)
+    plan.close()
+    del Q, par, qavg, favg, qface
+    torch.cuda.empty_cache()
