@@ -385,7 +385,7 @@ struct Fused {
                 __syncthreads();
                 T r[M][n];
                 volume(tb, P, G, la, lb, act, mt, p, r);
-                w = w * dt / (T)(o + 1);
+                w = w * dt * __builtin_amdgcn_rcpf((T)(o + 1));
 #pragma unroll
                 for (int q = 0; q < M; ++q)
 #pragma unroll

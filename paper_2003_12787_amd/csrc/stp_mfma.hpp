@@ -58,12 +58,38 @@ struct AOps {
     bf16x4 a1t, a2t, a1b, a2b;
 };
 
-// D u for the lane's half-line u[0..3]; the 16-line groups of the wave are formed by the permlane32 swap.
-__device__ inline void deriv_mfma(const AOps& A, const float (&u)[4], float (&out)[4])
-{
+// The split of the lane's 4 values: hi and lo of nodes (0, 1) and (2, 3), two bf16 per word.
+struct Split4 {
     unsigned h0, l0, h1, l1;
-    split_pair(u[0], u[1], h0, l0);
-    split_pair(u[2], u[3], h1, l1);
+};
+
+__device__ inline Split4 split4(const float (&u)[4])
+{
+    Split4 s;
+    split_pair(u[0], u[1], s.h0, s.l0);
+    split_pair(u[2], u[3], s.h1, s.l1);
+    return s;
+}
+
+// Node words of the LDS tile: hi of the node in the low half, lo in the high half (one word per node, the size of
+// the FP32 value), so that the y- and z-roles reassemble the hi and lo pairs with two byte permutes per pair
+// instead of splitting again.
+__device__ inline unsigned node_word(unsigned h, unsigned l, bool second)
+{
+    return __builtin_amdgcn_perm(l, h, second ? 0x07060302u : 0x05040100u);
+}
+
+__device__ inline Split4 from_words(unsigned w0, unsigned w1, unsigned w2, unsigned w3)
+{
+    return {__builtin_amdgcn_perm(w1, w0, 0x05040100u), __builtin_amdgcn_perm(w1, w0, 0x07060302u),
+            __builtin_amdgcn_perm(w3, w2, 0x05040100u), __builtin_amdgcn_perm(w3, w2, 0x07060302u)};
+}
+
+// D u for the lane's half-line, from the split of u[0..3]; the 16-line groups of the wave are formed by the
+// permlane32 swap.
+__device__ inline void deriv_mfma(const AOps& A, const Split4& sp, float (&out)[4])
+{
+    const unsigned h0 = sp.h0, l0 = sp.l0, h1 = sp.h1, l1 = sp.l1;
     // B1 = [hi of lanes 0..31 | lo of lanes 0..31], B2 = [hi of lanes 32..63 | lo of lanes 32..63]
     auto s0 = __builtin_amdgcn_permlane32_swap(h0, l0, false, false);
     auto s1 = __builtin_amdgcn_permlane32_swap(h1, l1, false, false);
@@ -184,7 +210,7 @@ struct Mfma8 {
 
     template <int K = 0>
     __device__ static inline void xpass(const AOps& A, const Material<float, PHYS> (&mt)[4], const GRow& Gd,
-                                        const float (&p)[M][4],
+                                        const Split4 (&p)[M],
                                         float (&r)[M][4])
     {
         if constexpr (K < NG) {
@@ -248,16 +274,15 @@ struct Mfma8 {
     __device__ static inline void transposed(const AOps& A, const float* P0, float* G0, const Offs& f)
     {
         const int z0 = opaque_zero();
-        const float* P = P0 + z0;
+        const unsigned* P = reinterpret_cast<const unsigned*>(P0) + z0;  // node words (node_word)
         float* G = G0 + z0;
         const int(&off)[4] = D == 1 ? f.y : f.z;
 #pragma unroll
         for (int k = K0; k < K1; ++k) {
             const int s = S::slot(S::dq(D, k));
-            float u[4], g[4];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) u[t] = P[s * SLOT + off[t]];
-            deriv_mfma(A, u, g);
+            float g[4];
+            const unsigned* Ps = P + s * SLOT;
+            deriv_mfma(A, from_words(Ps[off[0]], Ps[off[1]], Ps[off[2]], Ps[off[3]]), g);
 #pragma unroll
             for (int t = 0; t < 4; ++t) G[(k - K0) * SLOT + off[t]] = g[t];
             __builtin_amdgcn_sched_barrier(0);
@@ -297,15 +322,24 @@ struct Mfma8 {
         }
     }
 
-    __device__ static inline void write_tile(float* P0, const Offs& f, const float (&v)[M][4])
+    // the split of every quantity at the lane's 4 nodes (the x-pass and the tile use it; each value is split once)
+    __device__ static inline void split_all(const float (&v)[M][4], Split4 (&sp)[M])
     {
-        float* P = P0 + opaque_zero();
+#pragma unroll
+        for (int q = 0; q < M; ++q) sp[q] = split4(v[q]);
+    }
+
+    __device__ static inline void write_tile(float* P0, const Offs& f, const Split4 (&sp)[M])
+    {
+        unsigned* P = reinterpret_cast<unsigned*>(P0) + opaque_zero();
 #pragma unroll
         for (int q = 0; q < M; ++q) {
             const int s = S::slot(q);
             if (s < 0) continue;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) P[s * SLOT + f.o[t]] = v[q][t];
+            P[s * SLOT + f.o[0]] = node_word(sp[q].h0, sp[q].l0, false);
+            P[s * SLOT + f.o[1]] = node_word(sp[q].h0, sp[q].l0, true);
+            P[s * SLOT + f.o[2]] = node_word(sp[q].h1, sp[q].l1, false);
+            P[s * SLOT + f.o[3]] = node_word(sp[q].h1, sp[q].l1, true);
         }
     }
 
@@ -423,7 +457,9 @@ struct Mfma8 {
             const float dt = (float)er.dt;
 #pragma unroll 1
             for (int o = 1; o <= N; ++o) {
-                write_tile(P, off, p);
+                Split4 sp[M];
+                split_all(p, sp);
+                write_tile(P, off, sp);
                 __syncthreads();
                 float r[M][4];
 #pragma unroll
@@ -434,7 +470,7 @@ struct Mfma8 {
                 {
                     GRow G0;
                     load_grow<0>(gp, gs, G0);
-                    xpass(A, mt, G0, p, r);
+                    xpass(A, mt, G0, sp, r);
                 }
                 __syncthreads();
                 finish_dir<1>(A, P, G, off, mt, gp, gs, r);
@@ -442,7 +478,7 @@ struct Mfma8 {
                 transposed<2, 0, C1>(A, P, G, off);
                 __syncthreads();
                 finish_dir<2>(A, P, G, off, mt, gp, gs, r);
-                w = w * dt / (float)(o + 1);
+                w = w * dt * __builtin_amdgcn_rcpf((float)(o + 1));
 #pragma unroll
                 for (int q = 0; q < M; ++q)
 #pragma unroll
@@ -458,7 +494,9 @@ struct Mfma8 {
             const bool al = (er.q & 3) == 0;  // 16-byte aligned element blocks (float offsets)
             const int64_t wbase = (int64_t)32 * wv * n * M;  // first float of this wave's lines in a block
             store_block(Sw, static_cast<float*>(a.qavg) + er.q + wbase, qb, l, g, c, h, al);
-            write_tile(P, off, qb);
+            Split4 sq[M];
+            split_all(qb, sq);
+            write_tile(P, off, sq);
             __syncthreads();
             {
                 float fx[M][4];
@@ -470,7 +508,7 @@ struct Mfma8 {
                 {
                     GRow G0;
                     load_grow<0>(gp, gs, G0);
-                    xpass(A, mt, G0, qb, fx);
+                    xpass(A, mt, G0, sq, fx);
                 }
                 float* fav = static_cast<float*>(a.favg) + (fsum ? er.q : 3 * er.q) + wbase;
                 if (!fsum) {
