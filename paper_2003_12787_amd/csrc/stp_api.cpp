@@ -200,24 +200,23 @@ stp_status build_class(stp_plan_s* p, ClassState& cs)
         }
     }
     if (needSplit) {
-        // A operands of v_mfma_f32_16x16x16_bf16 for the split contraction: lane l holds row i = l % 16 and
-        // K entries k = 4 (l / 16) + t (t = 0..3), which pair with node x = 4 ((l / 16) % 2) + t of the hi
-        // (l / 16 < 2) or lo (l / 16 >= 2) part of a line. Matrices: D_hi and D_lo in the top row block
-        // (rows 0..7), then in the bottom row block (rows 8..15).
+        // A operands of v_mfma_f32_16x16x32_bf16 for the split contraction: lane l holds row i = l % 16 and K
+        // entries k = 8 (l / 16) + t (t = 0..7). K block l / 16 = 0..3 carries hi, lo of line group 0, then hi,
+        // lo of line group 1 (node x = t); rows 0..7 produce group 0, rows 8..15 group 1. Matrices: D_hi, D_lo.
         float Df[kMaxNodes * kMaxNodes];
         derivative_matrix_f32(n, D, Df);
         uint16_t Dh[kMaxNodes * kMaxNodes], Dl[kMaxNodes * kMaxNodes];
         split_bf16(n * n, Df, Dh, Dl);
-        uint16_t tab[4][64][4];
-        for (int mat = 0; mat < 4; ++mat)
+        uint16_t tab[2][64][8];
+        for (int mat = 0; mat < 2; ++mat)
             for (int l = 0; l < 64; ++l)
-                for (int t = 0; t < 4; ++t) {
-                    const int i = l % 16, kq = l / 16, x = 4 * (kq % 2) + t;
-                    const bool top = mat < 2, use = top ? i < 8 : i >= 8;
-                    const uint16_t* src = (mat % 2 == 0) ? Dh : Dl;
-                    tab[mat][l][t] = use ? src[(i % 8) * n + x] : (uint16_t)0;
+                for (int t = 0; t < 8; ++t) {
+                    const int i = l % 16, kb = l / 16;
+                    const bool use = i < 8 ? kb < 2 : kb >= 2;
+                    const uint16_t* src = mat == 0 ? Dh : Dl;
+                    tab[mat][l][t] = use ? src[(i % 8) * n + t] : (uint16_t)0;
                 }
-        if ((st = upload(&tab[0][0][0], 4 * 64 * 4, &cs.dDsplit)) != STP_OK) return st;
+        if ((st = upload(&tab[0][0][0], 2 * 64 * 8, &cs.dDsplit)) != STP_OK) return st;
     }
     (void)hasA;
     if ((st = set_kernel(p, cs, chosen)) != STP_OK) return st;

@@ -5,15 +5,17 @@
 // the 1D derivative u -> D u (the sum-factorised contraction of Sec. III-B) runs on MFMA, as split-BF16
 // products with FP32 accumulation: u = u_hi + u_lo and D = D_hi + D_lo with hi = bf16(x) (nearest) and
 // lo = bf16(x - hi); the products D_hi u_hi + D_hi u_lo + D_lo u_hi + D_lo u_lo are formed by two
-// v_mfma_f32_16x16x16_bf16 per 16 lines (the K dimension carries [hi | lo] of a line, so the fourth
-// product costs nothing).
+// v_mfma_f32_16x16x32_bf16 per 32 lines (the K dimension carries [hi | lo] of the lines of both 16-line
+// groups, so the fourth product costs nothing).
 //
 // Lane layout: an element is 128 lanes (two waves). Lane (wave w, lane l): line c = l % 16 of group
 // g = l / 32, half h = (l / 16) % 2, line index 32 w + 16 g + c, nodes 4h..4h+3 along the line. For the
-// x-direction the owner's registers already hold its half-line: each lane forms hi/lo of its 4 values, one
-// permlane32 swap of (hi, lo) produces the B operands of both 16-line groups of the wave, and
-//   C = A1top B1 + A2top B1 + A1bot B2 + A2bot B2
-// with A*top = [D rows; 0] and A*bot = [0; D rows] leaves D u exactly at each owner's 4 nodes. The y- and
+// x-direction the owner's registers already hold its half-line: each lane forms hi/lo of its 4 values, and two
+// permlane16 swaps of (hi, lo) give every lane the 8 K values of its row block of the B operand
+//   B = [hi of group 0 | lo of group 0 | hi of group 1 | lo of group 1]   (8 nodes each, column = line c)
+// With A_x = [[D_x, D_x, 0, 0]; [0, 0, D_x, D_x]] (rows 0..7: group 0, rows 8..15: group 1; x = hi, lo),
+//   C = A_hi B + A_lo B
+// leaves D u exactly at each owner's 4 nodes. The y- and
 // z-directions use the same lane roles on lines read from an LDS tile of p, and return the derivatives to the
 // owners through an LDS exchange buffer (as in the fused kernel). Pointwise terms, the time accumulation and
 // the faces stay on the VALU in FP32.
@@ -25,8 +27,9 @@
 namespace stp {
 namespace mfma {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -43,19 +46,19 @@ __device__ inline void split_pair(float a, float b, unsigned& hi, unsigned& lo)
     lo = __builtin_bit_cast(unsigned, __builtin_convertvector(r, bf16x2));
 }
 
-__device__ inline bf16x4 as_bf16x4(unsigned w0, unsigned w1)
+__device__ inline bf16x8 as_bf16x8(unsigned w0, unsigned w1, unsigned w2, unsigned w3)
 {
-    const u32x2 t = {w0, w1};
-    return __builtin_bit_cast(bf16x4, t);
+    const u32x4 t = {w0, w1, w2, w3};
+    return __builtin_bit_cast(bf16x8, t);
 }
 
 // opaque_zero() (stp_device.hpp) launders the LDS base addresses: they are recomputed where they are used
 // instead of being hoisted out of the Taylor loop (each quantity slot needs its own base register for the
 // paired LDS accesses, and keeping them all live would halve the occupancy).
 
-// A operands of the two-product pair for the top (rows 0..7) and bottom (rows 8..15) row blocks
+// A operands of the split contraction: D_hi and D_lo in the block layout [[D, D, 0, 0]; [0, 0, D, D]]
 struct AOps {
-    bf16x4 a1t, a2t, a1b, a2b;
+    bf16x8 hi, lo;
 };
 
 // The split of the lane's 4 values: hi and lo of nodes (0, 1) and (2, 3), two bf16 per word.
@@ -90,16 +93,15 @@ __device__ inline Split4 from_words(unsigned w0, unsigned w1, unsigned w2, unsig
 __device__ inline void deriv_mfma(const AOps& A, const Split4& sp, float (&out)[4])
 {
     const unsigned h0 = sp.h0, l0 = sp.l0, h1 = sp.h1, l1 = sp.l1;
-    // B1 = [hi of lanes 0..31 | lo of lanes 0..31], B2 = [hi of lanes 32..63 | lo of lanes 32..63]
-    auto s0 = __builtin_amdgcn_permlane32_swap(h0, l0, false, false);
-    auto s1 = __builtin_amdgcn_permlane32_swap(h1, l1, false, false);
-    const bf16x4 b1 = as_bf16x4(s0[0], s1[0]);
-    const bf16x4 b2 = as_bf16x4(s0[1], s1[1]);
+    // The swap exchanges the odd 16-lane rows of the first operand with the even rows of the second: rows 0 and
+    // 2 (h = 0) end with the hi parts of nodes 0..7 of their line, rows 1 and 3 (h = 1) with the lo parts, in
+    // node order (0, 1), (2, 3), (4, 5), (6, 7): the lane's 8 K values of B.
+    auto s0 = __builtin_amdgcn_permlane16_swap(h0, l0, false, false);
+    auto s1 = __builtin_amdgcn_permlane16_swap(h1, l1, false, false);
+    const bf16x8 b = as_bf16x8(s0[0], s1[0], s0[1], s1[1]);
     f32x4 c = {0.f, 0.f, 0.f, 0.f};
-    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A.a1t, b1, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A.a2t, b1, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A.a1b, b2, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A.a2b, b2, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.hi, b, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.lo, b, c, 0, 0, 0);
     out[0] = c[0];
     out[1] = c[1];
     out[2] = c[2];
@@ -425,12 +427,10 @@ struct Mfma8 {
 
         AOps A;
         {
-            // table: [4 matrices][64 lanes][4 bf16] in the order a1t, a2t, a1b, a2b
+            // table: [2 matrices (A_hi, A_lo)][64 lanes][8 bf16]
             const unsigned* t = static_cast<const unsigned*>(a.Dsplit);
-            A.a1t = as_bf16x4(t[(0 * 64 + l) * 2], t[(0 * 64 + l) * 2 + 1]);
-            A.a2t = as_bf16x4(t[(1 * 64 + l) * 2], t[(1 * 64 + l) * 2 + 1]);
-            A.a1b = as_bf16x4(t[(2 * 64 + l) * 2], t[(2 * 64 + l) * 2 + 1]);
-            A.a2b = as_bf16x4(t[(3 * 64 + l) * 2], t[(3 * 64 + l) * 2 + 1]);
+            A.hi = as_bf16x8(t[l * 4], t[l * 4 + 1], t[l * 4 + 2], t[l * 4 + 3]);
+            A.lo = as_bf16x8(t[(64 + l) * 4], t[(64 + l) * 4 + 1], t[(64 + l) * 4 + 2], t[(64 + l) * 4 + 3]);
         }
         const int64_t cnt = a.count ? (int64_t)*a.count : a.nelem;
 
