@@ -8,6 +8,7 @@ import subprocess
 import pytest
 
 import oracle
+import test_curvilinear_oracle as CP
 import test_oracle_pins as P
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "stp_oracle.c")
@@ -30,6 +31,10 @@ MUTANTS = {
     "source_order_shift": ("src[nn + m + o];", "src[nn + m + (o > 0 ? o - 1 : 0)];"),
     "dmatrix_diag": ("diag -= v;", "diag += v;"),
     "face_axis": ("else if (axis == 1) { z = a; y = j; x = b; }", "else if (axis == 1) { z = b; y = j; x = a; }"),
+    "curvilinear_metric_transposed": ("acc += G[d * 3 + j] * Mj[j * 81 + k];", "acc += G[j * 3 + d] * Mj[j * 81 + k];"),
+    "curvilinear_diagonal_only": ("acc += G[d * 3 + j] * Mj[j * 81 + k];",
+                                  "acc += (j == d) * G[d * 3 + j] * Mj[j * 81 + k];"),
+    "curvilinear_metric_row": ("acc += G[d * 3 + j] * Mj[j * 81 + k];", "acc += G[d * 3 + j] * Mj[d * 81 + k];"),
 }
 
 
@@ -51,6 +56,8 @@ def _pins():
         ("source", lambda: [P.test_point_source_with_zero_operator(o, 3), P.test_point_source_enters_recursion(o)]),
         ("fface", lambda: P.test_fface_is_extrapolated_conservative_flux(o)),
         ("axisperm", lambda: P.test_axis_permutation(o)),
+        ("curv_spectrum", lambda: CP.test_curvilinear_spectrum(o)),
+        ("curv_affine", lambda: [CP.test_affine_element_polynomial_plane_wave_exact(o, 2, w) for w in ("P", "S")]),
     ]
 
 
