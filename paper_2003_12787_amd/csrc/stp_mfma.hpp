@@ -88,8 +88,8 @@ __device__ inline Split4 from_words(unsigned w0, unsigned w1, unsigned w2, unsig
             __builtin_amdgcn_perm(w3, w2, 0x05040100u), __builtin_amdgcn_perm(w3, w2, 0x07060302u)};
 }
 
-// D u for the lane's half-line, from the split of u[0..3]; the 16-line groups of the wave are formed by the
-// permlane32 swap.
+// D u for the lane's half-line, from the split of u[0..3]; the B operand of both 16-line groups of the wave is
+// formed by two permlane16 swaps.
 __device__ inline void deriv_mfma(const AOps& A, const Split4& sp, float (&out)[4])
 {
     const unsigned h0 = sp.h0, l0 = sp.l0, h1 = sp.h1, l1 = sp.l1;
