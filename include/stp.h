@@ -132,8 +132,10 @@ typedef struct {
 enum {
     STP_VARIANT_AUTO = 0,
     STP_VARIANT_PLAIN = 1,   /* one element per workgroup, one thread per node, LDS-staged             */
-    STP_VARIANT_FUSED = 2,   /* register-blocked lines, LDS transposes (presets, FP32/FP64)           */
-    STP_VARIANT_MFMA = 3     /* split-BF16x3 MFMA contractions with FP32 accumulation (STP_BF16X3)    */
+    STP_VARIANT_FUSED = 2,   /* register-blocked lines, LDS transposes (acoustic and elastic presets,
+                                FP32 I/O without FP64 accumulation or point source, N <= 7)            */
+    STP_VARIANT_MFMA = 3     /* split-BF16x3 MFMA contractions with FP32 accumulation (STP_BF16X3;
+                                acoustic, elastic and curvilinear elastic presets at N = 7)            */
 };
 
 typedef struct {
@@ -166,9 +168,10 @@ typedef struct {
     int status;       /* STP_OK, STP_PENDING or an error                              */
 } stp_ticket_info;
 
-/* Build a plan: host tables (Gauss-Legendre nodes, D, face vectors, BF16 hi/lo split of D) in FP64,
- * uploaded once to the device; kernel choice per class. Returns STP_E_UNSUPPORTED for an order outside
- * 1..9, a preset with the wrong m, or a generic m outside 1..16. *out is NULL on failure. */
+/* Build a plan: host tables (Gauss-Legendre or Gauss-Lobatto nodes, D, face vectors, BF16 hi/lo split of D)
+ * in FP64, uploaded once to the device; kernel choice per class. Returns STP_E_UNSUPPORTED for an order
+ * outside 1..9, a preset with the wrong m, a generic m outside 1..16, or a requested variant that has no
+ * kernel for a class. *out is NULL on failure. */
 stp_status stp_plan(const stp_plan_desc* desc, stp_plan_t* out);
 
 /* Release a plan (waits for its outstanding serving work). NULL is a no-op. */
@@ -193,7 +196,7 @@ stp_status stp_run(stp_plan_t plan, const stp_batch* batch, void* hip_stream);
  * (the neighbour's), the correction is C = 1/2 alpha (q+ - q-) - 1/2 s (F+ - F-) - 1/2 s Bbar_d (q+ - q-),
  * Bbar_d the mean of both elements' B_d and alpha the larger fastest wave speed (acoustic sqrt(K/rho),
  * elastic sqrt((lambda + 2 mu)/rho), generic max_d ||A_d + B_d||_inf). Node k receives
- * dt l_{k_d}(face) / (h w_{k_d}) C at its face node (Gauss-Legendre collocation, diagonal mass matrix).
+ * dt l_{k_d}(face) / (h w_{k_d}) C at its face node (collocation on the plan's nodes, diagonal mass matrix).
  * Elements e = (iz * ny + iy) * nx + ix, uniform size h, periodic in x, y and z; layouts as in stp_batch,
  * contiguous (element e at e * size). Stability of the full step needs dt <= about 0.2 h / ((2N+1) c_max). */
 typedef struct {
@@ -209,8 +212,8 @@ typedef struct {
     void* Qnew;           /* q(t_{n+1}) [e][n^3][m]; must not alias Q, favg or qface                          */
 } stp_step;
 
-/* Queue the corrector of one step on `hip_stream`. Needs a single-class plan with per-element coefficients
- * and no point source (STP_E_UNSUPPORTED otherwise); STP_E_INVAL for NULL or aliasing buffers, a mesh
+/* Queue the corrector of one step on `hip_stream`. Needs a single-class plan of Cartesian physics (acoustic,
+ * elastic or generic) with per-element coefficients and no point source (STP_E_UNSUPPORTED otherwise); STP_E_INVAL for NULL or aliasing buffers, a mesh
  * dimension < 1, h <= 0 or dt < 0. I/O precision as the plan's (double for STP_FP64, else float). */
 stp_status stp_correct(stp_plan_t plan, const stp_step* step, void* hip_stream);
 
