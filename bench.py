@@ -522,9 +522,22 @@ def main():
                 curv[name]["checked_elements"] = int(len(ck["ids"]))
                 log(f"[bench] curvilinear {name}: max rel err vs oracle {errs}")
             del ref
+        # one host thread on a small sample, for the per-core rate
+        one = np.linspace(0, E - 1, min(E, 256)).astype(np.int64)
+        t0 = time.perf_counter()
+        oracle.stp(b.N, b.physics, b.Q[one], b.dt[one], b.h[one], params=b.params[one], nthreads=1)
+        t1 = time.perf_counter() - t0
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+        except OSError:
+            pass
         cpu = {"value": k / t, "unit": "element-updates/s", "cores": threads, "kind": "oracle",
-               "sample": f"{k} of the {E} elements (evenly spaced), FP64, {t:.1f} s"}
-        log(f"[bench] CPU oracle: {k / t:.1f} el/s")
+               "sample": f"{k} of the {E} elements (evenly spaced), FP64, {t:.1f} s",
+               "value_1thread": len(one) / t1, "sample_1thread": f"{len(one)} elements, {t1:.2f} s",
+               "cpu_model": model}
+        log(f"[bench] CPU oracle: {k / t:.1f} el/s ({threads} threads), {len(one) / t1:.1f} el/s (1 thread), {model}")
 
     line = {
         "metric": "STP element-updates/s + % roofline (elastic N=7) vs plain FP64; p50/p99 latency",
