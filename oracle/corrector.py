@@ -16,7 +16,10 @@ design notes):
 
   Bbar_d = (B_d(e) + B_d(neighbour)) / 2, alpha = max(alpha(e), alpha(neighbour)) (Rusanov), with alpha the
   fastest wave speed of the element: sqrt(K/rho) acoustic, sqrt((lambda+2 mu)/rho) elastic, and for generic
-  coefficients the bound max_d ||A_d + B_d||_inf (maximum absolute row sum).
+  coefficients the bound max_d ||A_d + B_d||_inf (maximum absolute row sum). Curvilinear elastic elements with
+  affine geometry (12 parameters per element: the material and the constant metric G[d][j] = h dxi_d/dx_j)
+  take B_d = sum_j G[d][j] M_j and alpha = sqrt((lambda+2 mu)/rho) max_d |G[d][:]|_2 (the spectral radius of
+  B_d in its worst direction): the scheme is the Cartesian one in the reference coordinates of the mesh.
 
   q(t_{n+1})_k = q(t_n)_k + dt sum_d favg[d]_k + dt sum_f l_{k_d}(x_f) / (h w_{k_d}) C_f(k_a, k_b)
 
@@ -33,7 +36,7 @@ import numpy as np
 
 import oracle
 
-ACOUSTIC, ELASTIC, GENERIC = 0, 1, 2
+ACOUSTIC, ELASTIC, GENERIC, ELASTIC_CURV = 0, 1, 2, 3
 
 
 def gl_weights01(n: int, nodes: int = 0) -> np.ndarray:
@@ -56,6 +59,9 @@ def wave_speed(physics: int, params=None, A=None, B=None) -> np.ndarray:
         return np.sqrt(params[:, 1] / params[:, 0])
     if physics == ELASTIC:
         return np.sqrt((params[:, 1] + 2 * params[:, 2]) / params[:, 0])
+    if physics == ELASTIC_CURV:
+        G = np.asarray(params[:, 3:], dtype=np.float64).reshape(-1, 3, 3)
+        return np.sqrt((params[:, 1] + 2 * params[:, 2]) / params[:, 0]) * np.linalg.norm(G, axis=2).max(axis=1)
     M = np.asarray(B, dtype=np.float64) + (0.0 if A is None else np.asarray(A, dtype=np.float64))
     return np.abs(M).sum(axis=-1).max(axis=(1, 2))
 
@@ -83,7 +89,8 @@ def correct(N: int, physics: int, grid, Q, favg, qface, dt: float, h: float, par
     """q(t_{n+1}) [E, n^3, m] from q(t_n) and the predictor outputs of every element of the mesh.
 
     Q [E, n^3, m]; favg [E, 3, n^3, m] (or [E, n^3, m] with favg_sum); qface, fface [E, 6, n^2, m] with the
-    faces ordered x-, x+, y-, y+, z-, z+ and the face nodes (a, b) = the two other axes, slower first."""
+    faces ordered x-, x+, y-, y+, z-, z+ and the face nodes (a, b) = the two other axes, slower first.
+    Presets take params [E, np] (np = 2, 3, or 12 for affine curvilinear elements)."""
     nx, ny, nz = grid
     n = N + 1
     E = nx * ny * nz
