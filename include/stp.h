@@ -45,7 +45,8 @@
  *                 the image of the reference cube under a map x(xi); by the chain rule the system becomes
  *                 q_t + sum_d B_d dq/dxi_d / h = 0 with B_d = sum_j G[d][j] M_j, M_j the Cartesian elastic
  *                 matrices and G[d][j] = h dxi_d/dx_j the metric terms (the inverse Jacobian of the map
- *                 scaled by the element size h; an undeformed cube of side h has G = I). No corrector.
+ *                 scaled by the element size h; an undeformed cube of side h has G = I). The corrector
+ *                 takes affine elements (STP_PARAM_PER_ELEMENT) only.
  *
  * Precision: STP_FP64 computes and stores in double. STP_FP32 and STP_BF16X3 read and write float; their
  * derivative contractions run in FP32 (VALU) or as three BF16 products with FP32 accumulation (MFMA).
@@ -195,7 +196,9 @@ stp_status stp_run(stp_plan_t plan, const stp_batch* batch, void* hip_stream);
  * element with outward normal s e_d and states q-/F- (own face projections of q-bar and A_d q-bar) and q+/F+
  * (the neighbour's), the correction is C = 1/2 alpha (q+ - q-) - 1/2 s (F+ - F-) - 1/2 s Bbar_d (q+ - q-),
  * Bbar_d the mean of both elements' B_d and alpha the larger fastest wave speed (acoustic sqrt(K/rho),
- * elastic sqrt((lambda + 2 mu)/rho), generic max_d ||A_d + B_d||_inf). Node k receives
+ * elastic sqrt((lambda + 2 mu)/rho), generic max_d ||A_d + B_d||_inf; curvilinear elements with affine
+ * geometry, STP_ELASTIC_CURV with STP_PARAM_PER_ELEMENT: B_d = sum_j G[d][j] M_j, the mean taken of the two
+ * elements' products, and sqrt((lambda + 2 mu)/rho) max_d |G[d][:]|_2). Node k receives
  * dt l_{k_d}(face) / (h w_{k_d}) C at its face node (collocation on the plan's nodes, diagonal mass matrix).
  * Elements e = (iz * ny + iy) * nx + ix, uniform size h, periodic in x, y and z; layouts as in stp_batch,
  * contiguous (element e at e * size). Stability of the full step needs dt <= about 0.2 h / ((2N+1) c_max). */
@@ -203,7 +206,7 @@ typedef struct {
     int nx, ny, nz;       /* elements per direction (nx * ny * nz <= 2^31 - 1)                               */
     double dt, h;         /* time step (>= 0) and element size (> 0)                                          */
     const void* Q;        /* q(t_n) [e][n^3][m]                                                               */
-    const void* params;   /* presets: [e][np] (the class must have STP_PARAM_PER_ELEMENT)                    */
+    const void* params;   /* presets: [e][np] (np = 2, 3 or 12; the class must have STP_PARAM_PER_ELEMENT)    */
     const void* A;        /* generic: [e][d][m][m] (STP_COEF_PER_ELEMENT); NULL without STP_A_PRESENT         */
     const void* B;        /* generic: [e][d][m][m]                                                            */
     const void* favg;     /* stp_run outputs of the same elements with the same dt and h                      */
@@ -212,8 +215,9 @@ typedef struct {
     void* Qnew;           /* q(t_{n+1}) [e][n^3][m]; must not alias Q, favg or qface                          */
 } stp_step;
 
-/* Queue the corrector of one step on `hip_stream`. Needs a single-class plan of Cartesian physics (acoustic,
- * elastic or generic) with per-element coefficients and no point source (STP_E_UNSUPPORTED otherwise); STP_E_INVAL for NULL or aliasing buffers, a mesh
+/* Queue the corrector of one step on `hip_stream`. Needs a single-class plan with per-element coefficients
+ * (for curvilinear elements: affine geometry, one metric per element) and no point source
+ * (STP_E_UNSUPPORTED otherwise); STP_E_INVAL for NULL or aliasing buffers, a mesh
  * dimension < 1, h <= 0 or dt < 0. I/O precision as the plan's (double for STP_FP64, else float). */
 stp_status stp_correct(stp_plan_t plan, const stp_step* step, void* hip_stream);
 

@@ -11,7 +11,10 @@
 // collocation and the diagonal mass matrix the node k of the element receives
 //     q(t_{n+1})_k = q(t_n)_k + dt sum_d favg[d]_k + dt sum_f l_{k_d}(x_f) / (h w_{k_d}) C_f(face node of k).
 // One workgroup per element: the face corrections of all six faces go to LDS, then every node is updated.
-// Coefficients are per element (presets: rho, K or rho, lambda, mu; generic: A_d, B_d [3][m][m]).
+// Coefficients are per element (presets: rho, K or rho, lambda, mu; generic: A_d, B_d [3][m][m]). Curvilinear
+// elastic elements with affine geometry carry rho, lambda, mu and the constant metric G[d][j] = h dxi_d/dx_j
+// (12 values): B_d = sum_j G[d][j] M_j with M_j the Cartesian elastic matrices, and alpha = sqrt((lambda +
+// 2 mu)/rho) max_d |G[d][:]|_2; the scheme is the Cartesian one in the reference coordinates of the mesh.
 #include <algorithm>
 #include <cmath>
 
@@ -67,6 +70,25 @@ __device__ inline void preset_Bj(int physics, int d, const T* c, const T* j, T* 
     }
 }
 
+// (Bbar_d j) for curvilinear elements: B_d = sum_j G[d][j] M_j is bilinear in the metric and the material,
+// so the mean over the two elements of the face is taken of the products, side by side. p0, p1: the 12
+// parameters (rho, lambda, mu, G) of the element and of its neighbour.
+template <typename T>
+__device__ inline void curv_Bj(int d, const T* p0, const T* p1, const T* j, T* out)
+{
+    for (int r = 0; r < 9; ++r) out[r] = 0;
+    for (int side = 0; side < 2; ++side) {
+        const T* p = side ? p1 : p0;
+        const T c[3] = {(T)1 / p[0], p[1], p[2]};
+        for (int k = 0; k < 3; ++k) {
+            T t[9];
+            preset_Bj<T>(kElastic, k, c, j, t);
+            const T g = (T)0.5 * p[3 + 3 * d + k];
+            for (int r = 0; r < 9; ++r) out[r] = fma(g, t[r], out[r]);
+        }
+    }
+}
+
 template <typename T>
 __device__ T wave_speed(const CorrArgs& a, int64_t e)
 {
@@ -77,6 +99,15 @@ __device__ T wave_speed(const CorrArgs& a, int64_t e)
     if (a.physics == kElastic) {
         const T* p = static_cast<const T*>(a.coef) + e * 3;
         return sqrt((p[1] + 2 * p[2]) / p[0]);
+    }
+    if (a.physics == kElasticCurv) {
+        const T* p = static_cast<const T*>(a.coef) + e * 12;
+        T g = 0;
+        for (int d = 0; d < 3; ++d) {
+            const T r = sqrt(p[3 + 3 * d] * p[3 + 3 * d] + p[4 + 3 * d] * p[4 + 3 * d] + p[5 + 3 * d] * p[5 + 3 * d]);
+            g = r > g ? r : g;
+        }
+        return sqrt((p[1] + 2 * p[2]) / p[0]) * g;
     }
     const int m = a.m;
     const T* B = static_cast<const T*>(a.coef) + e * 3 * m * m;
@@ -98,11 +129,13 @@ __global__ void __launch_bounds__(kCorrThreads) stp_correct_kernel(CorrArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int n = N + 1, n2 = n * n, n3 = n2 * n;
-    const int m = PHYS == kAcoustic ? 4 : (PHYS == kElastic ? 9 : a.m);
+    const int m = PHYS == kAcoustic ? 4 : (PHYS == kGeneric ? a.m : 9);
     constexpr bool preset = PHYS != kGeneric;
+    constexpr bool curv = PHYS == kElasticCurv;
     T* Bbar = reinterpret_cast<T*>(smem);  // generic: [6][m][m] mean B_d of the element and its neighbour
-    T* cbar = Bbar + (preset ? 0 : 6 * m * m);  // presets: [6][4] mean (1/rho, K) or (1/rho, lambda, mu)
-    T* Cf = cbar + 24;                     // [6][n^2][m] face corrections
+    T* cbar = Bbar + (preset ? 0 : 6 * m * m);  // presets: [6][4] mean (1/rho, K) or (1/rho, lambda, mu);
+                                               // curvilinear: [6][2][12] parameters of both elements
+    T* Cf = cbar + (curv ? 144 : 24);      // [6][n^2][m] face corrections
     T* alpha = Cf + 6 * n2 * m;            // [6]
     T* lift0 = alpha + 8;                  // [n] l_j(0) / (h w_j)
     T* lift1 = lift0 + n;                  // [n] l_j(1) / (h w_j)
@@ -118,7 +151,14 @@ __global__ void __launch_bounds__(kCorrThreads) stp_correct_kernel(CorrArgs a)
         if (tid < 6) {
             const int d = tid >> 1, s = (tid & 1) ? 1 : -1;
             const int64_t nb = neighbour_of(a, e, d, s);
-            if constexpr (preset) {
+            if constexpr (curv) {
+                const T* p0 = static_cast<const T*>(a.coef) + e * 12;
+                const T* p1 = static_cast<const T*>(a.coef) + nb * 12;
+                for (int i = 0; i < 12; ++i) {
+                    cbar[tid * 24 + i] = p0[i];
+                    cbar[tid * 24 + 12 + i] = p1[i];
+                }
+            } else if constexpr (preset) {
                 const int np = PHYS == kAcoustic ? 2 : 3;
                 const T* p0 = static_cast<const T*>(a.coef) + e * np;
                 const T* p1 = static_cast<const T*>(a.coef) + nb * np;
@@ -149,7 +189,9 @@ __global__ void __launch_bounds__(kCorrThreads) stp_correct_kernel(CorrArgs a)
             const T* qp = qf + ((nb * 6 + fo) * n2 + pt) * m;
             T jump[kCorrMaxM], bj[kCorrMaxM];
             for (int r = 0; r < m; ++r) jump[r] = qp[r] - qm[r];
-            if constexpr (preset) {
+            if constexpr (curv) {
+                curv_Bj<T>(d, cbar + f * 24, cbar + f * 24 + 12, jump, bj);
+            } else if constexpr (preset) {
                 preset_Bj<T>(PHYS, d, cbar + f * 4, jump, bj);
             } else {
                 const T* Bf = Bbar + f * m * m;
@@ -211,13 +253,14 @@ const void* corr_kernel(int N, int physics)
 {
     if (physics == kAcoustic) return corr_kernel_by_order<T, kAcoustic>(N);
     if (physics == kElastic) return corr_kernel_by_order<T, kElastic>(N);
+    if (physics == kElasticCurv) return corr_kernel_by_order<T, kElasticCurv>(N);
     return corr_kernel_by_order<T, kGeneric>(N);
 }
 
 size_t corr_lds(int N, int m, size_t io)
 {
     const int n = N + 1;
-    return io * (size_t)(6 * m * m + 24 + 6 * n * n * m + 8 + 2 * n);
+    return io * (size_t)(6 * m * m + 144 + 6 * n * n * m + 8 + 2 * n);
 }
 
 }  // namespace
@@ -234,11 +277,10 @@ extern "C" stp_status stp_correct(stp_plan_t p, const stp_step* st, void* stream
     const ClassState& cs = p->classes[0];
     const stp_class& c = cs.cls;
     const bool generic = c.physics == STP_GENERIC;
-    if (c.physics == STP_ELASTIC_CURV)
-        return fail(STP_E_UNSUPPORTED, "the corrector covers Cartesian meshes (no curvilinear elements)");
     if (generic ? !(c.flags & STP_COEF_PER_ELEMENT) : !(c.flags & STP_PARAM_PER_ELEMENT))
         return fail(STP_E_UNSUPPORTED, "the corrector needs per-element coefficients (STP_PARAM_PER_ELEMENT or "
-                                       "STP_COEF_PER_ELEMENT)");
+                                       "STP_COEF_PER_ELEMENT%s)",
+                    c.physics == STP_ELASTIC_CURV ? "; curvilinear elements: affine geometry only" : "");
     if (c.flags & STP_SRC_POINT) return fail(STP_E_UNSUPPORTED, "point sources are not supported by the corrector");
     if (st->nx < 1 || st->ny < 1 || st->nz < 1) return fail(STP_E_INVAL, "mesh %d x %d x %d", st->nx, st->ny, st->nz);
     if ((int64_t)st->nx * st->ny * st->nz > (int64_t)INT32_MAX) return fail(STP_E_INVAL, "mesh too large");

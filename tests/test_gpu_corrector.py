@@ -13,7 +13,7 @@ from parity import TOL
 
 pytestmark = pytest.mark.gpu
 
-ACOUSTIC, ELASTIC, GENERIC = 0, 1, 2
+ACOUSTIC, ELASTIC, GENERIC, ELASTIC_CURV = 0, 1, 2, 3
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -39,6 +39,9 @@ def mesh_inputs(physics, N, grid, seed, m=None, with_A=False):
     n3 = (N + 1) ** 3
     if physics == ELASTIC:
         params, A, B, m = W.elastic_material(rng, (E,)), None, None, 9
+    elif physics == ELASTIC_CURV:  # affine elements: material and a non-symmetric metric near I per element
+        G = np.eye(3) + 0.2 * rng.standard_normal((E, 3, 3))
+        params, A, B, m = np.concatenate([W.elastic_material(rng, (E,)), G.reshape(E, 9)], axis=1), None, None, 9
     elif physics == ACOUSTIC:
         params, A, B, m = np.stack([rng.uniform(2, 3, E), rng.uniform(1, 2, E)], axis=1), None, None, 4
     else:
@@ -75,7 +78,8 @@ def gpu_step(plan, prec, physics, N, grid, Q, params, A, B, dt, h, with_A, torch
 
 @pytest.mark.parametrize("physics,N,prec,with_A", [(ELASTIC, 3, stp.FP64, False), (ELASTIC, 3, stp.FP32, False),
                                                    (ACOUSTIC, 5, stp.FP64, False), (GENERIC, 2, stp.FP64, True),
-                                                   (GENERIC, 4, stp.FP32, True)])
+                                                   (GENERIC, 4, stp.FP32, True), (ELASTIC_CURV, 3, stp.FP64, False),
+                                                   (ELASTIC_CURV, 7, stp.FP32, False)])
 def test_corrector_matches_oracle_on_oracle_predictor_outputs(physics, N, prec, with_A, gpu):
     """stp_correct alone, fed with the oracle predictor's outputs (rounded to the I/O precision)."""
     torch = gpu
@@ -173,3 +177,65 @@ def test_corrector_validation(gpu):
     assert plan.correct_status(st) == stp.E_INVAL
     plan.close()
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", [stp.FP64, stp.FP32])
+def test_curvilinear_full_steps_match_oracle(prec, gpu):
+    """Three ADER-DG steps on affine curvilinear elements (a different metric per element)."""
+    torch = gpu
+    N, grid = 3, (3, 2, 2)
+    Q, params, _, _, m = mesh_inputs(ELASTIC_CURV, N, grid, 31)
+    if prec != stp.FP64:
+        Q, params = Q.astype(np.float32).astype(np.float64), params.astype(np.float32).astype(np.float64)
+    h = 0.5
+    dt = 0.2 * h / ((2 * N + 1) * OC.wave_speed(ELASTIC_CURV, params).max())
+    plan = stp.Plan([(N, m, ELASTIC_CURV, stp.PARAM_PER_ELEMENT)], prec=prec)
+    qg, qo = Q.copy(), Q.copy()
+    for k in range(3):
+        qg = gpu_step(plan, prec, ELASTIC_CURV, N, grid, qg, params, None, None, dt, h, False, torch)
+        qo = OC.ader_step(N, ELASTIC_CURV, grid, qo, dt, h, params=params)
+        err = rel(qg, qo)
+        say(f"[curvilinear full step] prec={prec} step {k}: max rel err {err:.2e}")
+        assert err < 3 * TOL[prec], err
+    plan.close()
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_gpu_affine_curvilinear_plane_wave_converges(N, gpu):
+    """End to end on the GPU (FP64): a P-wave on a mesh mapped by a non-symmetric affine map (the oracle's
+    convergence pin) converges at order N + 1."""
+    torch = gpu
+    rng = np.random.default_rng(12)
+    J = np.eye(3) + 0.3 * rng.standard_normal((3, 3))
+    G = np.linalg.inv(J)
+    rho, lam, mu = 2.0, 3.0, 1.5
+    cp = np.sqrt((lam + 2 * mu) / rho)
+    k = 2 * np.pi * G.T[:, 0]
+    kh = k / np.linalg.norm(k)
+    S = -(lam * np.eye(3) + 2 * mu * np.outer(kh, kh)) / cp
+    r = np.concatenate([kh, [S[0, 0], S[1, 1], S[2, 2], S[0, 1], S[1, 2], S[0, 2]]])
+    omega = cp * np.linalg.norm(k)
+    alpha = cp * np.linalg.norm(G, axis=1).max()
+    plan = stp.Plan([(N, 9, ELASTIC_CURV, stp.PARAM_PER_ELEMENT)], prec=stp.FP64)
+    errs = []
+    for nx in (8, 16):
+        h = 1.0 / nx
+        n = N + 1
+        xi, _ = oracle.gl_nodes(n)
+        xg = np.zeros((nx, n, n, n))
+        for e in range(nx):
+            xg[e] = (e + xi)[None, None, :] * h
+        xg = xg.reshape(nx, n ** 3)
+        f = lambda t: np.sin(2 * np.pi * xg - omega * t)
+        Q = f(0.0)[..., None] * r
+        params = np.tile(np.concatenate([[rho, lam, mu], G.ravel()]), (nx, 1))
+        T = 0.1
+        steps = int(np.ceil(T / (0.2 * h / ((2 * N + 1) * alpha))))
+        dt = T / steps
+        for _ in range(steps):
+            Q = gpu_step(plan, stp.FP64, ELASTIC_CURV, N, (nx, 1, 1), Q, params, None, None, dt, h, False, torch)
+        errs.append(np.abs(Q - f(T)[..., None] * r).max())
+    rate = np.log2(errs[0] / errs[1])
+    say(f"[curvilinear convergence] N={N} errors {errs} rate {rate:.2f}")
+    assert rate > N + 1 - 0.5, (errs, rate)
+    plan.close()
