@@ -192,6 +192,34 @@ def bench_full_step(args, torch, stp, W):
            "corrector_hbm_frac": corr_bytes / (ms_c * 1e-3) / 1e9 / HBM_PEAK_GBS}
     log(f"[bench] full step: predictor {res['ms_predictor']:.3f} ms, corrector {ms_c:.3f} ms "
         f"({res['corrector_hbm_gbs_algorithmic']:.0f} GB/s), step {res['ms_step']:.3f} ms")
+
+    # the same mesh under a non-symmetric affine map (curvilinear elastic elements, one metric per element):
+    # the paper's benchmark physics over a full step
+    rng = np.random.default_rng(W.SEED0 + 61)
+    G = np.linalg.inv(np.eye(3) + 0.2 * rng.standard_normal((3, 3)))
+    parc = torch.cat([par.reshape(E, 3), torch.tensor(G.ravel(), device="cuda", dtype=torch.float32).expand(E, 9)],
+                     dim=1).contiguous().reshape(-1)
+    gmax = float(np.linalg.norm(G, axis=1).max())
+    dtc = 0.2 * h / ((2 * N + 1) * W.C_MAX[W.ELASTIC] * gmax)
+    plan = stp.Plan([(N, m, stp.ELASTIC_CURV, stp.PARAM_PER_ELEMENT)], prec=stp.BF16X3)
+    batch = plan.batch(E, Q, qavg, favg, qface, dtc, h, params=parc)
+    t_pred = time_launches(lambda st: plan.run(batch, st), args.steps, args.warmup, stream, torch)
+    t_corr = time_launches(lambda st: plan.correct((nx, ny, nz), dtc, h, Q, favg, qface, Qn, params=parc, stream=st),
+                           args.steps, args.warmup, stream, torch)
+
+    def step_c(st):
+        plan.run(batch, st)
+        plan.correct((nx, ny, nz), dtc, h, Q, favg, qface, Qn, params=parc, stream=st)
+
+    t_step = time_launches(step_c, args.steps, args.warmup, stream, torch)
+    plan.close()
+    res["curvilinear"] = {"workload": "the same mesh under a non-symmetric affine map: curvilinear elastic "
+                                      "elements with one metric per element (12 parameters)",
+                          "ms_predictor": float(np.median(t_pred)), "ms_corrector": float(np.median(t_corr)),
+                          "ms_step": float(np.median(t_step)),
+                          "element_steps_per_s": E / (float(np.median(t_step)) * 1e-3)}
+    log(f"[bench] full step (affine curvilinear): predictor {res['curvilinear']['ms_predictor']:.3f} ms, corrector "
+        f"{res['curvilinear']['ms_corrector']:.3f} ms, step {res['curvilinear']['ms_step']:.3f} ms")
     del Q, qavg, favg, qface, Qn
     torch.cuda.empty_cache()
     return res

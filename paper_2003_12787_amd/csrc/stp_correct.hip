@@ -17,6 +17,7 @@
 // 2 mu)/rho) max_d |G[d][:]|_2; the scheme is the Cartesian one in the reference coordinates of the mesh.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "stp_plan.hpp"
 
@@ -54,38 +55,52 @@ __device__ inline int64_t neighbour_of(const CorrArgs& a, int64_t e, int d, int 
 
 // (Bbar_d j) for a preset, from the face's averaged coefficients c = (1/rho, K) or (1/rho, lambda, mu): the
 // entries of the presets' B_d are linear in these, so the mean of two elements' B_d is B_d of the means.
-template <typename T>
-__device__ inline void preset_Bj(int physics, int d, const T* c, const T* j, T* out)
+// The direction is a template parameter so that every quantity index is a constant (no indexed register
+// arrays).
+template <typename T, int PHYS, int D>
+__device__ inline void preset_Bj(const T* c, const T* j, T* out)
 {
-    if (physics == kAcoustic) {
-        out[0] = c[1] * j[1 + d];  // p <- K d_d v_d
-        for (int i = 0; i < 3; ++i) out[1 + i] = i == d ? c[0] * j[0] : T(0);  // v_d <- d_d p / rho
+    if constexpr (PHYS == kAcoustic) {
+        out[0] = c[1] * j[1 + D];  // p <- K d_d v_d
+#pragma unroll
+        for (int i = 0; i < 3; ++i) out[1 + i] = i == D ? c[0] * j[0] : T(0);  // v_d <- d_d p / rho
     } else {
-        auto sig = [](int i, int k) { return i == k ? 3 + i : (i + k == 1 ? 6 : (i + k == 3 ? 7 : 8)); };
-        for (int i = 0; i < 3; ++i) out[i] = -c[0] * j[sig(i, d)];                          // v_i <- d_d s_id
-        for (int i = 0; i < 3; ++i) out[3 + i] = i == d ? -(c[1] + 2 * c[2]) * j[d] : -c[1] * j[d];  // s_ii <- v_d
+        constexpr auto sig = [](int i, int k) { return i == k ? 3 + i : (i + k == 1 ? 6 : (i + k == 3 ? 7 : 8)); };
+#pragma unroll
+        for (int i = 0; i < 3; ++i) out[i] = -c[0] * j[sig(i, D)];                          // v_i <- d_d s_id
+#pragma unroll
+        for (int i = 0; i < 3; ++i) out[3 + i] = i == D ? -(c[1] + 2 * c[2]) * j[D] : -c[1] * j[D];  // s_ii <- v_d
         out[6] = out[7] = out[8] = 0;
+#pragma unroll
         for (int i = 0; i < 3; ++i)
-            if (i != d) out[sig(d, i)] = -c[2] * j[i];                                       // s_di <- v_i
+            if (i != D) out[sig(D, i)] = -c[2] * j[i];                                       // s_di <- v_i
     }
 }
 
 // (Bbar_d j) for curvilinear elements: B_d = sum_j G[d][j] M_j is bilinear in the metric and the material,
 // so the mean over the two elements of the face is taken of the products, side by side. p0, p1: the 12
 // parameters (rho, lambda, mu, G) of the element and of its neighbour.
-template <typename T>
-__device__ inline void curv_Bj(int d, const T* p0, const T* p1, const T* j, T* out)
+template <typename T, int K>
+__device__ inline void curv_term(const T* c, T g, const T* j, T* out)
 {
+    T t[9];
+    preset_Bj<T, kElastic, K>(c, j, t);
+#pragma unroll
+    for (int r = 0; r < 9; ++r) out[r] = fma(g, t[r], out[r]);
+}
+
+template <typename T, int D>
+__device__ inline void curv_Bj(const T* p0, const T* p1, const T* j, T* out)
+{
+#pragma unroll
     for (int r = 0; r < 9; ++r) out[r] = 0;
+#pragma unroll
     for (int side = 0; side < 2; ++side) {
         const T* p = side ? p1 : p0;
         const T c[3] = {(T)1 / p[0], p[1], p[2]};
-        for (int k = 0; k < 3; ++k) {
-            T t[9];
-            preset_Bj<T>(kElastic, k, c, j, t);
-            const T g = (T)0.5 * p[3 + 3 * d + k];
-            for (int r = 0; r < 9; ++r) out[r] = fma(g, t[r], out[r]);
-        }
+        curv_term<T, 0>(c, (T)0.5 * p[3 + 3 * D], j, out);
+        curv_term<T, 1>(c, (T)0.5 * p[4 + 3 * D], j, out);
+        curv_term<T, 2>(c, (T)0.5 * p[5 + 3 * D], j, out);
     }
 }
 
@@ -177,7 +192,8 @@ __global__ void __launch_bounds__(kCorrThreads) stp_correct_kernel(CorrArgs a)
             }
         }
         __syncthreads();
-        // face corrections: one face point (all quantities) per work item
+        // face corrections: one face point (all quantities) per work item; the preset products are dispatched on
+        // the direction so that they index registers with constants
         const T* qf = static_cast<const T*>(a.qface);
         const T* ff = static_cast<const T*>(a.fface);
         for (int it = tid; it < 6 * n2; it += kCorrThreads) {
@@ -190,9 +206,14 @@ __global__ void __launch_bounds__(kCorrThreads) stp_correct_kernel(CorrArgs a)
             T jump[kCorrMaxM], bj[kCorrMaxM];
             for (int r = 0; r < m; ++r) jump[r] = qp[r] - qm[r];
             if constexpr (curv) {
-                curv_Bj<T>(d, cbar + f * 24, cbar + f * 24 + 12, jump, bj);
+                const T* c = cbar + f * 24;
+                if (d == 0) curv_Bj<T, 0>(c, c + 12, jump, bj);
+                else if (d == 1) curv_Bj<T, 1>(c, c + 12, jump, bj);
+                else curv_Bj<T, 2>(c, c + 12, jump, bj);
             } else if constexpr (preset) {
-                preset_Bj<T>(PHYS, d, cbar + f * 4, jump, bj);
+                if (d == 0) preset_Bj<T, PHYS, 0>(cbar + f * 4, jump, bj);
+                else if (d == 1) preset_Bj<T, PHYS, 1>(cbar + f * 4, jump, bj);
+                else preset_Bj<T, PHYS, 2>(cbar + f * 4, jump, bj);
             } else {
                 const T* Bf = Bbar + f * m * m;
                 for (int r = 0; r < m; ++r) {
