@@ -20,6 +20,9 @@ design notes):
   affine geometry (12 parameters per element: the material and the constant metric G[d][j] = h dxi_d/dx_j)
   take B_d = sum_j G[d][j] M_j and alpha = sqrt((lambda+2 mu)/rho) max_d |G[d][:]|_2 (the spectral radius of
   B_d in its worst direction): the scheme is the Cartesian one in the reference coordinates of the mesh.
+  Curved elements (the 12 parameters per node) take, at every face point, the parameters extrapolated from
+  each side's nodes with the face vectors l_j(0), l_j(1), B_d and alpha of those parameters on each side,
+  Bbar_d the mean of the two sides' B_d and alpha the larger speed.
 
   q(t_{n+1})_k = q(t_n)_k + dt sum_d favg[d]_k + dt sum_f l_{k_d}(x_f) / (h w_{k_d}) C_f(k_a, k_b)
 
@@ -31,6 +34,8 @@ Elements are numbered e = (iz * ny + iy) * nx + ix; the mesh is periodic in all 
 or coefficients are per element: presets [E, np] (rho, K) or (rho, lambda, mu); generic A, B [E, 3, m, m].
 """
 from __future__ import annotations
+
+import hashlib
 
 import numpy as np
 
@@ -72,6 +77,52 @@ def lagrange(xi, x: float) -> np.ndarray:
     return np.array([np.prod([(x - xi[k]) / (xi[j] - xi[k]) for k in range(n) if k != j]) for j in range(n)])
 
 
+def face_values(u, n: int, nodes: int = 0) -> np.ndarray:
+    """Nodal data u [E, n^3, c] extrapolated to the six faces [E, 6, n, n, c] (face node (a, b) = the two other
+    axes, slower first) with the face vectors l_j(0), l_j(1) along the normal."""
+    E = u.shape[0]
+    U = np.asarray(u, dtype=np.float64).reshape(E, n, n, n, -1)  # [e][z][y][x][c]
+    xi, _ = oracle.nodes_of(n, nodes)
+    l0, l1 = lagrange(xi, 0.0), lagrange(xi, 1.0)
+    out = np.empty((E, 6, n, n, U.shape[-1]))
+    for side, lv in ((0, l0), (1, l1)):
+        out[:, 0 + side] = np.einsum("j,ezyjc->ezyc", lv, U)  # x faces: (a, b) = (z, y)
+        out[:, 2 + side] = np.einsum("j,ezjxc->ezxc", lv, U)  # y faces: (a, b) = (z, x)
+        out[:, 4 + side] = np.einsum("j,ejyxc->eyxc", lv, U)  # z faces: (a, b) = (y, x)
+    return out
+
+
+def curved_speed(P) -> float:
+    """alpha of one face point's curvilinear parameters (rho, lambda, mu, G)."""
+    G = np.asarray(P[3:]).reshape(3, 3)
+    return float(np.sqrt((P[1] + 2 * P[2]) / P[0]) * np.linalg.norm(G, axis=1).max())
+
+
+_face_cache: dict = {}
+
+
+def curved_face_coefficients(params, n: int, nodes: int = 0):
+    """B_{d_f} [E, 6, n, n, 9, 9] and alpha [E, 6, n, n] of the parameters extrapolated to every face point
+    (memoised on the parameter values: they do not change between steps)."""
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    key = (hashlib.sha1(params.tobytes()).hexdigest(), params.shape, n, nodes)
+    if key not in _face_cache:
+        fp = face_values(params, n, nodes)
+        E = fp.shape[0]
+        Bf = np.empty((E, 6, n, n, 9, 9))
+        af = np.empty((E, 6, n, n))
+        for e in range(E):
+            for f in range(6):
+                for ia in range(n):
+                    for ib in range(n):
+                        P = fp[e, f, ia, ib]
+                        Bf[e, f, ia, ib] = oracle.preset_B(ELASTIC_CURV, P)[f // 2]
+                        af[e, f, ia, ib] = curved_speed(P)
+        _face_cache.clear()
+        _face_cache[key] = (Bf, af)
+    return _face_cache[key]
+
+
 def neighbour(e: int, d: int, s: int, nx: int, ny: int, nz: int) -> int:
     """The periodic neighbour of element e across its face along d on side s (-1 lower, +1 upper)."""
     ix, iy, iz = e % nx, (e // nx) % ny, e // (nx * ny)
@@ -90,7 +141,8 @@ def correct(N: int, physics: int, grid, Q, favg, qface, dt: float, h: float, par
 
     Q [E, n^3, m]; favg [E, 3, n^3, m] (or [E, n^3, m] with favg_sum); qface, fface [E, 6, n^2, m] with the
     faces ordered x-, x+, y-, y+, z-, z+ and the face nodes (a, b) = the two other axes, slower first.
-    Presets take params [E, np] (np = 2, 3, or 12 for affine curvilinear elements)."""
+    Presets take params [E, np] (np = 2, 3, or 12 for affine curvilinear elements); curved curvilinear elements
+    take params [E, n^3, 12]."""
     nx, ny, nz = grid
     n = N + 1
     E = nx * ny * nz
@@ -100,8 +152,12 @@ def correct(N: int, physics: int, grid, Q, favg, qface, dt: float, h: float, par
     vol = fa.reshape(E, n ** 3, m) if favg_sum else fa.reshape(E, 3, n ** 3, m).sum(axis=1)
     qf = np.asarray(qface, dtype=np.float64).reshape(E, 6, n, n, m)
     ff = None if fface is None else np.asarray(fface, dtype=np.float64).reshape(E, 6, n, n, m)
-    Bd = element_B(physics, params, B)
-    alpha = wave_speed(physics, params, A, B)
+    curved = physics == ELASTIC_CURV and np.asarray(params).ndim == 3
+    if curved:
+        Bf, af = curved_face_coefficients(params, n, nodes)
+    else:
+        Bd = element_B(physics, params, B)
+        alpha = wave_speed(physics, params, A, B)
     xi, w = oracle.nodes_of(n, nodes)
     l0 = lagrange(xi, 0.0)
     l1 = lagrange(xi, 1.0)
@@ -113,9 +169,14 @@ def correct(N: int, physics: int, grid, Q, favg, qface, dt: float, h: float, par
                 nb = neighbour(e, d, s, nx, ny, nz)
                 fo = 2 * d + (1 - side)  # the neighbour's face on the shared plane
                 jump = qf[nb, fo] - qf[e, f]  # [a][b][m]
-                Bbar = 0.5 * (Bd[e, d] + Bd[nb, d])
-                a = max(alpha[e], alpha[nb])
-                C = 0.5 * a * jump - 0.5 * s * jump @ Bbar.T
+                if curved:  # B_d and alpha of each side's extrapolated parameters at every face point
+                    Bbar = 0.5 * (Bf[e, f] + Bf[nb, fo])  # [a][b][m][m]
+                    a = np.maximum(af[e, f], af[nb, fo])[..., None]
+                    C = 0.5 * a * jump - 0.5 * s * np.einsum("abrc,abc->abr", Bbar, jump)
+                else:
+                    Bbar = 0.5 * (Bd[e, d] + Bd[nb, d])
+                    a = max(alpha[e], alpha[nb])
+                    C = 0.5 * a * jump - 0.5 * s * jump @ Bbar.T
                 if ff is not None:
                     C -= 0.5 * s * (ff[nb, fo] - ff[e, f])
                 lift = (l1 if side else l0) / (h * w)  # [k_d]
@@ -131,7 +192,9 @@ def correct(N: int, physics: int, grid, Q, favg, qface, dt: float, h: float, par
 
 def ader_step(N: int, physics: int, grid, Q, dt: float, h: float, params=None, A=None, B=None, nodes: int = 0):
     """One full ADER-DG step: the oracle predictor on every element, then the corrector. Per-element
-    coefficients (params [E, np] or A, B [E, 3, m, m]); nodes 0 Gauss-Legendre, 1 Gauss-Lobatto."""
-    pred = oracle.stp(N, physics, Q, dt, h, params=params, A=A, B=B, coef_per_element=True, nodes=nodes)
+    coefficients (params [E, np] or A, B [E, 3, m, m]), or curvilinear parameters per node [E, n^3, 12];
+    nodes 0 Gauss-Legendre, 1 Gauss-Lobatto."""
+    per_elem = not (physics == ELASTIC_CURV and np.asarray(params).ndim == 3)
+    pred = oracle.stp(N, physics, Q, dt, h, params=params, A=A, B=B, coef_per_element=per_elem, nodes=nodes)
     return correct(N, physics, grid, Q, pred["favg"], pred["qface"], dt, h, params=params, A=A, B=B,
                    fface=pred.get("fface"), nodes=nodes)

@@ -187,3 +187,52 @@ def test_curvilinear_with_identity_metric_is_the_cartesian_step():
     a = OC.ader_step(N, ELASTIC, grid, Q, 0.01, 0.5, params=par)
     b = OC.ader_step(N, 3, grid, Q, 0.01, 0.5, params=pc)
     assert np.abs(a - b).max() < 1e-14
+
+
+def curved_wave_setup(N, M, eps=0.1):
+    """M^3 elements of the unit box under the smooth periodic deformation of the curvilinear workloads; a
+    P-wave along x_0, q = r sin(2 pi (x_0 - c_p t)), periodic on the deformed box. Returns the node positions,
+    the per-node parameters [E, n^3, 12], r, c_p and the largest Rusanov speed."""
+    from paper_2003_12787_amd import workloads as W
+    rho, lam, mu = 2.0, 3.0, 1.5
+    cp = np.sqrt((lam + 2 * mu) / rho)
+    x, G = W.curvilinear_geometry(N, (M, M, M), 1.0 / M, eps)
+    E, n3 = x.shape[:2]
+    params = np.concatenate([np.broadcast_to([rho, lam, mu], (E, n3, 3)), G.reshape(E, n3, 9)], axis=2)
+    S = -(lam * np.eye(3) + 2 * mu * np.outer([1, 0, 0], [1, 0, 0])) / cp
+    r = np.concatenate([[1.0, 0, 0], [S[0, 0], S[1, 1], S[2, 2], S[0, 1], S[1, 2], S[0, 2]]])
+    alpha = cp * np.linalg.norm(G, axis=3).max()
+    return x, params, r, cp, alpha
+
+
+def test_curved_elements_constant_parameters_are_the_affine_step():
+    """Parameters given per node but constant in every element reproduce the per-element (affine) step."""
+    rng = np.random.default_rng(14)
+    N, grid, E, n3 = 2, (3, 2, 2), 12, 27
+    par = np.concatenate([np.stack([rng.uniform(2, 3, E), rng.uniform(1, 4, E), rng.uniform(1, 3, E)], axis=1),
+                          (np.eye(3) + 0.2 * rng.standard_normal((E, 3, 3))).reshape(E, 9)], axis=1)
+    Q = rng.standard_normal((E, n3, 9))
+    a = OC.ader_step(N, 3, grid, Q, 0.01, 0.5, params=par)
+    b = OC.ader_step(N, 3, grid, Q, 0.01, 0.5, params=np.repeat(par[:, None, :], n3, axis=1))
+    assert np.abs(a - b).max() < 1e-14 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_curved_mesh_plane_wave_converges(N):
+    """Curved elements (metric per node) of the deformed periodic box: a P-wave converges at order >= N + 1 -
+    0.5 over full ADER-DG steps (4^3 -> 8^3 elements)."""
+    errs = []
+    for M in (4, 8):
+        x, params, r, cp, alpha = curved_wave_setup(N, M)
+        h = 1.0 / M
+        f = lambda t: np.sin(2 * np.pi * (x[..., 0] - cp * t))
+        Q = f(0.0)[..., None] * r
+        T = 0.05
+        steps = int(np.ceil(T / full_step_dt(N, h, alpha)))
+        dt = T / steps
+        for _ in range(steps):
+            Q = OC.ader_step(N, 3, (M, M, M), Q, dt, h, params=params)
+        errs.append(np.abs(Q - f(T)[..., None] * r).max())
+    rate = np.log2(errs[0] / errs[1])
+    print(f"curved mesh N={N}: errors {errs}, rate {rate:.2f}")
+    assert rate > N + 1 - 0.5, (errs, rate)
