@@ -15,6 +15,9 @@
 // elastic elements with affine geometry carry rho, lambda, mu and the constant metric G[d][j] = h dxi_d/dx_j
 // (12 values): B_d = sum_j G[d][j] M_j with M_j the Cartesian elastic matrices, and alpha = sqrt((lambda +
 // 2 mu)/rho) max_d |G[d][:]|_2; the scheme is the Cartesian one in the reference coordinates of the mesh.
+// Curved elements carry the 12 parameters per node: at every face point each side's parameters are
+// extrapolated from its nodes along the normal with the face vectors, and B_d and alpha are those of the
+// extrapolated parameters (mean of the two sides' B_d, larger alpha).
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
@@ -31,6 +34,7 @@ constexpr int kCorrMaxM = 16;
 struct CorrArgs {
     int nx, ny, nz;
     int N, m, physics, favg_sum, hasA;
+    int per_node;      // curvilinear elements with parameters per node [e][n^3][12]
     double dt, h;
     const void* Q;
     const void* coef;  // presets: params [e][np]; generic: B [e][3][m][m]
@@ -104,6 +108,18 @@ __device__ inline void curv_Bj(const T* p0, const T* p1, const T* j, T* out)
     }
 }
 
+// alpha of curvilinear parameters (rho, lambda, mu, G)
+template <typename T>
+__device__ inline T curv_speed(const T* p)
+{
+    T g = 0;
+    for (int d = 0; d < 3; ++d) {
+        const T r = sqrt(p[3 + 3 * d] * p[3 + 3 * d] + p[4 + 3 * d] * p[4 + 3 * d] + p[5 + 3 * d] * p[5 + 3 * d]);
+        g = r > g ? r : g;
+    }
+    return sqrt((p[1] + 2 * p[2]) / p[0]) * g;
+}
+
 template <typename T>
 __device__ T wave_speed(const CorrArgs& a, int64_t e)
 {
@@ -115,15 +131,7 @@ __device__ T wave_speed(const CorrArgs& a, int64_t e)
         const T* p = static_cast<const T*>(a.coef) + e * 3;
         return sqrt((p[1] + 2 * p[2]) / p[0]);
     }
-    if (a.physics == kElasticCurv) {
-        const T* p = static_cast<const T*>(a.coef) + e * 12;
-        T g = 0;
-        for (int d = 0; d < 3; ++d) {
-            const T r = sqrt(p[3 + 3 * d] * p[3 + 3 * d] + p[4 + 3 * d] * p[4 + 3 * d] + p[5 + 3 * d] * p[5 + 3 * d]);
-            g = r > g ? r : g;
-        }
-        return sqrt((p[1] + 2 * p[2]) / p[0]) * g;
-    }
+    if (a.physics == kElasticCurv) return curv_speed(static_cast<const T*>(a.coef) + e * 12);
     const int m = a.m;
     const T* B = static_cast<const T*>(a.coef) + e * 3 * m * m;
     const T* A = a.hasA ? static_cast<const T*>(a.A) + e * 3 * m * m : nullptr;
@@ -154,16 +162,20 @@ __global__ void __launch_bounds__(kCorrThreads) stp_correct_kernel(CorrArgs a)
     T* alpha = Cf + 6 * n2 * m;            // [6]
     T* lift0 = alpha + 8;                  // [n] l_j(0) / (h w_j)
     T* lift1 = lift0 + n;                  // [n] l_j(1) / (h w_j)
+    T* ev0 = lift1 + n;                    // [n] l_j(0)
+    T* ev1 = ev0 + n;                      // [n] l_j(1)
     const int64_t nelem = (int64_t)a.nx * a.ny * a.nz;
     const int tid = threadIdx.x;
     if (tid < n) {
         const T* w = static_cast<const T*>(a.w);
         lift0[tid] = static_cast<const T*>(a.e0)[tid] / ((T)a.h * w[tid]);
         lift1[tid] = static_cast<const T*>(a.e1)[tid] / ((T)a.h * w[tid]);
+        ev0[tid] = static_cast<const T*>(a.e0)[tid];
+        ev1[tid] = static_cast<const T*>(a.e1)[tid];
     }
     for (int64_t e = blockIdx.x; e < nelem; e += gridDim.x) {
         // per-face mean coefficients and Rusanov speeds
-        if (tid < 6) {
+        if (tid < 6 && !(curv && a.per_node)) {
             const int d = tid >> 1, s = (tid & 1) ? 1 : -1;
             const int64_t nb = neighbour_of(a, e, d, s);
             if constexpr (curv) {
@@ -205,11 +217,36 @@ __global__ void __launch_bounds__(kCorrThreads) stp_correct_kernel(CorrArgs a)
             const T* qp = qf + ((nb * 6 + fo) * n2 + pt) * m;
             T jump[kCorrMaxM], bj[kCorrMaxM];
             for (int r = 0; r < m; ++r) jump[r] = qp[r] - qm[r];
+            T al = 0;
             if constexpr (curv) {
-                const T* c = cbar + f * 24;
-                if (d == 0) curv_Bj<T, 0>(c, c + 12, jump, bj);
-                else if (d == 1) curv_Bj<T, 1>(c, c + 12, jump, bj);
-                else curv_Bj<T, 2>(c, c + 12, jump, bj);
+                if (a.per_node) {  // curved: both sides' parameters extrapolated to the face point (registers)
+                    T ext[24];
+                    const T* par = static_cast<const T*>(a.coef);
+                    const T* evm = side ? ev1 : ev0;  // own face vector, and the neighbour's opposite one
+                    const T* evp = side ? ev0 : ev1;
+                    const int fa = pt / n, fb = pt - fa * n;
+                    for (int i = 0; i < 24; ++i) ext[i] = 0;
+                    for (int j = 0; j < n; ++j) {
+                        const int node = d == 0 ? (fa * n + fb) * n + j : (d == 1 ? (fa * n + j) * n + fb : (j * n + fa) * n + fb);
+                        const T* pm = par + (e * n3 + node) * 12;
+                        const T* pp = par + (nb * n3 + node) * 12;
+                        for (int i = 0; i < 12; ++i) {
+                            ext[i] = fma(evm[j], pm[i], ext[i]);
+                            ext[12 + i] = fma(evp[j], pp[i], ext[12 + i]);
+                        }
+                    }
+                    const T a0 = curv_speed(ext), a1 = curv_speed(ext + 12);
+                    al = a0 > a1 ? a0 : a1;
+                    if (d == 0) curv_Bj<T, 0>(ext, ext + 12, jump, bj);
+                    else if (d == 1) curv_Bj<T, 1>(ext, ext + 12, jump, bj);
+                    else curv_Bj<T, 2>(ext, ext + 12, jump, bj);
+                } else {  // affine: the two elements' parameters staged in LDS
+                    const T* c = cbar + f * 24;
+                    al = alpha[f];
+                    if (d == 0) curv_Bj<T, 0>(c, c + 12, jump, bj);
+                    else if (d == 1) curv_Bj<T, 1>(c, c + 12, jump, bj);
+                    else curv_Bj<T, 2>(c, c + 12, jump, bj);
+                }
             } else if constexpr (preset) {
                 if (d == 0) preset_Bj<T, PHYS, 0>(cbar + f * 4, jump, bj);
                 else if (d == 1) preset_Bj<T, PHYS, 1>(cbar + f * 4, jump, bj);
@@ -222,7 +259,7 @@ __global__ void __launch_bounds__(kCorrThreads) stp_correct_kernel(CorrArgs a)
                     bj[r] = acc;
                 }
             }
-            const T al = alpha[f];
+            if constexpr (!curv) al = alpha[f];
             for (int r = 0; r < m; ++r) {
                 T v = (T)0.5 * al * jump[r] - (T)0.5 * s * bj[r];
                 if (a.hasA) {
@@ -281,7 +318,7 @@ const void* corr_kernel(int N, int physics)
 size_t corr_lds(int N, int m, size_t io)
 {
     const int n = N + 1;
-    return io * (size_t)(6 * m * m + 144 + 6 * n * n * m + 8 + 2 * n);
+    return io * (size_t)(6 * m * m + 144 + 6 * n * n * m + 8 + 4 * n);
 }
 
 }  // namespace
@@ -298,10 +335,10 @@ extern "C" stp_status stp_correct(stp_plan_t p, const stp_step* st, void* stream
     const ClassState& cs = p->classes[0];
     const stp_class& c = cs.cls;
     const bool generic = c.physics == STP_GENERIC;
-    if (generic ? !(c.flags & STP_COEF_PER_ELEMENT) : !(c.flags & STP_PARAM_PER_ELEMENT))
+    const bool curv = c.physics == STP_ELASTIC_CURV;  // affine (per element) or curved (per node)
+    if (!curv && (generic ? !(c.flags & STP_COEF_PER_ELEMENT) : !(c.flags & STP_PARAM_PER_ELEMENT)))
         return fail(STP_E_UNSUPPORTED, "the corrector needs per-element coefficients (STP_PARAM_PER_ELEMENT or "
-                                       "STP_COEF_PER_ELEMENT%s)",
-                    c.physics == STP_ELASTIC_CURV ? "; curvilinear elements: affine geometry only" : "");
+                                       "STP_COEF_PER_ELEMENT)");
     if (c.flags & STP_SRC_POINT) return fail(STP_E_UNSUPPORTED, "point sources are not supported by the corrector");
     if (st->nx < 1 || st->ny < 1 || st->nz < 1) return fail(STP_E_INVAL, "mesh %d x %d x %d", st->nx, st->ny, st->nz);
     if ((int64_t)st->nx * st->ny * st->nz > (int64_t)INT32_MAX) return fail(STP_E_INVAL, "mesh too large");
@@ -333,6 +370,7 @@ extern "C" stp_status stp_correct(stp_plan_t p, const stp_step* st, void* stream
     a.m = c.nquant;
     a.physics = c.physics;
     a.favg_sum = (c.flags & STP_FAVG_SUM) ? 1 : 0;
+    a.per_node = curv && !(c.flags & STP_PARAM_PER_ELEMENT) ? 1 : 0;
     a.hasA = hasA ? 1 : 0;
     a.dt = st->dt;
     a.h = st->h;

@@ -239,3 +239,71 @@ def test_gpu_affine_curvilinear_plane_wave_converges(N, gpu):
     say(f"[curvilinear convergence] N={N} errors {errs} rate {rate:.2f}")
     assert rate > N + 1 - 0.5, (errs, rate)
     plan.close()
+
+
+def curved_inputs(N, grid, seed):
+    """Per-node curvilinear parameters of a small deformed box and random Q. The material is constant in each
+    element (it jumps between elements); the face values extrapolate it, so it has to be smooth inside an
+    element, as the metric is."""
+    rng = np.random.default_rng(seed)
+    _, G = W.curvilinear_geometry(N, grid, 0.5, 0.15)
+    E, n3 = G.shape[:2]
+    mat = np.broadcast_to(W.elastic_material(rng, (E,))[:, None, :], (E, n3, 3))
+    params = np.concatenate([mat, G.reshape(E, n3, 9)], axis=2)
+    return rng.standard_normal((E, n3, 9)), params
+
+
+@pytest.mark.parametrize("N,prec", [(2, stp.FP64), (3, stp.FP64), (7, stp.FP32)])
+def test_curved_corrector_matches_oracle(N, prec, gpu):
+    """stp_correct on curved elements (12 parameters per node), fed with the oracle predictor's outputs."""
+    torch = gpu
+    grid = (3, 2, 2)
+    Q, params = curved_inputs(N, grid, 40 + N)
+    h, dt = 0.5, 0.005
+    rnd = (lambda a: a) if prec == stp.FP64 else (lambda a: None if a is None else a.astype(np.float32).astype(np.float64))
+    Q, params = rnd(Q), rnd(params)
+    pred = oracle.stp(N, ELASTIC_CURV, Q, dt, h, params=params)
+    favg, qface = rnd(pred["favg"]), rnd(pred["qface"])
+    ref = OC.correct(N, ELASTIC_CURV, grid, Q, favg, qface, dt, h, params=params)
+    say(f"[curved corrector] N={N} prec={prec} mesh={grid}")
+    plan = stp.Plan([(N, 9, ELASTIC_CURV, 0)], prec=prec)
+    tdt = torch.float64 if prec == stp.FP64 else torch.float32
+    up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", tdt)
+    Qn = torch.empty(Q.shape, device="cuda", dtype=tdt)
+    plan.correct(grid, dt, h, up(Q), up(favg), up(qface), Qn, params=up(params))
+    torch.cuda.synchronize()
+    err = rel(Qn.double().cpu().numpy(), ref)
+    say(f"[curved corrector]   max rel err {err:.2e}")
+    assert err < TOL[prec], err
+    plan.close()
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_gpu_curved_mesh_plane_wave_converges(N, gpu):
+    """End to end on the GPU (FP64): the oracle's curved-box P-wave (metric per node). The errors at 4^3
+    elements equal the oracle's, and the rate over 4^3 -> 8^3 -> 16^3 stays >= N + 1 - 0.5."""
+    from test_corrector_oracle import curved_wave_setup
+    torch = gpu
+    plan = stp.Plan([(N, 9, ELASTIC_CURV, 0)], prec=stp.FP64)
+    errs = []
+    for M in (4, 8, 16):
+        x, params, r, cp, alpha = curved_wave_setup(N, M)
+        h = 1.0 / M
+        f = lambda t: np.sin(2 * np.pi * (x[..., 0] - cp * t))
+        Q = f(0.0)[..., None] * r
+        T = 0.05
+        steps = int(np.ceil(T / (0.2 * h / ((2 * N + 1) * alpha))))
+        dt = T / steps
+        qo = Q.copy()
+        for k in range(steps):
+            Q = gpu_step(plan, stp.FP64, ELASTIC_CURV, N, (M, M, M), Q, params, None, None, dt, h, False, torch)
+            if M == 4:
+                qo = OC.ader_step(N, ELASTIC_CURV, (M, M, M), qo, dt, h, params=params)
+        if M == 4:
+            say(f"[curved convergence] N={N} M=4 GPU vs oracle after {steps} steps: {rel(Q, qo):.2e}")
+            assert rel(Q, qo) < 1e-11
+        errs.append(np.abs(Q - f(T)[..., None] * r).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    say(f"[curved convergence] N={N} errors {errs} rates {rates}")
+    assert rates[-1] > N + 1 - 0.5, (errs, rates)
+    plan.close()

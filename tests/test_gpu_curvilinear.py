@@ -117,12 +117,13 @@ def test_unsupported_combinations(gpu):
         with pytest.raises(stp.StpError) as ei:
             stp.Plan(cls, prec=prec, variant=variant)
         assert ei.value.status == stp.E_UNSUPPORTED
-    plan = stp.Plan([(3, 9, stp.ELASTIC_CURV, 0)], prec=stp.FP32)  # curved (per-node) geometry: no corrector
-    z = torch.zeros(8 * 64 * 9 * 3, device="cuda")
+    # the corrector rejects point sources for curvilinear classes as for the others
+    plan = stp.Plan([(3, 9, stp.ELASTIC_CURV, stp.SRC_POINT)], prec=stp.FP32)
+    z = torch.zeros(8 * 64 * 12 * 3, device="cuda")
     out = torch.zeros(8 * 64 * 9, device="cuda")
     st = stp.Step(2, 2, 2, 0.01, 0.5, z.data_ptr(), z.data_ptr(), None, None, z.data_ptr(), z.data_ptr(), None,
                   out.data_ptr())
-    assert plan.correct_status(st) == stp.E_UNSUPPORTED and "affine" in stp.last_error()
+    assert plan.correct_status(st) == stp.E_UNSUPPORTED and "point source" in stp.last_error()
     plan.close()
     torch.cuda.synchronize()
 
