@@ -45,8 +45,7 @@
  *                 the image of the reference cube under a map x(xi); by the chain rule the system becomes
  *                 q_t + sum_d B_d dq/dxi_d / h = 0 with B_d = sum_j G[d][j] M_j, M_j the Cartesian elastic
  *                 matrices and G[d][j] = h dxi_d/dx_j the metric terms (the inverse Jacobian of the map
- *                 scaled by the element size h; an undeformed cube of side h has G = I). The corrector
- *                 takes affine elements (STP_PARAM_PER_ELEMENT) only.
+ *                 scaled by the element size h; an undeformed cube of side h has G = I).
  *
  * Precision: STP_FP64 computes and stores in double. STP_FP32 and STP_BF16X3 read and write float; their
  * derivative contractions run in FP32 (VALU) or as three BF16 products with FP32 accumulation (MFMA).
@@ -198,7 +197,9 @@ stp_status stp_run(stp_plan_t plan, const stp_batch* batch, void* hip_stream);
  * Bbar_d the mean of both elements' B_d and alpha the larger fastest wave speed (acoustic sqrt(K/rho),
  * elastic sqrt((lambda + 2 mu)/rho), generic max_d ||A_d + B_d||_inf; curvilinear elements with affine
  * geometry, STP_ELASTIC_CURV with STP_PARAM_PER_ELEMENT: B_d = sum_j G[d][j] M_j, the mean taken of the two
- * elements' products, and sqrt((lambda + 2 mu)/rho) max_d |G[d][:]|_2). Node k receives
+ * elements' products, and sqrt((lambda + 2 mu)/rho) max_d |G[d][:]|_2; curved elements, parameters per node:
+ * the same with each side's parameters extrapolated to the face point by the face vectors, so the material
+ * must be smooth inside an element). Node k receives
  * dt l_{k_d}(face) / (h w_{k_d}) C at its face node (collocation on the plan's nodes, diagonal mass matrix).
  * Elements e = (iz * ny + iy) * nx + ix, uniform size h, periodic in x, y and z; layouts as in stp_batch,
  * contiguous (element e at e * size). Stability of the full step needs dt <= about 0.2 h / ((2N+1) c_max). */
@@ -206,7 +207,8 @@ typedef struct {
     int nx, ny, nz;       /* elements per direction (nx * ny * nz <= 2^31 - 1)                               */
     double dt, h;         /* time step (>= 0) and element size (> 0)                                          */
     const void* Q;        /* q(t_n) [e][n^3][m]                                                               */
-    const void* params;   /* presets: [e][np] (np = 2, 3 or 12; the class must have STP_PARAM_PER_ELEMENT)    */
+    const void* params;   /* presets: [e][np] (np = 2, 3 or 12, STP_PARAM_PER_ELEMENT); curvilinear without
+                             STP_PARAM_PER_ELEMENT: [e][n^3][12]                                             */
     const void* A;        /* generic: [e][d][m][m] (STP_COEF_PER_ELEMENT); NULL without STP_A_PRESENT         */
     const void* B;        /* generic: [e][d][m][m]                                                            */
     const void* favg;     /* stp_run outputs of the same elements with the same dt and h                      */
@@ -216,8 +218,7 @@ typedef struct {
 } stp_step;
 
 /* Queue the corrector of one step on `hip_stream`. Needs a single-class plan with per-element coefficients
- * (for curvilinear elements: affine geometry, one metric per element) and no point source
- * (STP_E_UNSUPPORTED otherwise); STP_E_INVAL for NULL or aliasing buffers, a mesh
+ * (curvilinear elements: per element or per node) and no point source (STP_E_UNSUPPORTED otherwise); STP_E_INVAL for NULL or aliasing buffers, a mesh
  * dimension < 1, h <= 0 or dt < 0. I/O precision as the plan's (double for STP_FP64, else float). */
 stp_status stp_correct(stp_plan_t plan, const stp_step* step, void* hip_stream);
 
