@@ -218,8 +218,8 @@ typedef struct {
 } stp_step;
 
 /* Queue the corrector of one step on `hip_stream`. Needs a single-class plan with per-element coefficients
- * (curvilinear elements: per element or per node) and no point source (STP_E_UNSUPPORTED otherwise); STP_E_INVAL for NULL or aliasing buffers, a mesh
- * dimension < 1, h <= 0 or dt < 0. I/O precision as the plan's (double for STP_FP64, else float). */
+ * (curvilinear elements: per element or per node) and no point source (STP_E_UNSUPPORTED otherwise);
+ * STP_E_INVAL for NULL or aliasing buffers, a mesh dimension < 1, h <= 0 or dt < 0. I/O precision as the plan's (double for STP_FP64, else float). */
 stp_status stp_correct(stp_plan_t plan, const stp_step* step, void* hip_stream);
 
 /* Describe the plan's choices as a JSON object into buf (NUL-terminated): per class the kernel variant,
