@@ -29,12 +29,14 @@ namespace stp {
 namespace {
 
 constexpr int kCorrThreads = 256;
+// Kernel instantiation tag of curved curvilinear elements (parameters per node [e][n^3][12]); the affine ones
+// (per element) use kElasticCurv.
+constexpr int kCurvNode = 4;
 constexpr int kCorrMaxM = 16;
 
 struct CorrArgs {
     int nx, ny, nz;
     int N, m, physics, favg_sum, hasA;
-    int per_node;      // curvilinear elements with parameters per node [e][n^3][12]
     double dt, h;
     const void* Q;
     const void* coef;  // presets: params [e][np]; generic: B [e][3][m][m]
@@ -154,7 +156,8 @@ __global__ void __launch_bounds__(kCorrThreads) stp_correct_kernel(CorrArgs a)
     constexpr int n = N + 1, n2 = n * n, n3 = n2 * n;
     const int m = PHYS == kAcoustic ? 4 : (PHYS == kGeneric ? a.m : 9);
     constexpr bool preset = PHYS != kGeneric;
-    constexpr bool curv = PHYS == kElasticCurv;
+    constexpr bool curv = PHYS == kElasticCurv || PHYS == kCurvNode;
+    constexpr bool per_node = PHYS == kCurvNode;
     T* Bbar = reinterpret_cast<T*>(smem);  // generic: [6][m][m] mean B_d of the element and its neighbour
     T* cbar = Bbar + (preset ? 0 : 6 * m * m);  // presets: [6][4] mean (1/rho, K) or (1/rho, lambda, mu);
                                                // curvilinear: [6][2][12] parameters of both elements
@@ -175,7 +178,7 @@ __global__ void __launch_bounds__(kCorrThreads) stp_correct_kernel(CorrArgs a)
     }
     for (int64_t e = blockIdx.x; e < nelem; e += gridDim.x) {
         // per-face mean coefficients and Rusanov speeds
-        if (tid < 6 && !(curv && a.per_node)) {
+        if (tid < 6 && !per_node) {
             const int d = tid >> 1, s = (tid & 1) ? 1 : -1;
             const int64_t nb = neighbour_of(a, e, d, s);
             if constexpr (curv) {
@@ -219,7 +222,7 @@ __global__ void __launch_bounds__(kCorrThreads) stp_correct_kernel(CorrArgs a)
             for (int r = 0; r < m; ++r) jump[r] = qp[r] - qm[r];
             T al = 0;
             if constexpr (curv) {
-                if (a.per_node) {  // curved: both sides' parameters extrapolated to the face point (registers)
+                if constexpr (per_node) {  // curved: both sides' parameters extrapolated to the face point
                     T ext[24];
                     const T* par = static_cast<const T*>(a.coef);
                     const T* evm = side ? ev1 : ev0;  // own face vector, and the neighbour's opposite one
@@ -307,11 +310,12 @@ const void* corr_kernel_by_order(int N)
 }
 
 template <typename T>
-const void* corr_kernel(int N, int physics)
+const void* corr_kernel(int N, int physics, bool per_node)
 {
     if (physics == kAcoustic) return corr_kernel_by_order<T, kAcoustic>(N);
     if (physics == kElastic) return corr_kernel_by_order<T, kElastic>(N);
-    if (physics == kElasticCurv) return corr_kernel_by_order<T, kElasticCurv>(N);
+    if (physics == kElasticCurv)
+        return per_node ? corr_kernel_by_order<T, kCurvNode>(N) : corr_kernel_by_order<T, kElasticCurv>(N);
     return corr_kernel_by_order<T, kGeneric>(N);
 }
 
@@ -370,7 +374,6 @@ extern "C" stp_status stp_correct(stp_plan_t p, const stp_step* st, void* stream
     a.m = c.nquant;
     a.physics = c.physics;
     a.favg_sum = (c.flags & STP_FAVG_SUM) ? 1 : 0;
-    a.per_node = curv && !(c.flags & STP_PARAM_PER_ELEMENT) ? 1 : 0;
     a.hasA = hasA ? 1 : 0;
     a.dt = st->dt;
     a.h = st->h;
@@ -385,7 +388,9 @@ extern "C" stp_status stp_correct(stp_plan_t p, const stp_step* st, void* stream
     a.e1 = cs.de1;
     a.w = cs.dw;
     const size_t lds = corr_lds(c.order, c.nquant, io);
-    const void* fn = p->prec == STP_FP64 ? corr_kernel<double>(c.order, c.physics) : corr_kernel<float>(c.order, c.physics);
+    const bool per_node = curv && !(c.flags & STP_PARAM_PER_ELEMENT);
+    const void* fn = p->prec == STP_FP64 ? corr_kernel<double>(c.order, c.physics, per_node)
+                                         : corr_kernel<float>(c.order, c.physics, per_node);
     DeviceGuard g(p->device);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
