@@ -307,3 +307,53 @@ def test_gpu_curved_mesh_plane_wave_converges(N, gpu):
     say(f"[curved convergence] N={N} errors {errs} rates {rates}")
     assert rates[-1] > N + 1 - 0.5, (errs, rates)
     plan.close()
+
+
+def test_time_loop_captured_in_a_graph(gpu):
+    """Four full ADER-DG steps (stp_run then stp_correct, Q ping-ponging between two buffers) captured in one
+    HIP graph: every replay, with other work and synchronisations in between, reproduces the eager steps bit
+    for bit (curved curvilinear elements, FP32)."""
+    torch = gpu
+    N, grid = 3, (4, 3, 2)
+    Q0, params = curved_inputs(N, grid, 50)
+    E, n3, m = Q0.shape
+    n2 = (N + 1) ** 2
+    h = 0.5
+    dt = 0.2 * h / ((2 * N + 1) * 2.5)
+    plan = stp.Plan([(N, m, ELASTIC_CURV, 0)], prec=stp.FP32)
+    f32 = dict(device="cuda", dtype=torch.float32)
+    Qa, Qb = torch.from_numpy(Q0).to(**f32), torch.empty((E, n3, m), **f32)
+    par = torch.from_numpy(np.ascontiguousarray(params)).to(**f32)
+    qavg, favg = torch.empty((E, n3, m), **f32), torch.empty((E, 3, n3, m), **f32)
+    qface = torch.empty((E, 6, n2, m), **f32)
+    ba = plan.batch(E, Qa, qavg, favg, qface, dt, h, params=par)
+    bb = plan.batch(E, Qb, qavg, favg, qface, dt, h, params=par)
+
+    def four_steps(st):
+        for _ in range(2):
+            plan.run(ba, st)
+            plan.correct(grid, dt, h, Qa, favg, qface, Qb, params=par, stream=st)
+            plan.run(bb, st)
+            plan.correct(grid, dt, h, Qb, favg, qface, Qa, params=par, stream=st)
+
+    # eager reference: three times four steps from Q0
+    ref = []
+    four_steps(torch.cuda.current_stream())
+    for _ in range(3):
+        ref.append(Qa.clone())
+        four_steps(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    Qa.copy_(torch.from_numpy(Q0).to(**f32))
+    g = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    with torch.cuda.graph(g, stream=cap):
+        four_steps(cap)
+    other = torch.randn(1 << 20, device="cuda")
+    for k in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        say(f"[graph] replay {k}: max |diff| {float((Qa - ref[k]).abs().max()):.3e}")
+        assert torch.equal(Qa, ref[k]), k
+        other.mul_(1.0001)  # unrelated work between replays
+        torch.cuda.synchronize()
+    plan.close()
