@@ -129,6 +129,29 @@ def time_launches(fn, steps, warmup, stream, torch):
     return np.array([a.elapsed_time(b) for a, b in ev])
 
 
+def bench_lobatto(args, torch, stp, runner, b, ids):
+    """The benchmark workload on Gauss-Lobatto nodes (the other node family of Sec. II-A): the split-BF16x3
+    MFMA and FP32 fused kernels with the plan's Lobatto tables. Returns timings and sampled outputs of the
+    elements `ids` for the CPU leg."""
+    E = b.nelem
+    res = {"workload": "elastic N=7 benchmark workload on Gauss-Lobatto nodes (same inputs)"}
+    tid = torch.from_numpy(ids).cuda()
+    for name, prec, var in (("bf16x3_mfma", stp.BF16X3, stp.VARIANT_MFMA), ("fp32_fused", stp.FP32, stp.VARIANT_FUSED)):
+        plan = stp.Plan([runner.class_of(b)], prec=prec, variant=var, nodes=stp.GAUSS_LOBATTO)
+        db = runner.DeviceBatch(plan, b)
+        ms = float(np.median(time_launches(lambda st: plan.run(db.cbatch, st), args.steps, args.warmup,
+                                           torch.cuda.Stream(), torch)))
+        res[name] = {"ms": ms, "elements_per_s": E / (ms * 1e-3),
+                     "hbm_gbs_algorithmic": plan.cost(0)[0] * E / (ms * 1e-3) / 1e9,
+                     "sampled": {k: v.index_select(0, tid).double().cpu().numpy()
+                                 for k, v in (("qavg", db.qavg), ("favg", db.favg), ("qface", db.qface))}}
+        log(f"[bench] Gauss-Lobatto {name}: {ms:.3f} ms")
+        del db
+        plan.close()
+        torch.cuda.empty_cache()
+    return res
+
+
 def bench_acoustic(args, torch, stp, W, runner):
     """Acoustic plane wave, N = 5 (6^3 nodes), m = 4, 32768 elements, rho = 1, K per element: the plain
     FP64 predictor against the fused FP32 kernel (their accuracy against the oracle is a parity test)."""
@@ -523,6 +546,8 @@ def main():
     if args.copy_gib > 0:
         copy = copy_bandwidth(args.copy_gib, torch)
 
+    lob_ids = np.linspace(0, E - 1, min(E, 256)).astype(np.int64)
+    lobatto = None if args.no_hetero else bench_lobatto(args, torch, stp, runner, b, lob_ids)
     acoustic = None if args.no_hetero else bench_acoustic(args, torch, stp, W, runner)
     full_step = None if args.no_hetero else bench_full_step(args, torch, stp, W)
     curv = None if args.no_hetero else bench_curvilinear(args, torch, stp, W)
@@ -558,6 +583,20 @@ def main():
             results[name]["checked_elements"] = int(len(pos))
             log(f"[bench] {name}: max rel err vs oracle {errs}")
         del ref
+        if lobatto is not None:  # sampled parity on Gauss-Lobatto nodes
+            ref = oracle.stp(b.N, b.physics, b.Q[lob_ids], b.dt[lob_ids], b.h[lob_ids], params=b.params[lob_ids],
+                             nthreads=threads, nodes=1)
+            for name in ("bf16x3_mfma", "fp32_fused"):
+                got = lobatto[name]["sampled"]
+                errs = {}
+                for key in ("qavg", "favg", "qface"):
+                    y = ref[key].reshape(len(lob_ids), -1)
+                    x = got[key].reshape(len(lob_ids), -1)
+                    errs[key] = float((np.abs(x - y).max(axis=1) / np.abs(y).max(axis=1)).max())
+                lobatto[name]["max_rel_err_vs_oracle"] = errs
+                lobatto[name]["checked_elements"] = int(len(lob_ids))
+                log(f"[bench] Gauss-Lobatto {name}: max rel err vs oracle {errs}")
+            del ref
         if curv is not None:  # sampled parity of the curvilinear workload
             ck = curv["check"]
             ref = oracle.stp(7, W.ELASTIC_CURV, ck["Q"], ck["dt"], 1.0, params=ck["params"], nthreads=threads)
@@ -611,6 +650,9 @@ def main():
         "copy_reference": copy,
         "acoustic_n5": acoustic,
         "ader_dg_step": full_step,
+        "gauss_lobatto": None if lobatto is None else {k: ({kk: vv for kk, vv in v.items() if kk != "sampled"}
+                                                           if isinstance(v, dict) else v)
+                                                       for k, v in lobatto.items()},
         "curvilinear": None if curv is None else {k: ({kk: vv for kk, vv in v.items() if kk != "sampled"}
                                                       if isinstance(v, dict) else v)
                                                   for k, v in curv.items() if k != "check"},
