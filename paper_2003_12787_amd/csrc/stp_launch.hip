@@ -28,6 +28,42 @@ __global__ void bucket_by_class(const int32_t* cls, int64_t nelem, int nclass, i
     lists[(int64_t)c * cap + pos] = (int32_t)e;
 }
 
+// The three bucketing steps (clear, per-class lists, tile queues) in one workgroup with the counts in LDS, for
+// batches small enough that one workgroup sorts them quickly: two launches fewer per batch (serving batches
+// are a few hundred elements). Same outputs as clear_counts + bucket_by_class + hetero_setup (the order of the
+// elements inside a class list is arbitrary in both).
+constexpr int kBucketThreads = 1024;
+constexpr int64_t kBucketSmallMax = 65536;
+
+__global__ void __launch_bounds__(kBucketThreads)
+    bucket_small(const int32_t* cls, int64_t nelem, int nclass, int32_t* lists, int64_t cap, int32_t* counts,
+                 const int32_t* slots, const int32_t* orders, const int32_t* bncls, int32_t* tile_start, int32_t* heads)
+{
+    __shared__ int32_t cnt[kMaxClasses];
+    const int t = threadIdx.x;
+    if (t < kMaxClasses) cnt[t] = 0;
+    __syncthreads();
+    for (int64_t e = t; e < nelem; e += kBucketThreads) {
+        const int c = cls[e];
+        if (c < 0 || c >= nclass) continue;  // elements with an invalid class id are skipped
+        const int pos = atomicAdd(&cnt[c], 1);
+        lists[(int64_t)c * cap + pos] = (int32_t)e;
+    }
+    __syncthreads();
+    if (t < nclass) counts[t] = cnt[t];
+    if (t < kHeteroBuckets) {
+        int acc = 0;
+        const int nc = bncls[t];
+        for (int k = 0; k < nc; ++k) {
+            tile_start[t * (kMaxClasses + 1) + k] = acc;
+            const int c = orders[t * kMaxClasses + k];
+            acc += (cnt[c] + slots[c] - 1) / slots[c];
+        }
+        tile_start[t * (kMaxClasses + 1) + nc] = acc;
+        heads[t] = 0;
+    }
+}
+
 // Tile queues of the persistent kernel: for every bucket, the first tile of each class in processing order
 // and a reset tile counter. One thread per bucket.
 __global__ void hetero_setup(const int32_t* counts, const int32_t* slots, const int32_t* orders, const int32_t* bncls,
@@ -199,11 +235,16 @@ stp_status launch_batch(stp_plan_s* p, const stp_batch* b, hipStream_t stream, H
             if (st != STP_OK) return st;
         }
     }
-    hipLaunchKernelGGL(clear_counts, dim3(1), dim3(64), 0, stream, s->counts, nclass);
-    hipLaunchKernelGGL(bucket_by_class, dim3((unsigned)((b->nelem + 255) / 256)), dim3(256), 0, stream, b->cls,
-                       b->nelem, nclass, s->lists, s->cap, s->counts);
-    hipLaunchKernelGGL(hetero_setup, dim3(1), dim3(64), 0, stream, s->counts, p->d_slots, p->d_orders, p->d_bncls,
-                       s->tile_start, s->heads);
+    if (b->nelem <= kBucketSmallMax) {
+        hipLaunchKernelGGL(bucket_small, dim3(1), dim3(kBucketThreads), 0, stream, b->cls, b->nelem, nclass, s->lists,
+                           s->cap, s->counts, p->d_slots, p->d_orders, p->d_bncls, s->tile_start, s->heads);
+    } else {
+        hipLaunchKernelGGL(clear_counts, dim3(1), dim3(64), 0, stream, s->counts, nclass);
+        hipLaunchKernelGGL(bucket_by_class, dim3((unsigned)((b->nelem + 255) / 256)), dim3(256), 0, stream, b->cls,
+                           b->nelem, nclass, s->lists, s->cap, s->counts);
+        hipLaunchKernelGGL(hetero_setup, dim3(1), dim3(64), 0, stream, s->counts, p->d_slots, p->d_orders,
+                           p->d_bncls, s->tile_start, s->heads);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "bucketing launch");
     // classes with their own launch (high orders, FP64 accumulation or I/O), most expensive first
