@@ -215,12 +215,27 @@ typedef struct {
     const void* qface;
     const void* fface;    /* with STP_A_PRESENT only                                                          */
     void* Qnew;           /* q(t_{n+1}) [e][n^3][m]; must not alias Q, favg or qface                          */
+    const void* fparams;  /* curved curvilinear elements, optional: params extrapolated to the face points,
+                             [e][6][n^2][12] from stp_face_params of the same params (NULL: the corrector
+                             extrapolates them at every step, with the same arithmetic); NULL otherwise     */
 } stp_step;
 
 /* Queue the corrector of one step on `hip_stream`. Needs a single-class plan with per-element coefficients
  * (curvilinear elements: per element or per node) and no point source (STP_E_UNSUPPORTED otherwise);
  * STP_E_INVAL for NULL or aliasing buffers, a mesh dimension < 1, h <= 0 or dt < 0. I/O precision as the plan's (double for STP_FP64, else float). */
 stp_status stp_correct(stp_plan_t plan, const stp_step* step, void* hip_stream);
+
+/* The parameters of curved curvilinear elements (STP_ELASTIC_CURV without STP_PARAM_PER_ELEMENT, params
+ * [e][n^3][12]) at the points of their six faces: each of the 12 values extrapolated along the face normal
+ * with the face vector l_j(0) or l_j(1) of the plan's nodes, the face projection of Sec. II-A applied to the
+ * material and metric fields. fparams [e][6][n^2][12], faces and face nodes ordered as qface. These are the
+ * values the corrector forms at every face point; they do not change between steps, so a time loop computes
+ * them once and hands them to every stp_correct in stp_step.fparams, which then reads 24 values per face
+ * point instead of 24 n. The result is bit-identical to the corrector's own extrapolation. Queued on
+ * hip_stream (NULL = the null stream); allocates nothing; stream-capturable. STP_E_UNSUPPORTED unless the
+ * plan has a single class, a curved curvilinear one; STP_E_INVAL for NULL buffers, nelem outside
+ * 0..2^31-1 or fparams overlapping params. I/O precision as the plan's. */
+stp_status stp_face_params(stp_plan_t plan, int64_t nelem, const void* params, void* fparams, void* hip_stream);
 
 /* Describe the plan's choices as a JSON object into buf (NUL-terminated): per class the kernel variant,
  * whether it is tiled in the persistent heterogeneous launch and its elements per tile, FP64 accumulation;

@@ -17,7 +17,8 @@
 // 2 mu)/rho) max_d |G[d][:]|_2; the scheme is the Cartesian one in the reference coordinates of the mesh.
 // Curved elements carry the 12 parameters per node: at every face point each side's parameters are
 // extrapolated from its nodes along the normal with the face vectors, and B_d and alpha are those of the
-// extrapolated parameters (mean of the two sides' B_d, larger alpha).
+// extrapolated parameters (mean of the two sides' B_d, larger alpha). Those face values do not change between
+// steps: stp_face_params forms them once (same arithmetic), and the corrector then reads them per face point.
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
@@ -32,6 +33,8 @@ constexpr int kCorrThreads = 256;
 // Kernel instantiation tag of curved curvilinear elements (parameters per node [e][n^3][12]); the affine ones
 // (per element) use kElasticCurv.
 constexpr int kCurvNode = 4;
+// ... and of curved elements whose face-point parameters [e][6][n^2][12] are given (stp_face_params).
+constexpr int kCurvFace = 5;
 constexpr int kCorrMaxM = 16;
 
 struct CorrArgs {
@@ -45,6 +48,7 @@ struct CorrArgs {
     const void* qface;
     const void* fface;
     void* Qnew;
+    const void* fparams;  // curved elements: parameters at the face points [e][6][n^2][12], or NULL
     const void* e0;  // face vectors l_j(0), l_j(1) and quadrature weights on [0, 1] (compute precision)
     const void* e1;
     const void* w;
@@ -110,6 +114,29 @@ __device__ inline void curv_Bj(const T* p0, const T* p1, const T* j, T* out)
     }
 }
 
+// The node of the line along d through face node (fa, fb) (the two other axes, slower first), at index j.
+template <int n>
+__device__ inline int line_node(int d, int fa, int fb, int j)
+{
+    return d == 0 ? (fa * n + fb) * n + j : (d == 1 ? (fa * n + j) * n + fb : (j * n + fa) * n + fb);
+}
+
+// The 12 parameters of element nodes par [n^3][12] extrapolated to face node (fa, fb) of a face normal to d,
+// with that face's vector ev (l_j(0) or l_j(1)).
+template <typename T, int n>
+__device__ inline void face_extrapolate(const T* par, const T* ev, int d, int fa, int fb, T* ext)
+{
+#pragma unroll
+    for (int i = 0; i < 12; ++i) ext[i] = 0;
+#pragma unroll 1  // unrolled, the loads of all n nodes are hoisted and the corrector loses occupancy
+    for (int j = 0; j < n; ++j) {
+        const T* p = par + line_node<n>(d, fa, fb, j) * 12;
+        const T w = ev[j];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) ext[i] = fma(w, p[i], ext[i]);
+    }
+}
+
 // alpha of curvilinear parameters (rho, lambda, mu, G)
 template <typename T>
 __device__ inline T curv_speed(const T* p)
@@ -156,8 +183,9 @@ __global__ void __launch_bounds__(kCorrThreads) stp_correct_kernel(CorrArgs a)
     constexpr int n = N + 1, n2 = n * n, n3 = n2 * n;
     const int m = PHYS == kAcoustic ? 4 : (PHYS == kGeneric ? a.m : 9);
     constexpr bool preset = PHYS != kGeneric;
-    constexpr bool curv = PHYS == kElasticCurv || PHYS == kCurvNode;
+    constexpr bool curv = PHYS == kElasticCurv || PHYS == kCurvNode || PHYS == kCurvFace;
     constexpr bool per_node = PHYS == kCurvNode;
+    constexpr bool pointwise = per_node || PHYS == kCurvFace;  // parameters differ between face points
     T* Bbar = reinterpret_cast<T*>(smem);  // generic: [6][m][m] mean B_d of the element and its neighbour
     T* cbar = Bbar + (preset ? 0 : 6 * m * m);  // presets: [6][4] mean (1/rho, K) or (1/rho, lambda, mu);
                                                // curvilinear: [6][2][12] parameters of both elements
@@ -178,7 +206,7 @@ __global__ void __launch_bounds__(kCorrThreads) stp_correct_kernel(CorrArgs a)
     }
     for (int64_t e = blockIdx.x; e < nelem; e += gridDim.x) {
         // per-face mean coefficients and Rusanov speeds
-        if (tid < 6 && !per_node) {
+        if (tid < 6 && !pointwise) {
             const int d = tid >> 1, s = (tid & 1) ? 1 : -1;
             const int64_t nb = neighbour_of(a, e, d, s);
             if constexpr (curv) {
@@ -222,20 +250,21 @@ __global__ void __launch_bounds__(kCorrThreads) stp_correct_kernel(CorrArgs a)
             for (int r = 0; r < m; ++r) jump[r] = qp[r] - qm[r];
             T al = 0;
             if constexpr (curv) {
-                if constexpr (per_node) {  // curved: both sides' parameters extrapolated to the face point
+                if constexpr (pointwise) {  // curved: both sides' parameters at the face point
                     T ext[24];
-                    const T* par = static_cast<const T*>(a.coef);
-                    const T* evm = side ? ev1 : ev0;  // own face vector, and the neighbour's opposite one
-                    const T* evp = side ? ev0 : ev1;
-                    const int fa = pt / n, fb = pt - fa * n;
-                    for (int i = 0; i < 24; ++i) ext[i] = 0;
-                    for (int j = 0; j < n; ++j) {
-                        const int node = d == 0 ? (fa * n + fb) * n + j : (d == 1 ? (fa * n + j) * n + fb : (j * n + fa) * n + fb);
-                        const T* pm = par + (e * n3 + node) * 12;
-                        const T* pp = par + (nb * n3 + node) * 12;
+                    if constexpr (per_node) {  // extrapolated from the nodes: own face vector, the neighbour's
+                        const T* par = static_cast<const T*>(a.coef);  // opposite one
+                        const int fa = pt / n, fb = pt - fa * n;
+                        face_extrapolate<T, n>(par + e * n3 * 12, side ? ev1 : ev0, d, fa, fb, ext);
+                        face_extrapolate<T, n>(par + nb * n3 * 12, side ? ev0 : ev1, d, fa, fb, ext + 12);
+                    } else {
+                        const T* fp = static_cast<const T*>(a.fparams);
+                        const T* pm = fp + ((e * 6 + f) * n2 + pt) * 12;
+                        const T* pp = fp + ((nb * 6 + fo) * n2 + pt) * 12;
+#pragma unroll
                         for (int i = 0; i < 12; ++i) {
-                            ext[i] = fma(evm[j], pm[i], ext[i]);
-                            ext[12 + i] = fma(evp[j], pp[i], ext[12 + i]);
+                            ext[i] = pm[i];
+                            ext[12 + i] = pp[i];
                         }
                     }
                     const T a0 = curv_speed(ext), a1 = curv_speed(ext + 12);
@@ -310,12 +339,14 @@ const void* corr_kernel_by_order(int N)
 }
 
 template <typename T>
-const void* corr_kernel(int N, int physics, bool per_node)
+const void* corr_kernel(int N, int physics, bool per_node, bool face_params)
 {
     if (physics == kAcoustic) return corr_kernel_by_order<T, kAcoustic>(N);
     if (physics == kElastic) return corr_kernel_by_order<T, kElastic>(N);
-    if (physics == kElasticCurv)
-        return per_node ? corr_kernel_by_order<T, kCurvNode>(N) : corr_kernel_by_order<T, kElasticCurv>(N);
+    if (physics == kElasticCurv) {
+        if (!per_node) return corr_kernel_by_order<T, kElasticCurv>(N);
+        return face_params ? corr_kernel_by_order<T, kCurvFace>(N) : corr_kernel_by_order<T, kCurvNode>(N);
+    }
     return corr_kernel_by_order<T, kGeneric>(N);
 }
 
@@ -323,6 +354,42 @@ size_t corr_lds(int N, int m, size_t io)
 {
     const int n = N + 1;
     return io * (size_t)(6 * m * m + 144 + 6 * n * n * m + 8 + 4 * n);
+}
+
+constexpr int kFaceThreads = 256;
+
+// One work item per face point of an element: fp[e][f][pt][12] from par[e][n^3][12].
+template <typename T, int N>
+__global__ void __launch_bounds__(kFaceThreads) stp_face_params_kernel(int64_t nelem, const T* __restrict__ par,
+                                                                        T* __restrict__ fp, const T* e0, const T* e1)
+{
+    constexpr int n = N + 1, n2 = n * n, n3 = n2 * n;
+    const int64_t total = nelem * 6 * n2;
+    for (int64_t it = blockIdx.x * (int64_t)kFaceThreads + threadIdx.x; it < total;
+         it += (int64_t)gridDim.x * kFaceThreads) {
+        const int64_t e = it / (6 * n2);
+        const int r = (int)(it - e * (6 * n2)), f = r / n2, pt = r - f * n2, fa = pt / n;
+        T ext[12];
+        face_extrapolate<T, n>(par + e * n3 * 12, (f & 1) ? e1 : e0, f >> 1, fa, pt - fa * n, ext);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) fp[it * 12 + i] = ext[i];
+    }
+}
+
+template <typename T>
+const void* face_params_kernel(int N)
+{
+    switch (N) {
+    case 1: return reinterpret_cast<const void*>(&stp_face_params_kernel<T, 1>);
+    case 2: return reinterpret_cast<const void*>(&stp_face_params_kernel<T, 2>);
+    case 3: return reinterpret_cast<const void*>(&stp_face_params_kernel<T, 3>);
+    case 4: return reinterpret_cast<const void*>(&stp_face_params_kernel<T, 4>);
+    case 5: return reinterpret_cast<const void*>(&stp_face_params_kernel<T, 5>);
+    case 6: return reinterpret_cast<const void*>(&stp_face_params_kernel<T, 6>);
+    case 7: return reinterpret_cast<const void*>(&stp_face_params_kernel<T, 7>);
+    case 8: return reinterpret_cast<const void*>(&stp_face_params_kernel<T, 8>);
+    default: return reinterpret_cast<const void*>(&stp_face_params_kernel<T, 9>);
+    }
 }
 
 }  // namespace
@@ -352,6 +419,9 @@ extern "C" stp_status stp_correct(stp_plan_t p, const stp_step* st, void* stream
     if (!st->Q || !st->favg || !st->qface || !st->Qnew) return fail(STP_E_INVAL, "Q / favg / qface / Qnew is NULL");
     if (generic ? !st->B : !st->params) return fail(STP_E_INVAL, "coefficients are NULL");
     if (hasA && (!st->A || !st->fface)) return fail(STP_E_INVAL, "A / fface is NULL for a class with A present");
+    const bool per_node = curv && !(c.flags & STP_PARAM_PER_ELEMENT);
+    if (st->fparams && !per_node)
+        return fail(STP_E_INVAL, "fparams is for curved curvilinear elements (parameters per node) only");
     const int64_t E = (int64_t)st->nx * st->ny * st->nz;
     const size_t io = p->prec == STP_FP64 ? 8 : 4;
     {
@@ -359,8 +429,10 @@ extern "C" stp_status stp_correct(stp_plan_t p, const stp_step* st, void* stream
         const size_t fmul = (c.flags & STP_FAVG_SUM) ? 1 : 3;
         struct R { const void* q; size_t bytes; const char* name; };
         const R ins[] = {{st->Q, (size_t)E * cs.size_q * io, "Q"}, {st->favg, (size_t)E * fmul * cs.size_q * io, "favg"},
-                         {st->qface, (size_t)E * cs.size_face * io, "qface"}};
+                         {st->qface, (size_t)E * cs.size_face * io, "qface"},
+                         {st->fparams, (size_t)E * 6 * (c.order + 1) * (c.order + 1) * 12 * io, "fparams"}};
         for (const R& r : ins) {
+            if (!r.q) continue;
             const uintptr_t a0 = (uintptr_t)r.q, a1 = a0 + r.bytes;
             if (a0 < o1 && o0 < a1) return fail(STP_E_INVAL, "Qnew aliases %s", r.name);
         }
@@ -384,13 +456,14 @@ extern "C" stp_status stp_correct(stp_plan_t p, const stp_step* st, void* stream
     a.qface = st->qface;
     a.fface = st->fface;
     a.Qnew = st->Qnew;
+    a.fparams = st->fparams;
     a.e0 = cs.de0;
     a.e1 = cs.de1;
     a.w = cs.dw;
     const size_t lds = corr_lds(c.order, c.nquant, io);
-    const bool per_node = curv && !(c.flags & STP_PARAM_PER_ELEMENT);
-    const void* fn = p->prec == STP_FP64 ? corr_kernel<double>(c.order, c.physics, per_node)
-                                         : corr_kernel<float>(c.order, c.physics, per_node);
+    const bool fpar = st->fparams != nullptr;
+    const void* fn = p->prec == STP_FP64 ? corr_kernel<double>(c.order, c.physics, per_node, fpar)
+                                         : corr_kernel<float>(c.order, c.physics, per_node, fpar);
     DeviceGuard g(p->device);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -400,5 +473,34 @@ extern "C" stp_status stp_correct(stp_plan_t p, const stp_step* st, void* stream
     void* args[] = {&a};
     hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kCorrThreads), args, lds, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "hipLaunchKernel(corrector)");
+    return STP_OK;
+}
+
+extern "C" stp_status stp_face_params(stp_plan_t p, int64_t nelem, const void* params, void* fparams, void* stream)
+{
+    if (!p) return fail(STP_E_INVAL, "plan is NULL");
+    if (p->classes.size() != 1) return fail(STP_E_UNSUPPORTED, "stp_face_params takes a single-class plan");
+    const ClassState& cs = p->classes[0];
+    const stp_class& c = cs.cls;
+    if (c.physics != STP_ELASTIC_CURV || (c.flags & STP_PARAM_PER_ELEMENT))
+        return fail(STP_E_UNSUPPORTED, "stp_face_params is for curved curvilinear elements (STP_ELASTIC_CURV, "
+                                       "parameters per node)");
+    if (nelem < 0 || nelem > (int64_t)INT32_MAX) return fail(STP_E_INVAL, "nelem %lld", (long long)nelem);
+    if (!params || !fparams) return fail(STP_E_INVAL, "params / fparams is NULL");
+    const size_t io = p->prec == STP_FP64 ? 8 : 4;
+    const int n = c.order + 1;
+    {
+        const uintptr_t i0 = (uintptr_t)params, i1 = i0 + (size_t)nelem * n * n * n * 12 * io;
+        const uintptr_t o0 = (uintptr_t)fparams, o1 = o0 + (size_t)nelem * 6 * n * n * 12 * io;
+        if (i0 < o1 && o0 < i1) return fail(STP_E_INVAL, "fparams overlaps params");
+    }
+    if (nelem == 0) return STP_OK;
+    const int64_t items = nelem * 6 * n * n;
+    const unsigned grid = (unsigned)std::min<int64_t>((items + kFaceThreads - 1) / kFaceThreads, 1 << 20);
+    const void* fn = p->prec == STP_FP64 ? face_params_kernel<double>(c.order) : face_params_kernel<float>(c.order);
+    DeviceGuard g(p->device);
+    void* args[] = {&nelem, &params, &fparams, const_cast<void**>(&cs.de0), const_cast<void**>(&cs.de1)};
+    hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kFaceThreads), args, 0, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "hipLaunchKernel(face parameters)");
     return STP_OK;
 }

@@ -25,7 +25,7 @@ VARIANT_AUTO, VARIANT_PLAIN, VARIANT_FUSED, VARIANT_MFMA = 0, 1, 2, 3
 
 # Exported symbols declared in include/stp.h.
 SYMBOLS = ("stp_plan", "stp_plan_free", "stp_run", "stp_reserve", "stp_submit", "stp_poll", "stp_drain",
-           "stp_class_cost", "stp_correct", "stp_plan_describe", "stp_last_error")
+           "stp_class_cost", "stp_correct", "stp_face_params", "stp_plan_describe", "stp_last_error")
 
 
 class StpError(RuntimeError):
@@ -55,7 +55,8 @@ class Batch(C.Structure):
 class Step(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("dt", C.c_double), ("h", C.c_double),
                 ("Q", C.c_void_p), ("params", C.c_void_p), ("A", C.c_void_p), ("B", C.c_void_p),
-                ("favg", C.c_void_p), ("qface", C.c_void_p), ("fface", C.c_void_p), ("Qnew", C.c_void_p)]
+                ("favg", C.c_void_p), ("qface", C.c_void_p), ("fface", C.c_void_p), ("Qnew", C.c_void_p),
+                ("fparams", C.c_void_p)]
 
 
 class TicketInfo(C.Structure):
@@ -88,6 +89,7 @@ def lib():
         L.stp_reserve.argtypes = [C.c_void_p, C.c_int64]
         L.stp_plan_describe.argtypes = [C.c_void_p, C.c_char_p, C.c_size_t]
         L.stp_correct.argtypes = [C.c_void_p, C.POINTER(Step), C.c_void_p]
+        L.stp_face_params.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
         L.stp_last_error.argtypes = []
         L.stp_last_error.restype = C.c_char_p
         for f in ("stp_plan", "stp_run", "stp_reserve", "stp_submit", "stp_poll", "stp_drain", "stp_class_cost",
@@ -113,6 +115,14 @@ def _ptr(t):
     if isinstance(t, int):
         return t
     return t.data_ptr()
+
+
+def _stream(stream):
+    """A raw HIP stream handle from a torch.cuda.Stream, a handle, or None (torch's current stream)."""
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
 
 
 class Plan:
@@ -181,27 +191,29 @@ class Plan:
 
     def run(self, batch, stream=None):
         """Queue the predictor on `stream` (a torch.cuda.Stream, a raw handle, or None = current)."""
-        if stream is None:
-            import torch
-            stream = torch.cuda.current_stream().cuda_stream
-        elif hasattr(stream, "cuda_stream"):
-            stream = stream.cuda_stream
-        return _check(lib().stp_run(self.handle, C.byref(batch), C.c_void_p(stream)))
+        return _check(lib().stp_run(self.handle, C.byref(batch), C.c_void_p(_stream(stream))))
 
     def run_status(self, batch, stream=0):
         """stp_run returning the raw status (for error-path tests)."""
         return lib().stp_run(self.handle, C.byref(batch), C.c_void_p(stream))
 
-    def correct(self, grid, dt, h, Q, favg, qface, Qnew, params=None, A=None, B=None, fface=None, stream=None):
-        """Queue the corrector step on a periodic nx x ny x nz mesh (stp_correct); tensors are device tensors."""
+    def correct(self, grid, dt, h, Q, favg, qface, Qnew, params=None, A=None, B=None, fface=None, fparams=None,
+                stream=None):
+        """Queue the corrector step on a periodic nx x ny x nz mesh (stp_correct); tensors are device tensors.
+        fparams: the face-point parameters of curved curvilinear elements from face_params, or None."""
         st = Step(int(grid[0]), int(grid[1]), int(grid[2]), float(dt), float(h), _ptr(Q), _ptr(params), _ptr(A),
-                  _ptr(B), _ptr(favg), _ptr(qface), _ptr(fface), _ptr(Qnew))
-        if stream is None:
-            import torch
-            stream = torch.cuda.current_stream().cuda_stream
-        elif hasattr(stream, "cuda_stream"):
-            stream = stream.cuda_stream
-        return _check(lib().stp_correct(self.handle, C.byref(st), C.c_void_p(stream)))
+                  _ptr(B), _ptr(favg), _ptr(qface), _ptr(fface), _ptr(Qnew), _ptr(fparams))
+        return _check(lib().stp_correct(self.handle, C.byref(st), C.c_void_p(_stream(stream))))
+
+    def face_params(self, nelem, params, fparams=None, stream=None):
+        """stp_face_params: the per-node parameters [e][n^3][12] of curved curvilinear elements at their face
+        points, [e][6][n^2][12]; allocates fparams (torch, like params) when it is None."""
+        if fparams is None:
+            n = self.classes[0][0] + 1
+            fparams = params.new_empty((int(nelem), 6, n * n, 12))
+        _check(lib().stp_face_params(self.handle, C.c_int64(int(nelem)), C.c_void_p(_ptr(params)),
+                                     C.c_void_p(_ptr(fparams)), C.c_void_p(_stream(stream))))
+        return fparams
 
     def correct_status(self, step, stream=0):
         """stp_correct returning the raw status (for error-path tests)."""

@@ -104,6 +104,7 @@ def test_null_plan_entry_points(L):
     assert L.stp_reserve(None, 10) == stp.E_INVAL
     assert L.stp_plan_describe(None, None, 0) == stp.E_INVAL
     assert L.stp_correct(None, None, None) == stp.E_INVAL
+    assert L.stp_face_params(None, 1, 16, 1 << 20, None) == stp.E_INVAL
     assert L.stp_class_cost(None, 0, None, None) == stp.E_INVAL
     L.stp_plan_free(None)  # no-op
     assert "NULL" in stp.last_error()

@@ -255,7 +255,9 @@ def curved_inputs(N, grid, seed):
 
 @pytest.mark.parametrize("N,prec", [(2, stp.FP64), (3, stp.FP64), (7, stp.FP32)])
 def test_curved_corrector_matches_oracle(N, prec, gpu):
-    """stp_correct on curved elements (12 parameters per node), fed with the oracle predictor's outputs."""
+    """stp_correct on curved elements (12 parameters per node), fed with the oracle predictor's outputs; then
+    stp_face_params against the oracle's face extrapolation of the parameters, and the corrector given those
+    face parameters reproduces its own extrapolation bit for bit."""
     torch = gpu
     grid = (3, 2, 2)
     Q, params = curved_inputs(N, grid, 40 + N)
@@ -270,12 +272,55 @@ def test_curved_corrector_matches_oracle(N, prec, gpu):
     tdt = torch.float64 if prec == stp.FP64 else torch.float32
     up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", tdt)
     Qn = torch.empty(Q.shape, device="cuda", dtype=tdt)
-    plan.correct(grid, dt, h, up(Q), up(favg), up(qface), Qn, params=up(params))
+    dQ, dfavg, dqface, dpar = up(Q), up(favg), up(qface), up(params)
+    plan.correct(grid, dt, h, dQ, dfavg, dqface, Qn, params=dpar)
     torch.cuda.synchronize()
     err = rel(Qn.double().cpu().numpy(), ref)
     say(f"[curved corrector]   max rel err {err:.2e}")
     assert err < TOL[prec], err
+    n = N + 1
+    E = Q.shape[0]
+    fp = plan.face_params(E, dpar)
+    torch.cuda.synchronize()
+    fref = OC.face_values(params, n).reshape(E, 6, n * n, 12)
+    ferr = np.abs(fp.double().cpu().numpy() - fref).max() / np.abs(fref).max()
+    say(f"[curved corrector]   face parameters max rel err {ferr:.2e}")
+    assert ferr < (1e-13 if prec == stp.FP64 else 1e-5), ferr
+    Qf = torch.empty_like(Qn)
+    plan.correct(grid, dt, h, dQ, dfavg, dqface, Qf, params=dpar, fparams=fp)
+    torch.cuda.synchronize()
+    assert torch.equal(Qf, Qn)
     plan.close()
+
+
+def test_face_params_argument_errors(gpu):
+    torch = gpu
+    N, grid = 2, (2, 2, 2)
+    E, n3, n2 = 8, 27, 9
+    z = torch.zeros(E * n3 * 12 * 8, device="cuda")
+    out = torch.zeros(E * n3 * 9, device="cuda")
+    fp = torch.zeros(E * 6 * n2 * 12, device="cuda")
+    cart = stp.Plan([(N, 9, ELASTIC, stp.PARAM_PER_ELEMENT)], prec=stp.FP32)
+    affine = stp.Plan([(N, 9, ELASTIC_CURV, stp.PARAM_PER_ELEMENT)], prec=stp.FP32)
+    curved = stp.Plan([(N, 9, ELASTIC_CURV, 0)], prec=stp.FP32)
+    for plan in (cart, affine):  # face parameters are for curved elements only
+        with pytest.raises(stp.StpError) as ei:
+            plan.face_params(E, z, fp)
+        assert ei.value.status == stp.E_UNSUPPORTED
+        with pytest.raises(stp.StpError) as ei:
+            plan.correct(grid, 0.01, 0.5, z, z, z, out, params=z, fparams=fp)
+        assert ei.value.status == stp.E_INVAL and "fparams" in stp.last_error()
+    for args in ((-1, z, fp), (E, None, fp), (E, z, z[1:])):  # nelem < 0, NULL params, fparams overlapping
+        with pytest.raises(stp.StpError) as ei:
+            curved.face_params(*args)
+        assert ei.value.status == stp.E_INVAL
+    with pytest.raises(stp.StpError) as ei:  # Qnew aliasing fparams
+        curved.correct(grid, 0.01, 0.5, z, z, z, fp, params=z, fparams=fp)
+    assert ei.value.status == stp.E_INVAL and "fparams" in stp.last_error()
+    curved.face_params(0, z, fp)  # an empty batch queues nothing
+    torch.cuda.synchronize()
+    for plan in (cart, affine, curved):
+        plan.close()
 
 
 @pytest.mark.parametrize("N", [2, 3])
@@ -310,9 +355,10 @@ def test_gpu_curved_mesh_plane_wave_converges(N, gpu):
 
 
 def test_time_loop_captured_in_a_graph(gpu):
-    """Four full ADER-DG steps (stp_run then stp_correct, Q ping-ponging between two buffers) captured in one
-    HIP graph: every replay, with other work and synchronisations in between, reproduces the eager steps bit
-    for bit (curved curvilinear elements, FP32)."""
+    """stp_face_params and four full ADER-DG steps (stp_run then stp_correct with those face parameters, Q
+    ping-ponging between two buffers) captured in one HIP graph: every replay, with other work and
+    synchronisations in between, reproduces the eager steps (which extrapolate the parameters in the
+    corrector) bit for bit (curved curvilinear elements, FP32)."""
     torch = gpu
     N, grid = 3, (4, 3, 2)
     Q0, params = curved_inputs(N, grid, 50)
@@ -329,12 +375,14 @@ def test_time_loop_captured_in_a_graph(gpu):
     ba = plan.batch(E, Qa, qavg, favg, qface, dt, h, params=par)
     bb = plan.batch(E, Qb, qavg, favg, qface, dt, h, params=par)
 
-    def four_steps(st):
+    fpar = torch.empty((E, 6, n2, 12), **f32)
+
+    def four_steps(st, fp=None):
         for _ in range(2):
             plan.run(ba, st)
-            plan.correct(grid, dt, h, Qa, favg, qface, Qb, params=par, stream=st)
+            plan.correct(grid, dt, h, Qa, favg, qface, Qb, params=par, fparams=fp, stream=st)
             plan.run(bb, st)
-            plan.correct(grid, dt, h, Qb, favg, qface, Qa, params=par, stream=st)
+            plan.correct(grid, dt, h, Qb, favg, qface, Qa, params=par, fparams=fp, stream=st)
 
     # eager reference: three times four steps from Q0
     ref = []
@@ -347,7 +395,8 @@ def test_time_loop_captured_in_a_graph(gpu):
     g = torch.cuda.CUDAGraph()
     cap = torch.cuda.Stream()
     with torch.cuda.graph(g, stream=cap):
-        four_steps(cap)
+        plan.face_params(E, par, fpar, stream=cap)
+        four_steps(cap, fpar)
     other = torch.randn(1 << 20, device="cuda")
     for k in range(3):
         g.replay()
