@@ -145,12 +145,39 @@ struct Mfma8 {
         }
     }
 
-    // r[.][t] += contribution of the derivative g (quantity dq(D, K)) at the lane's 4 nodes
-    template <int D, int K>
+    // Accumulator rows of a Taylor step on curvilinear elements: the reference derivatives of all directions are
+    // first mapped to the 9 velocity gradients h dv_i/dx_j (rows 3i + j) and the 3 stress divergences
+    // h sum_j ds_ij/dx_j (rows 9 + i), 18 FMAs per node and direction; the elastic operator is applied once to
+    // those (grad_finish) instead of 36 operations per node and direction. The time-averaged fluxes need each
+    // direction's term on its own and keep the per-direction form (rows = M).
+    static constexpr int kGradRows = 12;
+    static constexpr int TR = PHYS == kElasticCurv ? kGradRows : M;  // accumulator rows of a Taylor step
+
+    // r[.][t] += contribution of the derivative g (quantity dq(D, K)) at the lane's 4 nodes; with R ==
+    // kGradRows (curvilinear Taylor steps) to the gradient accumulators instead
+    template <int D, int K, int R>
     __device__ static inline void ncp(const Material<float, PHYS> (&mt)[4], const GRow& Gd, const float (&g)[4],
-                                      float (&r)[M][4])
+                                      float (&r)[R][4])
     {
-        if constexpr (PHYS == kElasticCurv) {
+        if constexpr (PHYS == kElasticCurv && R == kGradRows) {
+            if constexpr (K < 3) {  // v_K: h dv_K/dx_j += G[D][j] g
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) r[3 * K + j][t] = fma(Gd[t][j], g[t], r[3 * K + j][t]);
+            } else if constexpr (K < 6) {  // s_aa: row a of the divergence gets G[D][a] g
+                constexpr int a = K - 3;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) r[9 + a][t] = fma(Gd[t][a], g[t], r[9 + a][t]);
+            } else {  // s_ab: rows a and b get G[D][b] g and G[D][a] g
+                constexpr int a = K == 6 ? 0 : (K == 7 ? 1 : 0), b = K == 6 ? 1 : 2;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    r[9 + a][t] = fma(Gd[t][b], g[t], r[9 + a][t]);
+                    r[9 + b][t] = fma(Gd[t][a], g[t], r[9 + b][t]);
+                }
+            }
+        } else if constexpr (PHYS == kElasticCurv) {
             // g = d/dxi_D of quantity K contributes G[D][j] g / h to its derivative along x_j (1/h is in c);
             // the elastic operator's column K of sum_j G[D][j] M_j:
             using P = PhysTraits<kElastic>;
@@ -210,10 +237,32 @@ struct Mfma8 {
         }
     }
 
-    template <int K = 0>
+    // The elastic operator on the gradient accumulators: r = (1/rho) div s, s_ii = lambda tr(grad v) +
+    // 2 mu dv_i/dx_i, s_ab = mu (dv_a/dx_b + dv_b/dx_a), with 1/h in the material coefficients.
+    __device__ static inline void grad_finish(const Material<float, PHYS> (&mt)[4], const float (&a)[TR][4],
+                                              float (&r)[M][4])
+    {
+        if constexpr (TR == kGradRows) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const float tr = a[0][t] + a[4][t] + a[8][t];
+                const float mu2 = mt[t].c[3] - mt[t].c[1];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    r[i][t] = mt[t].c[0] * a[9 + i][t];
+                    r[3 + i][t] = fma(mt[t].c[1], tr, mu2 * a[4 * i][t]);
+                }
+                r[6][t] = mt[t].c[2] * (a[1][t] + a[3][t]);
+                r[7][t] = mt[t].c[2] * (a[5][t] + a[7][t]);
+                r[8][t] = mt[t].c[2] * (a[2][t] + a[6][t]);
+            }
+        }
+    }
+
+    template <int K = 0, int R = M>
     __device__ static inline void xpass(const AOps& A, const Material<float, PHYS> (&mt)[4], const GRow& Gd,
                                         const Split4 (&p)[M],
-                                        float (&r)[M][4])
+                                        float (&r)[R][4])
     {
         if constexpr (K < NG) {
             float g[4];
@@ -291,9 +340,9 @@ struct Mfma8 {
         }
     }
 
-    template <int D, int K0, int K1, int K = K0>
+    template <int D, int K0, int K1, int K = K0, int R = M>
     __device__ static inline void gather(const float* G0, const Offs& f, const Material<float, PHYS> (&mt)[4],
-                                         const GRow& Gd, float (&r)[M][4])
+                                         const GRow& Gd, float (&r)[R][4])
     {
         const float* G = G0 + (K == K0 ? opaque_zero() : 0);
         if constexpr (K < K1) {
@@ -308,10 +357,10 @@ struct Mfma8 {
     // r += the y- or z-contributions, once every lane has written the first chunk of direction D (transposed
     // <D, 0, C1>) and passed a barrier; the other chunk, if any, goes through the exchange buffer here. gp, gs:
     // the lane's first node's parameters and the per-node stride (0 for per-element parameters).
-    template <int D>
+    template <int D, int R>
     __device__ static inline void finish_dir(const AOps& A, const float* P, float* G, const Offs& f,
                                              const Material<float, PHYS> (&mt)[4], const float* gp, int gs,
-                                             float (&r)[M][4])
+                                             float (&r)[R][4])
     {
         GRow Gd;
         load_grow<D>(gp, gs, Gd);
@@ -461,9 +510,9 @@ struct Mfma8 {
                 split_all(p, sp);
                 write_tile(P, off, sp);
                 __syncthreads();
-                float r[M][4];
+                float r[TR][4];
 #pragma unroll
-                for (int q = 0; q < M; ++q)
+                for (int q = 0; q < TR; ++q)
 #pragma unroll
                     for (int t = 0; t < 4; ++t) r[q][t] = 0.f;
                 transposed<1, 0, C1>(A, P, G, off);
@@ -479,13 +528,18 @@ struct Mfma8 {
                 __syncthreads();
                 finish_dir<2>(A, P, G, off, mt, gp, gs, r);
                 w = w * dt * __builtin_amdgcn_rcpf((float)(o + 1));
+                if constexpr (TR == kGradRows) {
+                    grad_finish(mt, r, p);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < M; ++q)
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) p[q][t] = r[q][t];
+                }
 #pragma unroll
                 for (int q = 0; q < M; ++q)
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        p[q][t] = r[q][t];
-                        qb[q][t] = fma(w, r[q][t], qb[q][t]);
-                    }
+                    for (int t = 0; t < 4; ++t) qb[q][t] = fma(w, p[q][t], qb[q][t]);
                 __syncthreads();
             }
 
