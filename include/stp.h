@@ -198,8 +198,8 @@ stp_status stp_run(stp_plan_t plan, const stp_batch* batch, void* hip_stream);
  * elastic sqrt((lambda + 2 mu)/rho), generic max_d ||A_d + B_d||_inf; curvilinear elements with affine
  * geometry, STP_ELASTIC_CURV with STP_PARAM_PER_ELEMENT: B_d = sum_j G[d][j] M_j, the mean taken of the two
  * elements' products, and sqrt((lambda + 2 mu)/rho) max_d |G[d][:]|_2; curved elements, parameters per node:
- * the same with each side's parameters extrapolated to the face point by the face vectors, so the material
- * must be smooth inside an element). Node k receives
+ * the same with each side's parameters extrapolated to the face point by the face vectors, or read from
+ * stp_step.fparams (stp_face_params), so the material must be smooth inside an element). Node k receives
  * dt l_{k_d}(face) / (h w_{k_d}) C at its face node (collocation on the plan's nodes, diagonal mass matrix).
  * Elements e = (iz * ny + iy) * nx + ix, uniform size h, periodic in x, y and z; layouts as in stp_batch,
  * contiguous (element e at e * size). Stability of the full step needs dt <= about 0.2 h / ((2N+1) c_max). */

@@ -253,8 +253,10 @@ def curved_inputs(N, grid, seed):
     return rng.standard_normal((E, n3, 9)), params
 
 
-@pytest.mark.parametrize("N,prec", [(2, stp.FP64), (3, stp.FP64), (7, stp.FP32)])
-def test_curved_corrector_matches_oracle(N, prec, gpu):
+@pytest.mark.parametrize("N,prec,nodes", [(2, stp.FP64, stp.GAUSS_LEGENDRE), (3, stp.FP64, stp.GAUSS_LEGENDRE),
+                                           (7, stp.FP32, stp.GAUSS_LEGENDRE), (3, stp.FP64, stp.GAUSS_LOBATTO),
+                                           (5, stp.FP32, stp.GAUSS_LOBATTO)])
+def test_curved_corrector_matches_oracle(N, prec, nodes, gpu):
     """stp_correct on curved elements (12 parameters per node), fed with the oracle predictor's outputs; then
     stp_face_params against the oracle's face extrapolation of the parameters, and the corrector given those
     face parameters reproduces its own extrapolation bit for bit."""
@@ -264,11 +266,11 @@ def test_curved_corrector_matches_oracle(N, prec, gpu):
     h, dt = 0.5, 0.005
     rnd = (lambda a: a) if prec == stp.FP64 else (lambda a: None if a is None else a.astype(np.float32).astype(np.float64))
     Q, params = rnd(Q), rnd(params)
-    pred = oracle.stp(N, ELASTIC_CURV, Q, dt, h, params=params)
+    pred = oracle.stp(N, ELASTIC_CURV, Q, dt, h, params=params, nodes=nodes)
     favg, qface = rnd(pred["favg"]), rnd(pred["qface"])
-    ref = OC.correct(N, ELASTIC_CURV, grid, Q, favg, qface, dt, h, params=params)
-    say(f"[curved corrector] N={N} prec={prec} mesh={grid}")
-    plan = stp.Plan([(N, 9, ELASTIC_CURV, 0)], prec=prec)
+    ref = OC.correct(N, ELASTIC_CURV, grid, Q, favg, qface, dt, h, params=params, nodes=nodes)
+    say(f"[curved corrector] N={N} prec={prec} nodes={nodes} mesh={grid}")
+    plan = stp.Plan([(N, 9, ELASTIC_CURV, 0)], prec=prec, nodes=nodes)
     tdt = torch.float64 if prec == stp.FP64 else torch.float32
     up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda", tdt)
     Qn = torch.empty(Q.shape, device="cuda", dtype=tdt)
@@ -282,7 +284,7 @@ def test_curved_corrector_matches_oracle(N, prec, gpu):
     E = Q.shape[0]
     fp = plan.face_params(E, dpar)
     torch.cuda.synchronize()
-    fref = OC.face_values(params, n).reshape(E, 6, n * n, 12)
+    fref = OC.face_values(params, n, nodes).reshape(E, 6, n * n, 12)
     ferr = np.abs(fp.double().cpu().numpy() - fref).max() / np.abs(fref).max()
     say(f"[curved corrector]   face parameters max rel err {ferr:.2e}")
     assert ferr < (1e-13 if prec == stp.FP64 else 1e-5), ferr
