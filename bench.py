@@ -354,7 +354,7 @@ def bench_hetero(args, torch, stp, W):
     bytes_tot = sum(plan.cost(c)[0] * int(k) for c, k in enumerate(d["counts"]))
     flops_tot = sum(plan.cost(c)[1] * int(k) for c, k in enumerate(d["counts"]))
     # the same elements, one uniform plan and launch per class over its contiguous storage
-    per_class = []
+    per_class, per_class_ms = [], {}
     for c, (first, k) in enumerate(d["class_ranges"]):
         if k == 0:
             continue
@@ -367,6 +367,7 @@ def bench_hetero(args, torch, stp, W):
                       qface[of:of + k * sf], dts, hs, B=d["B"][oc:oc + k * sc])
         t = time_launches(lambda st: up.run(ub, st), max(3, args.steps // 2), 2, stream, torch)
         per_class.append(float(np.median(t)))
+        per_class_ms[f"N{d['classes'][c][0]}m{d['classes'][c][1]}"] = per_class[-1]
         up.close()
     del g
     plan.close()
@@ -377,7 +378,7 @@ def bench_hetero(args, torch, stp, W):
            "algorithmic_bytes": bytes_tot, "hbm_gbs_algorithmic": bytes_tot / (ms * 1e-3) / 1e9,
            "hbm_frac": bytes_tot / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
            "gflops": flops_tot / (ms * 1e-3) / 1e9,
-           "ms_one_launch_per_class_sum": float(sum(per_class)),
+           "ms_one_launch_per_class_sum": float(sum(per_class)), "ms_one_launch_per_class": per_class_ms,
            "tuned": {"grid_per_cu": tuned["hetero_grid_per_cu"], "tile_lds_budget": tuned["hetero_lds_budget"],
                      "elements_per_tile": {f"N{c['order']}m{c['nquant']}": c["elements_per_tile"]
                                            for c in tuned["classes"] if c["tiled"]}}}

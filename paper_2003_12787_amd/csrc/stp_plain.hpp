@@ -28,11 +28,16 @@ struct Plain {
     static constexpr int nn = n * n * n;
     static constexpr int NT = ((nn + 63) / 64) * 64;
     static constexpr bool kPreset = PHYS != kGeneric;
-    // Rows of a per-node B_d product issued between scheduling barriers (FP32): three rows (27 loads in
-    // flight at m = 9) for the wider buckets; no barrier for m <= 4 up to N = 7 (the 1024-thread N = 8, 9
-    // blocks run at 128 registers and want one row at a time). Chosen by timing each class of the mixed
-    // 16384-element workload.
-    static constexpr int kNcpGroup = MB >= 9 ? 3 : (N <= 7 ? 0 : 1);
+    // Rows of a per-node B_d product issued between scheduling barriers (FP32, generic orders up to 7): three
+    // rows (27 loads in flight at m = 9) for the wider buckets, no barrier for m <= 4. Chosen by timing each
+    // class of the mixed 16384-element workload.
+    static constexpr int kNcpGroup = MB >= 9 ? 3 : 0;
+    // Orders 8 and 9 of the generic physics form B_d g one column at a time: the loads of column q are in
+    // flight while the derivative of quantity q is formed from LDS, and only one derivative is live. In the
+    // row form (all m derivatives, then the rows of B_d) the waves of those large blocks sit idle on the
+    // B_d loads after each direction's LDS work; the column form runs their classes about twice as fast. At
+    // orders 7 and below the row form is as fast or faster.
+    static constexpr bool kColumnNcp = !kPreset && N >= 8;
 
     // Byte offsets of the LDS regions, each 16-byte aligned; `total` is the dynamic LDS size.
     struct Layout {
@@ -110,6 +115,28 @@ struct Plain {
             }
         }
         if (!own) return;
+        if constexpr (kColumnNcp) {
+            // r += -(1/h) sum_q B_d[:, q] (D x_d u)_q
+            auto ncp_cols = [&](const T* Bd, int cs) {
+#pragma unroll
+                for (int q = 0; q < MB; ++q) {
+                    if (q >= m) break;
+                    T b[MB];
+#pragma unroll
+                    for (int s = 0; s < MB; ++s) b[s] = s < m ? Bd[(s * m + q) * cs] : T(0);
+                    const T gq = -inv_h * dline<D>(Ds, u, m, tid, z, y, x, q);
+#pragma unroll
+                    for (int s = 0; s < MB; ++s)
+                        if (s < m) r[s] = fma(b[s], gq, r[s]);
+                    if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
+                }
+            };
+            if (per_elem)
+                ncp_cols(coefs + D * m * m, 1);
+            else  // re-read every Taylor step: the laundered offset keeps the loads inside the loop
+                ncp_cols(static_cast<const T*>(a.B) + er.coef + (int64_t)D * m * m * nn + tid + opaque_zero(), nn);
+            return;
+        }
         T g[MB];
 #pragma unroll
         for (int s = 0; s < MB; ++s) {

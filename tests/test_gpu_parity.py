@@ -196,10 +196,20 @@ def test_unsupported_variant_is_reported():
 
 
 # ------------------------------------------------------------------------------------------------ generic
-@pytest.mark.parametrize("N,m", [(1, 1), (2, 5), (3, 9), (4, 16)])
+@pytest.mark.parametrize("N,m", [(1, 1), (2, 5), (3, 9), (4, 16), (8, 9), (9, 4), (9, 16)])
 @pytest.mark.parametrize("prec", [stp.FP64, stp.FP32])
 def test_generic_dense_B_per_node(N, m, prec):
     check(W.generic_batch(N, m, 67, 700 + N * 20 + m), prec, label="generic")
+
+
+@pytest.mark.parametrize("prec", [stp.FP64, stp.FP32])
+def test_generic_high_orders_with_A_source_and_per_element(prec):
+    """Orders 8 and 9 form B_d (D x_d u) column by column: with A_d and a point source (per node), and with
+    per-element coefficients (B_d from LDS)."""
+    b = W.generic_batch(9, 7, 40, 805, with_A=True)
+    b.src = W.point_source(b, 806)
+    check(b, prec, label="generic-N9-A-src")
+    check(W.generic_batch(8, 9, 40, 807, with_A=True, per_node=False), prec, label="generic-N8-per-element")
 
 
 @pytest.mark.parametrize("prec", [stp.FP64, stp.FP32])
