@@ -212,6 +212,12 @@ def test_generic_high_orders_with_A_source_and_per_element(prec):
     check(W.generic_batch(8, 9, 40, 807, with_A=True, per_node=False), prec, label="generic-N8-per-element")
 
 
+def test_generic_high_orders_fp64_accumulation():
+    """FP32 I/O with FP64 accumulation (the serving configuration at N >= 8) through the column form."""
+    check(W.generic_batch(9, 9, 40, 808), stp.FP32, acc64=8, label="generic-N9-acc64")
+    check(W.generic_batch(8, 12, 30, 809, with_A=True), stp.FP32, acc64=8, label="generic-N8-m12-A-acc64")
+
+
 @pytest.mark.parametrize("prec", [stp.FP64, stp.FP32])
 def test_generic_with_A_and_point_source(prec):
     b = W.generic_batch(3, 6, 66, 801, with_A=True)
