@@ -408,3 +408,57 @@ def test_time_loop_captured_in_a_graph(gpu):
         other.mul_(1.0001)  # unrelated work between replays
         torch.cuda.synchronize()
     plan.close()
+
+
+def test_curved_full_step_full_size(gpu):
+    """The bench's curved full step at full size (65536 elements of the deformed 64 x 32 x 32 box, N = 7, MFMA
+    predictor, FP32; material constant in each element): stp_face_params against the oracle's face
+    extrapolation on 24 sampled elements, and the corrector with those face parameters equal, bit for bit, to
+    the corrector that extrapolates them, with finite results."""
+    torch = gpu
+    N, E, n3, n2 = 7, 65536, 512, 64
+    Q, par, dt = W.curvilinear_device(N, E, W.SEED0 + 7)
+    par[..., 0:3] = par[:, :1, 0:3].clone()  # smooth inside an element (R25 reading of curved elements)
+    grid = W.grid_of(E)
+    assert grid[0] * grid[1] * grid[2] == E
+    plan = stp.Plan([(N, 9, ELASTIC_CURV, 0)], prec=stp.BF16X3, variant=stp.VARIANT_MFMA)
+    f32 = dict(device="cuda", dtype=torch.float32)
+    qavg, favg, qface = torch.empty((E, n3, 9), **f32), torch.empty((E, 3, n3, 9), **f32), torch.empty((E, 6, n2, 9), **f32)
+    say(f"[curved full size] E={E} grid={grid}")
+    plan.run(plan.batch(E, Q, qavg, favg, qface, dt / 2, 1.0, params=par))
+    fp = plan.face_params(E, par)
+    Qa, Qb = torch.empty_like(Q), torch.empty_like(Q)
+    plan.correct(grid, dt / 2, 1.0, Q, favg, qface, Qa, params=par, fparams=fp)
+    plan.correct(grid, dt / 2, 1.0, Q, favg, qface, Qb, params=par)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(Qa).all())
+    assert torch.equal(Qa, Qb)
+    ids = torch.from_numpy(np.linspace(0, E - 1, 24).astype(np.int64)).cuda()
+    p = par.index_select(0, ids).double().cpu().numpy()
+    fref = OC.face_values(p, N + 1).reshape(24, 6, n2, 12)
+    ferr = np.abs(fp.index_select(0, ids).double().cpu().numpy() - fref).max() / np.abs(fref).max()
+    say(f"[curved full size]   face parameters max rel err {ferr:.2e}; corrector paths equal")
+    assert ferr < 1e-5, ferr
+    plan.close()
+    del Q, par, qavg, favg, qface, fp, Qa, Qb
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("N", [1, 4, 9])
+@pytest.mark.parametrize("prec", [stp.FP64, stp.FP32])
+def test_face_params_orders(N, prec, gpu):
+    """stp_face_params against the oracle's face extrapolation at the lowest and highest orders."""
+    torch = gpu
+    _, params = curved_inputs(N, (3, 2, 2), 60 + N)
+    if prec != stp.FP64:
+        params = params.astype(np.float32).astype(np.float64)
+    tdt = torch.float64 if prec == stp.FP64 else torch.float32
+    plan = stp.Plan([(N, 9, ELASTIC_CURV, 0)], prec=prec)
+    E, n = params.shape[0], N + 1
+    fp = plan.face_params(E, torch.from_numpy(np.ascontiguousarray(params)).to("cuda", tdt))
+    torch.cuda.synchronize()
+    fref = OC.face_values(params, n).reshape(E, 6, n * n, 12)
+    err = np.abs(fp.double().cpu().numpy() - fref).max() / np.abs(fref).max()
+    say(f"[face params] N={N} prec={prec}: max rel err {err:.2e}")
+    assert err < (1e-13 if prec == stp.FP64 else 1e-5), err
+    plan.close()
