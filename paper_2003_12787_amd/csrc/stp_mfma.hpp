@@ -336,7 +336,11 @@ struct Mfma8 {
             deriv_mfma(A, from_words(Ps[off[0]], Ps[off[1]], Ps[off[2]], Ps[off[3]]), g);
 #pragma unroll
             for (int t = 0; t < 4; ++t) G[(k - K0) * SLOT + off[t]] = g[t];
-            __builtin_amdgcn_sched_barrier(0);
+            // The Cartesian presets leave the scheduler free to overlap the quantities' chains (LDS read,
+            // MFMA pair, LDS write): 231 registers, still two waves per SIMD. Curvilinear elements (244
+            // registers) overlap them in pairs.
+            if constexpr (PHYS == kElasticCurv)
+                if (((k - K0) & 1) == 1) __builtin_amdgcn_sched_barrier(0);
         }
     }
 
