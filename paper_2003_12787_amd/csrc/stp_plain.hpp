@@ -146,8 +146,12 @@ struct Plain {
                 g[s] = s < m ? dline<D>(Ds, u, m, tid, z, y, x, s) : T(0);
             }
             // one quantity's line at a time: bounds the LDS reads in flight (and the registers they hold).
-            // FP32 only: with FP64 data this barrier makes the gfx950 back end emit an illegal instruction.
-            if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
+            // Curvilinear elements up to order 7 take two at a time (5.71 -> 5.04 ms at N = 7); for the
+            // other classes two cost the persistent elastic bucket a wave per SIMD. FP32 only: with FP64
+            // data this barrier makes the gfx950 back end emit an illegal instruction.
+            if constexpr (sizeof(T) == 4) {
+                if (N > 7 || PHYS != kElasticCurv || (s & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+            }
         }
         if constexpr (kPreset) {
             apply_ncp<T, PHYS, D>(mt, g, r);
