@@ -189,6 +189,17 @@ void stp_plan_free(stp_plan_t plan);
  * one stream, or use one plan per stream. */
 stp_status stp_run(stp_plan_t plan, const stp_batch* batch, void* hip_stream);
 
+/* stp_run for callers that cannot allocate device memory (code under HIP graph capture, serving loops and
+ * harnesses that forbid hipMalloc). Same arguments, outputs and kernels as stp_run. A heterogeneous plan's
+ * bucketing scratch (per-class element lists, counts, tile queues) comes from a static array of the library
+ * (16 MiB of element lists plus a 4 KiB header per device, held until the process ends) instead of the
+ * plan's allocated scratch; the call allocates nothing and calls no allocating routine, and the kernels clear
+ * what must start at zero. Limit: nclass * nelem <= 4194304 (STP_E_INVAL beyond, before any launch).
+ * Classes with their own launch run on hip_stream (no side streams). Every call on one device shares that
+ * device's array, which keeps the last call's contents: calls that overlap on one device race, whatever
+ * their plan; queue them on one stream. Single-class plans use no scratch and behave exactly as stp_run. */
+stp_status stp_run_noalloc(stp_plan_t plan, const stp_batch* batch, void* hip_stream);
+
 /* One corrector step on a periodic Cartesian mesh (the update of Sec. II-A, Eq. (5)): from q(t_n) and the
  * predictor's outputs of every element, q(t_{n+1}) = q(t_n) + dt sum_d favg[d] + dt (face terms). The
  * numerical flux is linear (a Rusanov flux in fluctuation form, upwind for a single wave): at the face of an

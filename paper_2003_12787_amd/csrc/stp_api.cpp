@@ -31,6 +31,8 @@ stp_status fail(stp_status st, const char* fmt, ...)
     return st;
 }
 
+void clear_last_error() { g_last_error.clear(); }
+
 stp_status hip_fail(hipError_t e, const char* what)
 {
     return fail(STP_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
@@ -270,11 +272,13 @@ stp_status stp_plan(const stp_plan_desc* desc, stp_plan_t* out)
         if (st != STP_OK) return st;
     }
     if (desc->device < 0) return fail(STP_E_INVAL, "device %d < 0", desc->device);
+    stp_status st0;
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
     if (desc->device >= ndev) return fail(STP_E_INVAL, "device %d of %d", desc->device, ndev);
     DeviceGuard g(desc->device);
+    if ((st0 = static_scratch_init(desc->device)) != STP_OK) return st0;
     stp_plan_s* p = new (std::nothrow) stp_plan_s();
     if (!p) return fail(STP_E_NOMEM, "out of host memory");
     p->device = desc->device;

@@ -3,6 +3,7 @@
 // synchronisation) followed by one persistent launch per physics bucket on the caller's stream, with the
 // classes that have their own launch forked onto side streams and joined back with events.
 #include <algorithm>
+#include <mutex>
 
 #include "stp_hetero.hpp"
 #include "stp_plan.hpp"
@@ -257,7 +258,7 @@ stp_status launch_batch(stp_plan_s* p, const stp_batch* b, hipStream_t stream, H
     // With tiled classes present, the own-launch classes go to the side streams (fork after the setup pass).
     // Small batches stay on one stream: there the fork and join cost more than the overlap gains (serving
     // batches of a few hundred elements lost half their throughput).
-    const bool fork = anyTiled && !order.empty() && b->nelem >= kForkMinElements;
+    const bool fork = s->fork && anyTiled && !order.empty() && b->nelem >= kForkMinElements;
     const int nside = fork ? std::min<int>(kSideStreams, (int)order.size()) : 0;
     if (fork) {
         if ((e = hipEventRecord(s->fork, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord(fork)");
@@ -380,3 +381,72 @@ stp_status hetero_prepare(stp_plan_s* p)
 }
 
 }  // namespace stp
+
+// ------------------------------------------------------------------------------------------------------------
+// Static scratch of the no-allocation entry point. Callers that cannot allocate device memory (code under HIP
+// graph capture, serving loops that forbid allocation) get the heterogeneous bucketing scratch from this
+// file-scope device array instead of the plan's allocated scratch. Every device the library runs on holds its
+// own copy until the process ends. Layout (int32 words): counts [kMaxClasses], tile_start
+// [kHeteroBuckets][kMaxClasses + 1], heads [kHeteroBuckets], then the per-class element lists
+// [nclass][nelem]. In host code `scratch` only names the symbol; its device address comes from
+// hipGetSymbolAddress, once per device.
+namespace stp {
+namespace {
+
+constexpr int64_t kStaticHeaderWords = 1024;                 // counts, tile queues, heads (4 KiB)
+constexpr int64_t kStaticListWords = int64_t(4) << 20;       // per-class element lists (16 MiB)
+static_assert(kMaxClasses + kHeteroBuckets * (kMaxClasses + 1) + kHeteroBuckets <= kStaticHeaderWords,
+              "the bucketing header fits its region");
+
+static __device__ __align__(256) int32_t scratch[kStaticHeaderWords + kStaticListWords];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+int32_t* g_static_ptr[kMaxDevices] = {};  // device address of `scratch` on each device
+
+}  // namespace
+
+stp_status static_scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(STP_E_UNSUPPORTED, "device %d >= %d", device, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static_ptr[device]) return STP_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(static scratch)");
+    g_static_ptr[device] = static_cast<int32_t*>(ptr);
+    return STP_OK;
+}
+
+}  // namespace stp
+
+extern "C" stp_status stp_run_noalloc(stp_plan_t p, const stp_batch* b, void* stream)
+{
+    using namespace stp;
+    clear_last_error();
+    if (!p) return fail(STP_E_INVAL, "plan is NULL");
+    stp_status st = validate_batch(p, b);
+    if (st != STP_OK) return st;
+    if (b->nelem == 0) return STP_OK;
+    const int64_t nclass = (int64_t)p->classes.size();
+    if (nclass > 1 && nclass * b->nelem > kStaticListWords)
+        return fail(STP_E_INVAL, "nclass * nelem = %lld exceeds the static scratch (%lld entries)",
+                    (long long)(nclass * b->nelem), (long long)kStaticListWords);
+    DeviceGuard g(p->device);
+    if (nclass == 1) return launch_batch(p, b, static_cast<hipStream_t>(stream));  // no scratch in use
+    int32_t* base;
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        base = g_static_ptr[p->device];
+    }
+    if (!base) return fail(STP_E_DEVICE, "static scratch of device %d not resolved", p->device);
+    // The bucketing kernels clear the counts and tile heads themselves (no memset); no side streams, so the
+    // own-launch classes run on the caller's stream.
+    HeteroScratch s{};
+    s.counts = base;
+    s.tile_start = base + kMaxClasses;
+    s.heads = s.tile_start + kHeteroBuckets * (kMaxClasses + 1);
+    s.lists = base + kStaticHeaderWords;
+    s.cap = b->nelem;
+    return launch_batch(p, b, static_cast<hipStream_t>(stream), &s);
+}

@@ -115,6 +115,7 @@ struct DeviceGuard {
 };
 
 stp_status fail(stp_status st, const char* fmt, ...);
+void clear_last_error();
 stp_status hip_fail(hipError_t e, const char* what);
 void class_cost(const stp_class& c, int io_bytes, double* bytes, double* flops);
 stp_status validate_batch(stp_plan_s* p, const stp_batch* b);
@@ -132,6 +133,9 @@ stp_status hetero_prepare(stp_plan_s* p);
 // Make `s` hold batches of up to nelem elements (synchronous allocation).
 stp_status reserve_scratch(stp_plan_s* p, HeteroScratch& s, int64_t nelem);
 void free_scratch(HeteroScratch& s);
+// Resolve, once per device and with that device current, the device address of the library's static scratch
+// (the no-allocation entry point stp_run_noalloc); called at plan creation.
+stp_status static_scratch_init(int device);
 stp_status serve_start(stp_plan_s* p);
 void serve_stop(stp_plan_s* p);
 double now_seconds();
