@@ -48,7 +48,9 @@
  *                 scaled by the element size h; an undeformed cube of side h has G = I).
  *
  * Precision: STP_FP64 computes and stores in double. STP_FP32 and STP_BF16X3 read and write float; their
- * derivative contractions run in FP32 (VALU) or as three BF16 products with FP32 accumulation (MFMA).
+ * derivative contractions run in FP32 (VALU) or on the matrix cores with the operands split into three BF16
+ * pieces each (D = D0 + D1 + D2 and u = hi + mid + lo, the six products of order up to 2^-16 formed) and FP32
+ * accumulation (MFMA; about FP32 accuracy).
  * Classes whose order is >= acc64_min_order (when > 0) accumulate qavg and the face extrapolation in FP64.
  *
  * Ownership: the caller owns every buffer and passes raw pointers; device pointers must be device memory
@@ -168,7 +170,7 @@ typedef struct {
     int status;       /* STP_OK, STP_PENDING or an error                              */
 } stp_ticket_info;
 
-/* Build a plan: host tables (Gauss-Legendre or Gauss-Lobatto nodes, D, face vectors, BF16 hi/lo split of D)
+/* Build a plan: host tables (Gauss-Legendre or Gauss-Lobatto nodes, D, face vectors, three-piece BF16 split of D)
  * in FP64, uploaded once to the device; kernel choice per class. Returns STP_E_UNSUPPORTED for an order
  * outside 1..9, a preset with the wrong m, a generic m outside 1..16, or a requested variant that has no
  * kernel for a class. *out is NULL on failure. */

@@ -27,9 +27,17 @@ CFLAGS = [
 ]
 
 
+# Per-source additions. The matrix-core kernel keeps its MFMA accumulators in ordinary VGPRs: with the
+# compiler's default (AGPR results) every derivative pays four accumulator-to-VGPR moves and the kernel needs
+# more than the 128 registers that allow four waves per SIMD.
+EXTRA = {
+    "stp_mfma_n7.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *CFLAGS, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     noise = ("packed-fp32-ops", "warning: unknown target feature", "1 warning generated", "warnings generated")
     msgs = [l for l in r.stdout.splitlines() if l.strip() and not any(k in l for k in noise)]

@@ -1,7 +1,7 @@
 // basis.cpp -- host-side constant tables of the predictor, built once per plan in FP64/long double:
 // Gauss-Legendre nodes on [0,1] (Sec. II-A nodal Lagrange basis), the derivative matrix D[i][j] = l_j'(xi_i)
 // (Sec. II-A "discrete derivative operator"), the face vectors l_j(0), l_j(1) (Sec. II-B face projection)
-// and the BF16 hi/lo split of D used by the split-BF16x3 contraction.
+// and the three-piece BF16 split of D used by the split-BF16x3 contraction.
 //
 // The nodes are the eigenvalues of the symmetric Jacobi matrix of the Legendre recurrence, isolated by
 // Sturm-sequence bisection and polished by Newton steps on the recurrence.
@@ -143,28 +143,28 @@ void derivative_matrix_f32(int n, const double* D, float* Df)
     }
 }
 
-uint16_t bf16_round(float x)
+void split3_bf16(int count, const float* x, uint16_t* p0, uint16_t* p1, uint16_t* p2)
 {
-    uint32_t u;
-    std::memcpy(&u, &x, 4);
-    uint32_t lsb = (u >> 16) & 1u;
-    u += 0x7fffu + lsb;  // round to nearest even (inputs are finite)
-    return (uint16_t)(u >> 16);
-}
-
-float bf16_to_float(uint16_t b)
-{
-    uint32_t u = (uint32_t)b << 16;
-    float f;
-    std::memcpy(&f, &u, 4);
-    return f;
-}
-
-void split_bf16(int count, const float* x, uint16_t* hi, uint16_t* lo)
-{
+    // Truncation split: p0 keeps the sign, the exponent and the 7 leading fraction bits of x; the remainder
+    // x - p0 is exact in FP32 and has at most 16 significant bits, of which p1 keeps the leading 8; the rest
+    // (at most 8 bits) is p2 exactly. So x = p0 + p1 + p2 with no rounding (for finite x of normal range).
     for (int i = 0; i < count; ++i) {
-        hi[i] = bf16_round(x[i]);
-        lo[i] = bf16_round(x[i] - bf16_to_float(hi[i]));
+        uint32_t u;
+        std::memcpy(&u, &x[i], 4);
+        float h, r, m, l;
+        const uint32_t hu = u & 0xffff0000u;
+        std::memcpy(&h, &hu, 4);
+        r = x[i] - h;
+        uint32_t ru;
+        std::memcpy(&ru, &r, 4);
+        const uint32_t mu = ru & 0xffff0000u;
+        std::memcpy(&m, &mu, 4);
+        l = r - m;
+        uint32_t lu;
+        std::memcpy(&lu, &l, 4);
+        p0[i] = (uint16_t)(hu >> 16);
+        p1[i] = (uint16_t)(mu >> 16);
+        p2[i] = (uint16_t)(lu >> 16);
     }
 }
 

@@ -18,8 +18,7 @@ void derivative_matrix(int n, const double* xi, double* D);
 // FP32 copy of D with zero row sums in FP32.
 void derivative_matrix_f32(int n, const double* D, float* Df);
 // Round-to-nearest-even BF16 and the hi/lo split x ~ hi + lo.
-uint16_t bf16_round(float x);
-float bf16_to_float(uint16_t b);
-void split_bf16(int count, const float* x, uint16_t* hi, uint16_t* lo);
+// x = p0 + p1 + p2 exactly, each a BF16 bit pattern (truncation split; finite x of normal range).
+void split3_bf16(int count, const float* x, uint16_t* p0, uint16_t* p1, uint16_t* p2);
 
 }  // namespace stp

@@ -29,7 +29,7 @@ struct ClassState {
     void* de1 = nullptr;
     void* de0_64 = nullptr;  // FP64 face vectors (FP32 plans)
     void* de1_64 = nullptr;
-    void* dDsplit = nullptr; // BF16 hi/lo tables (split-BF16x3 variant)
+    void* dDsplit = nullptr; // BF16 three-piece split tables of D (split-BF16x3 variant)
     void* daux = nullptr;    // even/odd derivative tables in the compute precision (fused variant)
     void* dw = nullptr;      // Gauss-Legendre weights on [0, 1] in the compute precision (corrector)
     bool acc64 = false;      // FP64 accumulation of q-bar and faces

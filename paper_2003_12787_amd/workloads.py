@@ -264,6 +264,42 @@ def acoustic_plane_wave_batch(N: int, nelem: int, seed: int, h: float = 1.0, noi
     return Batch(N, 4, ACOUSTIC, Q, dt, np.full(nelem, h), params=par, coef_per_element=True)
 
 
+def elastic_plane_wave_batch(N: int, nelem: int, seed: int, h: float = 1.0, noise: float = 1e-2,
+                             per_node: bool = True) -> Batch:
+    """Elastic waves, m = 9, smooth fields: the per-node material of the elastic workloads, and Q a P-wave plus
+    an S-wave of the reference material (rho, lambda, mu) = (2.5, 2.5, 2), both sin(k.x) with
+    k = (2 pi / 8h) (1,2,2)/3, plus N(0, noise^2) per DOF. Elements sit on a cubic grid (x fastest). Q is
+    smooth but not a solution for the sampled material; it is an input recipe for accuracy tests on smooth
+    data."""
+    rng = np.random.default_rng(seed)
+    n = N + 1
+    grid = max(1, int(round(nelem ** (1.0 / 3.0))))
+    while grid ** 3 < nelem:
+        grid += 1
+    par = elastic_material(rng, (nelem, n ** 3) if per_node else (nelem,))
+    rho0, lam0, mu0 = 2.5, 2.5, 2.0
+    cp0, cs0 = math.sqrt((lam0 + 2 * mu0) / rho0), math.sqrt(mu0 / rho0)
+    kvec = (2 * math.pi / (8 * h)) * np.array([1.0, 2.0, 2.0]) / 3.0
+    khat = kvec / np.linalg.norm(kvec)
+    a = np.cross(khat, [1.0, 0.0, 0.0])
+    a /= np.linalg.norm(a)
+    def voigt(S):  # (xx, yy, zz, xy, yz, xz)
+        return np.array([S[0, 0], S[1, 1], S[2, 2], S[0, 1], S[1, 2], S[0, 2]])
+    rP = np.concatenate([khat, -voigt(lam0 * np.eye(3) + 2 * mu0 * np.outer(khat, khat)) / cp0])
+    rS = np.concatenate([a, -voigt(mu0 * (np.outer(a, khat) + np.outer(khat, a))) / cs0])
+    xi = _node_positions(n)
+    e = np.arange(nelem)
+    ex, ey, ez = e % grid, (e // grid) % grid, e // (grid * grid)
+    Z, Y, X = np.meshgrid(xi, xi, xi, indexing="ij")
+    phase = (kvec[0] * (ex[:, None] + X.reshape(1, -1)) + kvec[1] * (ey[:, None] + Y.reshape(1, -1))
+             + kvec[2] * (ez[:, None] + Z.reshape(1, -1))) * h
+    Q = np.sin(phase)[..., None] * rP + 0.5 * np.sin(phase + 1.0)[..., None] * rS
+    Q = Q + noise * rng.standard_normal(Q.shape)
+    cp = np.sqrt((par[..., 1] + 2 * par[..., 2]) / par[..., 0]).max() if nelem else 1.0
+    dt = np.full(nelem, cfl_dt(N, h, cp))
+    return Batch(N, 9, ELASTIC, Q, dt, np.full(nelem, h), params=par, coef_per_element=not per_node)
+
+
 def acoustic_batch(N: int, nelem: int, seed: int, h: float = 1.0, per_node: bool = True) -> Batch:
     """Acoustic waves with random per-node material rho ~ U[2,3], K ~ U[1,2] and Q ~ N(0, 1)."""
     rng = np.random.default_rng(seed)
