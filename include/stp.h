@@ -61,8 +61,9 @@
  *
  * Errors: every entry point returns a stp_status and never throws or aborts. Problems detectable on the
  * host (bad sizes, NULL required pointers, unsupported order/quantity count, h <= 0 or dt < 0 given as host
- * scalars, outputs aliasing inputs, class ids out of range when checked on the host) return STP_E_INVAL or
- * STP_E_UNSUPPORTED before any device work is queued. HIP failures return STP_E_DEVICE. A human-readable
+ * scalars, outputs aliasing inputs) return STP_E_INVAL or STP_E_UNSUPPORTED before any device work is
+ * queued. Class ids are device data: out-of-range ids are reported by stp_sync and stp_poll (see stp_run).
+ * HIP failures return STP_E_DEVICE. A human-readable
  * message for the last failure on the calling thread is available from stp_last_error().
  */
 #ifndef STP_H
@@ -188,8 +189,16 @@ void stp_plan_free(stp_plan_t plan);
  * The element lists and tile queues live in the plan's scratch, which the first call that needs more of it
  * allocates synchronously (stp_reserve avoids that, after which the call is stream-capturable). Because the
  * scratch is shared, stp_run calls of one heterogeneous plan must not overlap on the device: queue them on
- * one stream, or use one plan per stream. */
+ * one stream, or use one plan per stream. The class ids live in device memory and are checked there:
+ * elements whose id is outside 0..nclass-1 are skipped (their outputs are not written) and flagged, and the
+ * next stp_sync of the plan returns STP_E_INVAL. */
 stp_status stp_run(stp_plan_t plan, const stp_batch* batch, void* hip_stream);
+
+/* Wait for the work queued on hip_stream (NULL = the null stream), then report what the device found in the
+ * plan's heterogeneous batches since the previous stp_sync: STP_E_INVAL if any element of a batch of stp_run
+ * or stp_run_noalloc had a class id outside 0..nclass-1 (those elements' outputs were not written; the flag
+ * is cleared), else STP_OK. STP_E_DEVICE if the stream reported a failure. Synchronous; not capturable. */
+stp_status stp_sync(stp_plan_t plan, void* hip_stream);
 
 /* stp_run for callers that cannot allocate device memory (code under HIP graph capture, serving loops and
  * harnesses that forbid hipMalloc). Same arguments, outputs and kernels as stp_run. A heterogeneous plan's
@@ -271,8 +280,9 @@ stp_status stp_reserve(stp_plan_t plan, int64_t max_nelem);
 stp_status stp_submit(stp_plan_t plan, const stp_batch* batch, uint64_t* ticket);
 
 /* Query a ticket. Returns STP_PENDING while queued or running, STP_OK once complete (info filled, the
- * ticket retired), STP_E_INVAL for an unknown or already retired ticket, STP_E_DEVICE if its launch
- * failed. info may be NULL. */
+ * ticket retired), STP_E_INVAL for an unknown or already retired ticket, or for a completed batch with class
+ * ids outside 0..nclass-1 (those elements' outputs were not written), STP_E_DEVICE if its launch failed.
+ * info may be NULL. */
 stp_status stp_poll(stp_plan_t plan, uint64_t ticket, stp_ticket_info* info);
 
 /* Wait until every submitted ticket of the plan has completed (completion info stays pollable). */

@@ -252,7 +252,7 @@ void free_plan_memory(stp_plan_s* p)
         for (void* q : {cs.dD, cs.de0, cs.de1, cs.de0_64, cs.de1_64, cs.dDsplit, cs.daux, cs.dw})
             if (q) (void)hipFree(q);
     }
-    for (void* q : {p->d_hcls, (void*)p->d_slots, (void*)p->d_orders, (void*)p->d_bncls})
+    for (void* q : {p->d_hcls, (void*)p->d_slots, (void*)p->d_orders, (void*)p->d_bncls, (void*)p->d_bad})
         if (q) (void)hipFree(q);
     free_scratch(p->run_scratch);
 }
@@ -408,6 +408,23 @@ stp_status stp_run(stp_plan_t p, const stp_batch* b, void* stream)
     if (b->nelem == 0) return STP_OK;
     DeviceGuard g(p->device);
     return launch_batch(p, b, static_cast<hipStream_t>(stream));
+}
+
+stp_status stp_sync(stp_plan_t p, void* stream)
+{
+    g_last_error.clear();
+    if (!p) return fail(STP_E_INVAL, "plan is NULL");
+    DeviceGuard g(p->device);
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (!p->d_bad) return STP_OK;  // single-class plans have no class ids
+    int32_t bad = 0;
+    if ((e = hipMemcpy(&bad, p->d_bad, sizeof bad, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e, "hipMemcpy(flag)");
+    if (!bad) return STP_OK;
+    const int32_t zero = 0;
+    if ((e = hipMemcpy(p->d_bad, &zero, sizeof zero, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e, "hipMemcpy(flag)");
+    return fail(STP_E_INVAL, "a batch run since the last stp_sync had class ids outside 0..%d; those elements' outputs "
+                "were not written", (int)p->classes.size() - 1);
 }
 
 }  // extern "C"

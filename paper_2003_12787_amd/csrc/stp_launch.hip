@@ -18,13 +18,18 @@ __global__ void clear_counts(int32_t* counts, int n)
     if (i < n) counts[i] = 0;
 }
 
+// Elements with a class id outside 0..nclass-1 are skipped (their outputs are not written) and flagged in
+// *bad, which the host reports (stp_sync, or the serving ticket's status).
 __global__ void bucket_by_class(const int32_t* cls, int64_t nelem, int nclass, int32_t* lists, int64_t cap,
-                                int32_t* counts)
+                                int32_t* counts, int32_t* bad)
 {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= nelem) return;
     int c = cls[e];
-    if (c < 0 || c >= nclass) return;  // elements with an invalid class id are skipped
+    if (c < 0 || c >= nclass) {
+        *bad = 1;
+        return;
+    }
     int pos = atomicAdd(&counts[c], 1);
     lists[(int64_t)c * cap + pos] = (int32_t)e;
 }
@@ -38,7 +43,8 @@ constexpr int64_t kBucketSmallMax = 65536;
 
 __global__ void __launch_bounds__(kBucketThreads)
     bucket_small(const int32_t* cls, int64_t nelem, int nclass, int32_t* lists, int64_t cap, int32_t* counts,
-                 const int32_t* slots, const int32_t* orders, const int32_t* bncls, int32_t* tile_start, int32_t* heads)
+                 const int32_t* slots, const int32_t* orders, const int32_t* bncls, int32_t* tile_start, int32_t* heads,
+                 int32_t* bad)
 {
     __shared__ int32_t cnt[kMaxClasses];
     const int t = threadIdx.x;
@@ -46,7 +52,10 @@ __global__ void __launch_bounds__(kBucketThreads)
     __syncthreads();
     for (int64_t e = t; e < nelem; e += kBucketThreads) {
         const int c = cls[e];
-        if (c < 0 || c >= nclass) continue;  // elements with an invalid class id are skipped
+        if (c < 0 || c >= nclass) {  // skipped and flagged, as in bucket_by_class
+            *bad = 1;
+            continue;
+        }
         const int pos = atomicAdd(&cnt[c], 1);
         lists[(int64_t)c * cap + pos] = (int32_t)e;
     }
@@ -199,7 +208,9 @@ stp_status reserve_scratch(stp_plan_s* p, HeteroScratch& s, int64_t nelem)
     if (s.cap >= nelem && s.counts) return STP_OK;
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    int32_t* const bad = s.bad;  // not owned by the scratch (a serving lane's flag word)
     free_scratch(s);
+    s.bad = bad;
     const size_t cap = (size_t)std::max<int64_t>(nelem, 1);
     if ((e = hipMalloc(&s.lists, sizeof(int32_t) * (size_t)nclass * cap)) != hipSuccess) return hip_fail(e, "hipMalloc(lists)");
     if ((e = hipMalloc(&s.counts, sizeof(int32_t) * kMaxClasses)) != hipSuccess) return hip_fail(e, "hipMalloc(counts)");
@@ -236,13 +247,14 @@ stp_status launch_batch(stp_plan_s* p, const stp_batch* b, hipStream_t stream, H
             if (st != STP_OK) return st;
         }
     }
+    int32_t* bad = s->bad ? s->bad : p->d_bad;
     if (b->nelem <= kBucketSmallMax) {
         hipLaunchKernelGGL(bucket_small, dim3(1), dim3(kBucketThreads), 0, stream, b->cls, b->nelem, nclass, s->lists,
-                           s->cap, s->counts, p->d_slots, p->d_orders, p->d_bncls, s->tile_start, s->heads);
+                           s->cap, s->counts, p->d_slots, p->d_orders, p->d_bncls, s->tile_start, s->heads, bad);
     } else {
         hipLaunchKernelGGL(clear_counts, dim3(1), dim3(64), 0, stream, s->counts, nclass);
         hipLaunchKernelGGL(bucket_by_class, dim3((unsigned)((b->nelem + 255) / 256)), dim3(256), 0, stream, b->cls,
-                           b->nelem, nclass, s->lists, s->cap, s->counts);
+                           b->nelem, nclass, s->lists, s->cap, s->counts, bad);
         hipLaunchKernelGGL(hetero_setup, dim3(1), dim3(64), 0, stream, s->counts, p->d_slots, p->d_orders,
                            p->d_bncls, s->tile_start, s->heads);
     }
@@ -305,7 +317,7 @@ stp_status launch_batch(stp_plan_s* p, const stp_batch* b, hipStream_t stream, H
 stp_status hetero_prepare(stp_plan_s* p)
 {
     const int nclass = (int)p->classes.size();
-    for (void** q : {&p->d_hcls, (void**)&p->d_slots, (void**)&p->d_orders, (void**)&p->d_bncls})
+    for (void** q : {&p->d_hcls, (void**)&p->d_slots, (void**)&p->d_orders, (void**)&p->d_bncls, (void**)&p->d_bad})
         if (*q) {
             (void)hipFree(*q);
             *q = nullptr;
@@ -365,6 +377,8 @@ stp_status hetero_prepare(stp_plan_s* p)
         }
     }
     hipError_t e;
+    if ((e = hipMalloc(&p->d_bad, sizeof(int32_t))) != hipSuccess) return hip_fail(e, "hipMalloc(flag)");
+    if ((e = hipMemset(p->d_bad, 0, sizeof(int32_t))) != hipSuccess) return hip_fail(e, "hipMemset(flag)");
     if ((e = hipMalloc(&p->d_hcls, sizeof(hetero::HClass) * nclass)) != hipSuccess) return hip_fail(e, "hipMalloc(classes)");
     if ((e = hipMemcpy(p->d_hcls, hc.data(), sizeof(hetero::HClass) * nclass, hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "hipMemcpy(classes)");

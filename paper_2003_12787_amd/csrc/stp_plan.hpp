@@ -62,6 +62,8 @@ struct HeteroScratch {
     int32_t* counts = nullptr;      // [kMaxClasses]
     int32_t* tile_start = nullptr;  // [kHeteroBuckets][kMaxClasses + 1]
     int32_t* heads = nullptr;       // [kHeteroBuckets]
+    int32_t* bad = nullptr;         // set to 1 by the bucketing pass when a class id is out of range (NULL:
+                                    // the plan's d_bad)
     int64_t cap = 0;
     // Classes with their own launch run on side streams, forked from and joined back into the caller's
     // stream with events, concurrently with the persistent launches (their tails overlap).
@@ -90,6 +92,8 @@ struct stp_plan_s {
     int32_t* d_slots = nullptr;   // [nclass] elements per tile (1 for classes with their own launch)
     int32_t* d_orders = nullptr;  // [kHeteroBuckets][kMaxClasses]
     int32_t* d_bncls = nullptr;   // [kHeteroBuckets]
+    int32_t* d_bad = nullptr;     // set to 1 when stp_run / stp_run_noalloc met an out-of-range class id
+                                  // (read and cleared by stp_sync)
     int hetero_grid_per_cu = 4;   // persistent workgroups per CU
     size_t hetero_lds_budget = stp::kHeteroLdsBudget;  // LDS of one persistent workgroup (sets tile sizes)
     int autotune = 0;

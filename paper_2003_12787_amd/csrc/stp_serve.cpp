@@ -7,10 +7,14 @@
 //                launches on the lane with the fewest batches in flight and records a completion event;
 //   completers : one per lane, wait for that lane's events in launch order (one stream, so they finish in
 //                order), stamp the completion time and release the batch's bytes.
+// Completion events are pooled per lane. Heterogeneous batches report class ids outside the plan through a
+// ring of pinned host words per lane, one per batch in flight: the bucketing pass writes the batch's word,
+// and its completer turns it into the ticket's status.
 // Small batches cannot fill the GPU and a batch takes at least as long as its slowest element, so several
 // lanes let independent batches overlap. Tickets carry host monotonic timestamps (submit, launch, completion)
 // for latency statistics.
 #include <chrono>
+#include <cstring>
 
 #include "stp_plan.hpp"
 
@@ -25,6 +29,7 @@ double now_seconds()
 namespace {
 
 constexpr int kLanes = 4;
+constexpr int kRing = 4096;  // flag words per lane: bounds the batches in flight on a lane
 
 struct Pending {
     uint64_t ticket;
@@ -37,6 +42,7 @@ struct InFlight {
     uint64_t ticket;
     hipEvent_t ev;
     size_t bytes;
+    int slot;  // flag word of the batch in the lane's ring (-1: single-class plan)
 };
 
 struct TicketRec {
@@ -47,6 +53,10 @@ struct Lane {
     hipStream_t stream = nullptr;
     HeteroScratch scratch;
     std::deque<InFlight> inflight;
+    std::vector<hipEvent_t> events;   // completion events not in use
+    int32_t* ring = nullptr;          // [kRing] pinned host flags (heterogeneous plans)
+    int32_t* dring = nullptr;         // the same words as the device addresses them
+    uint64_t seq = 0;                 // batches launched on the lane
     std::condition_variable cv;
     std::thread completer;
 };
@@ -87,6 +97,14 @@ size_t batch_bytes(const stp_plan_s* p, const stp_batch* b)
     return (size_t)b->nelem * (per + scratch);
 }
 
+int least_loaded(const ServeState* s)
+{
+    int li = 0;
+    for (int l = 1; l < kLanes; ++l)
+        if (s->lanes[l].inflight.size() < s->lanes[li].inflight.size()) li = l;
+    return li;
+}
+
 void dispatcher_main(stp_plan_s* p)
 {
     ServeState* s = p->serve;
@@ -94,7 +112,8 @@ void dispatcher_main(stp_plan_s* p)
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         s->cv_dispatch.wait(lk, [&] {
-            return (!s->queue.empty() && s->inflight_bytes + s->queue.front().bytes <= p->serve_budget) ||
+            return (!s->queue.empty() && s->inflight_bytes + s->queue.front().bytes <= p->serve_budget &&
+                    s->lanes[least_loaded(s)].inflight.size() < (size_t)kRing) ||
                    (s->stop && s->queue.empty());
         });
         if (s->queue.empty()) break;  // stopping, nothing left to launch
@@ -102,28 +121,35 @@ void dispatcher_main(stp_plan_s* p)
         s->queue.pop_front();
         s->inflight_bytes += job.bytes;
         ++s->launching;
-        int li = 0;
-        for (int l = 1; l < kLanes; ++l)
-            if (s->lanes[l].inflight.size() < s->lanes[li].inflight.size()) li = l;
-        Lane& lane = s->lanes[li];
+        Lane& lane = s->lanes[least_loaded(s)];
         s->tickets[job.ticket].info.t_start = now_seconds();
+        hipEvent_t ev = nullptr;
+        if (!lane.events.empty()) {
+            ev = lane.events.back();
+            lane.events.pop_back();
+        }
         lk.unlock();
         if (job.batch.dt_h_scalar) {
             job.batch.dt = &job.dt_s;
             job.batch.h = &job.h_s;
         }
+        int slot = -1;
+        if (lane.ring) {  // the batch's flag word; its previous batch has completed (at most kRing in flight)
+            slot = (int)(lane.seq++ % kRing);
+            lane.ring[slot] = 0;
+            lane.scratch.bad = lane.dring + slot;
+        }
         // Only this thread launches on a lane, so its scratch is not shared by overlapping launches.
         stp_status st = launch_batch(p, &job.batch, lane.stream, &lane.scratch);
-        hipEvent_t ev = nullptr;
         if (st == STP_OK) {
-            hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            hipError_t e = ev ? hipSuccess : hipEventCreateWithFlags(&ev, hipEventDisableTiming);
             if (e == hipSuccess) e = hipEventRecord(ev, lane.stream);
             if (e != hipSuccess) st = STP_E_DEVICE;
         }
         lk.lock();
         --s->launching;
         if (st != STP_OK) {
-            if (ev) (void)hipEventDestroy(ev);
+            if (ev) lane.events.push_back(ev);
             auto& r = s->tickets[job.ticket];
             r.info.status = st;
             r.info.t_done = now_seconds();
@@ -131,7 +157,7 @@ void dispatcher_main(stp_plan_s* p)
             if (s->idle()) s->cv_idle.notify_all();
             continue;
         }
-        lane.inflight.push_back({job.ticket, ev, job.bytes});
+        lane.inflight.push_back({job.ticket, ev, job.bytes, slot});
         ++s->inflight_count;
         lane.cv.notify_one();
     }
@@ -151,13 +177,14 @@ void completer_main(stp_plan_s* p, int li)
         lk.unlock();
         hipError_t e = hipEventSynchronize(f.ev);
         double t = now_seconds();
-        (void)hipEventDestroy(f.ev);
+        const bool bad = f.slot >= 0 && reinterpret_cast<volatile int32_t*>(lane.ring)[f.slot] != 0;
         lk.lock();
+        lane.events.push_back(f.ev);
         lane.inflight.pop_front();
         --s->inflight_count;
         auto& r = s->tickets[f.ticket];
         r.info.t_done = t;
-        r.info.status = e == hipSuccess ? STP_OK : STP_E_DEVICE;
+        r.info.status = e != hipSuccess ? STP_E_DEVICE : (bad ? STP_E_INVAL : STP_OK);
         s->inflight_bytes -= f.bytes;
         s->cv_dispatch.notify_one();
         if (s->idle()) s->cv_idle.notify_all();
@@ -187,9 +214,16 @@ stp_status serve_start(stp_plan_s* p)
         const int64_t cap = std::min<int64_t>(65536, std::max<int64_t>(1, (int64_t)(p->serve_budget / batch_bytes(p, &one))));
         for (auto& l : s->lanes) {
             stp_status st = reserve_scratch(p, l.scratch, cap);
+            if (st == STP_OK) {
+                hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&l.ring), sizeof(int32_t) * kRing, hipHostMallocMapped);
+                if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&l.dring), l.ring, 0);
+                if (e != hipSuccess) st = hip_fail(e, "hipHostMalloc(serving flags)");
+                else std::memset(l.ring, 0, sizeof(int32_t) * kRing);
+            }
             if (st != STP_OK) {
                 for (auto& m : s->lanes) {
                     free_scratch(m.scratch);
+                    if (m.ring) (void)hipHostFree(m.ring);
                     if (m.stream) (void)hipStreamDestroy(m.stream);
                 }
                 delete s;
@@ -224,6 +258,8 @@ void serve_stop(stp_plan_s* p)
         (void)hipStreamSynchronize(l.stream);
         (void)hipStreamDestroy(l.stream);
         free_scratch(l.scratch);
+        for (hipEvent_t ev : l.events) (void)hipEventDestroy(ev);
+        if (l.ring) (void)hipHostFree(l.ring);
     }
     delete s;
     p->serve = nullptr;
@@ -284,6 +320,9 @@ stp_status stp_poll(stp_plan_t p, uint64_t ticket, stp_ticket_info* info)
     stp_status st = (stp_status)it->second.info.status;
     if (st == STP_PENDING) return STP_PENDING;
     s->tickets.erase(it);
+    if (st == STP_E_INVAL)
+        return fail(st, "ticket %llu had class ids outside 0..%d; those elements' outputs were not written",
+                    (unsigned long long)ticket, (int)p->classes.size() - 1);
     if (st != STP_OK) return fail(st, "ticket %llu failed on the device", (unsigned long long)ticket);
     return STP_OK;
 }

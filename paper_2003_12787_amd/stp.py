@@ -24,7 +24,7 @@ GAUSS_LEGENDRE, GAUSS_LOBATTO = 0, 1
 VARIANT_AUTO, VARIANT_PLAIN, VARIANT_FUSED, VARIANT_MFMA = 0, 1, 2, 3
 
 # Exported symbols declared in include/stp.h.
-SYMBOLS = ("stp_plan", "stp_plan_free", "stp_run", "stp_run_noalloc", "stp_reserve", "stp_submit", "stp_poll", "stp_drain",
+SYMBOLS = ("stp_plan", "stp_plan_free", "stp_run", "stp_run_noalloc", "stp_sync", "stp_reserve", "stp_submit", "stp_poll", "stp_drain",
            "stp_class_cost", "stp_correct", "stp_face_params", "stp_plan_describe", "stp_last_error")
 
 
@@ -83,6 +83,7 @@ def lib():
         L.stp_plan_free.restype = None
         L.stp_run.argtypes = [C.c_void_p, C.POINTER(Batch), C.c_void_p]
         L.stp_run_noalloc.argtypes = [C.c_void_p, C.POINTER(Batch), C.c_void_p]
+        L.stp_sync.argtypes = [C.c_void_p, C.c_void_p]
         L.stp_submit.argtypes = [C.c_void_p, C.POINTER(Batch), C.POINTER(C.c_uint64)]
         L.stp_poll.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(TicketInfo)]
         L.stp_drain.argtypes = [C.c_void_p]
@@ -93,7 +94,7 @@ def lib():
         L.stp_face_params.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
         L.stp_last_error.argtypes = []
         L.stp_last_error.restype = C.c_char_p
-        for f in ("stp_plan", "stp_run", "stp_run_noalloc", "stp_reserve", "stp_submit", "stp_poll", "stp_drain", "stp_class_cost",
+        for f in ("stp_plan", "stp_run", "stp_run_noalloc", "stp_sync", "stp_reserve", "stp_submit", "stp_poll", "stp_drain", "stp_class_cost",
                   "stp_plan_describe", "stp_correct"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -193,6 +194,11 @@ class Plan:
     def run(self, batch, stream=None):
         """Queue the predictor on `stream` (a torch.cuda.Stream, a raw handle, or None = current)."""
         return _check(lib().stp_run(self.handle, C.byref(batch), C.c_void_p(_stream(stream))))
+
+    def sync_status(self, stream=None):
+        """stp_sync: wait for `stream` and return the raw status (STP_E_INVAL if a heterogeneous batch since the
+        last sync had out-of-range class ids)."""
+        return lib().stp_sync(self.handle, C.c_void_p(_stream(stream)))
 
     def run_noalloc(self, batch, stream=None):
         """stp_run_noalloc: as run(), with the heterogeneous scratch taken from the library's static array."""

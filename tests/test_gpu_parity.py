@@ -461,7 +461,8 @@ def test_uniform_graph_capture_replays():
 
 
 def test_serving_heterogeneous_batches_match_run():
-    """Mixed-physics batches through the serving lanes (each with its own scratch) equal stp_run's output."""
+    """Mixed-physics batches through the serving lanes (each with its own scratch) equal stp_run's output, and
+    the served outputs match the oracle."""
     import torch
     mb = mixed_batch(seed=907)
     plan = stp.Plan(mb.classes, prec=stp.FP32, serve_mem_budget=256 << 20)
@@ -490,6 +491,7 @@ def test_serving_heterogeneous_batches_match_run():
     for o, _ in outs:
         for k, v in o.items():
             assert np.array_equal(v.double().cpu().numpy(), ref[k]), k
+    say(f"[serve]   served outputs vs oracle: worst {check_mixed(mb, stp.FP32, {k: v.double().cpu().numpy() for k, v in outs[0][0].items()}):.2e}")
     plan.close()
 
 
