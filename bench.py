@@ -39,7 +39,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--nelem", type=int, default=65536)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU-oracle time (bounded sample)")
+    ap.add_argument("--cpu-seconds", type=float, default=18.0,
+                    help="target CPU-oracle time over its three timed runs (bounded sample)")
     ap.add_argument("--copy-gib", type=float, default=1.0,
                     help="size of the device-to-device copy timed as the measured HBM reference (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -129,6 +130,61 @@ def time_launches(fn, steps, warmup, stream, torch):
     return np.array([a.elapsed_time(b) for a, b in ev])
 
 
+def bench_c1(args, torch, stp, W, runner):
+    """The small FP64 configuration: elastic N = 3 (4^3 nodes), 64 elements, per-node material, the plain FP64
+    predictor. The whole batch is 2 MB, so a call is bound by launch latency, not by a roofline: report the
+    per-call GPU time (HIP events on the stream) and the wall latency of a call plus its synchronisation, as
+    p50 / p99 over many calls. Returns the outputs for the CPU leg's error check."""
+    b = W.c1_elastic_n3()
+    plan = stp.Plan([runner.class_of(b)], prec=stp.FP64)
+    db = runner.DeviceBatch(plan, b)
+    stream = torch.cuda.Stream()
+    calls = 400
+    ev = time_launches(lambda st: plan.run(db.cbatch, st), calls, 20, stream, torch)
+    wall = np.zeros(calls)
+    for i in range(calls):
+        t0 = time.perf_counter()
+        plan.run(db.cbatch, stream)
+        stream.synchronize()
+        wall[i] = time.perf_counter() - t0
+    out = db.outputs()
+    plan.close()
+    res = {"workload": "elastic N=3 (4^3 nodes), m=9, 64 elements, per-node material, FP64 plain",
+           "calls": calls, "gpu_p50_us": float(np.percentile(ev, 50) * 1e3),
+           "gpu_p99_us": float(np.percentile(ev, 99) * 1e3), "wall_p50_us": float(np.percentile(wall, 50) * 1e6),
+           "wall_p99_us": float(np.percentile(wall, 99) * 1e6)}
+    res["elements_per_s_gpu"] = b.nelem / (res["gpu_p50_us"] * 1e-6)
+    res["elements_per_s_wall"] = b.nelem / (res["wall_p50_us"] * 1e-6)
+    log(f"[bench] C1 elastic N=3, 64 elements, FP64: GPU p50 {res['gpu_p50_us']:.1f} us p99 {res['gpu_p99_us']:.1f} us; "
+        f"wall p50 {res['wall_p50_us']:.1f} us p99 {res['wall_p99_us']:.1f} us")
+    return res, b, out
+
+
+def cpu_description(threads):
+    """The host CPU as /proc/cpuinfo names it, with the logical CPUs visible and the oracle's thread count."""
+    info = {}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for l in f:
+                if ":" not in l:
+                    if info:
+                        break  # first processor only
+                    continue
+                k, v = (x.strip() for x in l.split(":", 1))
+                if k in ("vendor_id", "model name", "cpu family", "model", "stepping", "cpu MHz", "cache size") \
+                        and k not in info:
+                    info[k] = v
+    except OSError:
+        pass
+    info["logical_cpus"] = os.cpu_count()
+    try:
+        info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    info["oracle_threads"] = threads
+    return info
+
+
 def bench_lobatto(args, torch, stp, runner, b, ids):
     """The benchmark workload on Gauss-Lobatto nodes (the other node family of Sec. II-A): the split-BF16x3
     MFMA and FP32 fused kernels with the plan's Lobatto tables. Returns timings and sampled outputs of the
@@ -205,7 +261,9 @@ def bench_full_step(args, torch, stp, W):
 
     t_step = time_launches(step, args.steps, args.warmup, stream, torch)
     plan.close()
-    corr_bytes = 4.0 * (5 * n3 * m + 12 * n2 * m) * E  # Q, favg x3, own and neighbours' faces read; q_new written
+    # algorithmic bytes: Q and favg x3 read, q_new written, and every element's face block read once (a block is
+    # used by its element and by the neighbour across each face; the second use is not new HBM data)
+    corr_bytes = 4.0 * (5 * n3 * m + 6 * n2 * m) * E
     ms_c = float(np.median(t_corr))
     res = {"workload": f"periodic {nx}x{ny}x{nz} mesh, elastic N=7, per-element material, split-BF16x3 predictor "
                        "+ FP32 corrector", "nelem": E,
@@ -532,14 +590,16 @@ def main():
     h = results[head]
     # Roofline of the dominant (only) kernel of a step: which ceiling binds at the algorithmic counts. The
     # derivative contractions are 2 n n^3 q_d flops per direction and application (q_d = 6 quantities read
-    # by the elastic B_d), N+1 applications; on the split-BF16x3 variant they run on the matrix cores as
-    # three BF16 products (dense BF16 peak), the rest of its flops on the VALU.
+    # by the elastic B_d), N+1 applications; on the split-BF16x3 variant they run on the matrix cores: one
+    # 16x16x32 BF16 product per 16 lines of 8 nodes, 8 times the contraction's multiply-adds (the six split
+    # products, two output rows per node, the other line group's zero blocks), at the dense BF16 peak; the
+    # rest of its flops run on the VALU.
     valu = "f64" if h["dtype"] == "f64" else "f32"  # the VALU type of the non-contraction work
     n = b.N + 1
     contr = (b.N + 1) * 3 * 2 * n * n ** 3 * 6
     t_hbm = h["bytes_per_element"] / (HBM_PEAK_GBS * 1e9)
     if head == "bf16x3_mfma":
-        t_cmp = 3 * contr / (MFMA_BF16_PEAK_TFS * 1e12) + (h["flops_per_element"] - contr) / (ALU_PEAK_TFS["f32"] * 1e12)
+        t_cmp = 8 * contr / (MFMA_BF16_PEAK_TFS * 1e12) + (h["flops_per_element"] - contr) / (ALU_PEAK_TFS["f32"] * 1e12)
     else:
         t_cmp = h["flops_per_element"] / (ALU_PEAK_TFS[valu] * 1e12)
     if t_hbm >= t_cmp:
@@ -558,6 +618,7 @@ def main():
     if args.copy_gib > 0:
         copy = copy_bandwidth(args.copy_gib, torch)
 
+    c1, c1_batch, c1_out = bench_c1(args, torch, stp, W, runner)
     lob_ids = np.linspace(0, E - 1, min(E, 256)).astype(np.int64)
     lobatto = None if args.no_hetero else bench_lobatto(args, torch, stp, runner, b, lob_ids)
     acoustic = None if args.no_hetero else bench_acoustic(args, torch, stp, W, runner)
@@ -576,13 +637,16 @@ def main():
         t0 = time.perf_counter()
         oracle.stp(b.N, b.physics, b.Q[probe], b.dt[probe], b.h[probe], params=b.params[probe], nthreads=threads)
         rate = len(probe) / (time.perf_counter() - t0)
-        k = int(min(E, max(threads, rate * args.cpu_seconds)))
+        k = int(min(E, max(threads, rate * args.cpu_seconds / 3)))
         ids = np.unique(np.concatenate([np.linspace(0, E - 1, k).astype(np.int64), err_ids]))
         k = len(ids)
-        log(f"[bench] CPU oracle on {k} elements, {threads} threads")
-        t0 = time.perf_counter()
-        ref = oracle.stp(b.N, b.physics, b.Q[ids], b.dt[ids], b.h[ids], params=b.params[ids], nthreads=threads)
-        t = time.perf_counter() - t0
+        log(f"[bench] CPU oracle on {k} elements, {threads} threads, 3 runs")
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            ref = oracle.stp(b.N, b.physics, b.Q[ids], b.dt[ids], b.h[ids], params=b.params[ids], nthreads=threads)
+            times.append(time.perf_counter() - t0)
+        t = float(np.median(times))
         # per-output max-relative error of every variant on the checked elements (a subset of the sample)
         pos = np.searchsorted(ids, err_ids)
         for name, got in sampled.items():
@@ -623,22 +687,30 @@ def main():
                 curv[name]["checked_elements"] = int(len(ck["ids"]))
                 log(f"[bench] curvilinear {name}: max rel err vs oracle {errs}")
             del ref
+        # C1: every element of the small FP64 batch against the oracle
+        ref = oracle.stp(c1_batch.N, c1_batch.physics, c1_batch.Q, c1_batch.dt, c1_batch.h, params=c1_batch.params,
+                         nthreads=threads)
+        errs = {}
+        for key in ("qavg", "favg", "qface"):
+            y = ref[key].reshape(c1_batch.nelem, -1)
+            x = c1_out[key].reshape(c1_batch.nelem, -1)
+            errs[key] = float((np.abs(x - y).max(axis=1) / np.abs(y).max(axis=1)).max())
+        c1["max_rel_err_vs_oracle"] = errs
+        log(f"[bench] C1: max rel err vs oracle {errs}")
+        del ref
         # one host thread on a small sample, for the per-core rate
         one = np.linspace(0, E - 1, min(E, 256)).astype(np.int64)
         t0 = time.perf_counter()
         oracle.stp(b.N, b.physics, b.Q[one], b.dt[one], b.h[one], params=b.params[one], nthreads=1)
         t1 = time.perf_counter() - t0
-        model = ""
-        try:
-            with open("/proc/cpuinfo") as f:
-                model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
-        except OSError:
-            pass
+        desc = cpu_description(threads)
         cpu = {"value": k / t, "unit": "element-updates/s", "cores": threads, "kind": "oracle",
-               "sample": f"{k} of the {E} elements (evenly spaced), FP64, {t:.1f} s",
+               "sample": f"{k} of the {E} elements (evenly spaced), FP64; median of 3 runs "
+                         f"({', '.join(f'{x:.1f}' for x in times)} s)",
                "value_1thread": len(one) / t1, "sample_1thread": f"{len(one)} elements, {t1:.2f} s",
-               "cpu_model": model}
-        log(f"[bench] CPU oracle: {k / t:.1f} el/s ({threads} threads), {len(one) / t1:.1f} el/s (1 thread), {model}")
+               "cpu_model": desc.get("model name", ""), "cpu": desc}
+        log(f"[bench] CPU oracle: {k / t:.1f} el/s ({threads} threads, median of 3), {len(one) / t1:.1f} el/s "
+            f"(1 thread), {desc}")
 
     line = {
         "metric": "STP element-updates/s + % roofline (elastic N=7) vs plain FP64; p50/p99 latency",
@@ -668,6 +740,7 @@ def main():
         "curvilinear": None if curv is None else {k: ({kk: vv for kk, vv in v.items() if kk != "sampled"}
                                                       if isinstance(v, dict) else v)
                                                   for k, v in curv.items() if k != "check"},
+        "c1_latency": c1,
         "heterogeneous": hetero,
         "serving": serving,
         "latency_p50_ms": serving["load_80pct"]["p50_ms"] if serving else None,

@@ -1,7 +1,11 @@
 """Summarise rocprofv3 CSV output (kernel trace stats, or one --pmc pass) into a short text table.
 
 usage: python -m paper_2003_12787_amd.profsummary stats <kernel_stats.csv>
+       python -m paper_2003_12787_amd.profsummary trace <kernel_trace.csv> [last_k]
        python -m paper_2003_12787_amd.profsummary pmc <counter_collection.csv> [<counter_collection.csv> ...]
+
+`trace` gives, per kernel, the dispatch count and the mean, median, min and max duration over all dispatches
+and over the last `last_k` of them (the launches a benchmark times after its warm-up ones).
 """
 import collections
 import csv
@@ -14,6 +18,29 @@ def stats(path):
     for r in rows:
         print(f"{r['Name'][:72]:<72} {r['Calls']:>5} {float(r['AverageNs']) / 1e3:>10.1f} "
               f"{float(r['MinNs']) / 1e3:>10.1f} {float(r['MaxNs']) / 1e3:>10.1f} {float(r['Percentage']):>6.2f}")
+
+
+def trace(path, last_k=None):
+    per = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        per[r["Kernel_Name"]].append((int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    hdr = f"{'kernel':<64} {'calls':>5} {'mean_us':>9} {'med_us':>9} {'min_us':>9} {'max_us':>9}"
+    if last_k:
+        hdr += f" | {'last':>4} {'mean_us':>9} {'med_us':>9} {'min_us':>9} {'max_us':>9}"
+    print(hdr)
+    rows = sorted(per.items(), key=lambda kv: -sum(e - b for b, e in kv[1]))
+    for name, d in rows:
+        d.sort()
+        us = [(e - b) / 1e3 for b, e in d]
+
+        def fmt(v):
+            v2 = sorted(v)
+            med = v2[len(v2) // 2] if len(v2) % 2 else 0.5 * (v2[len(v2) // 2 - 1] + v2[len(v2) // 2])
+            return f"{sum(v) / len(v):>9.1f} {med:>9.1f} {min(v):>9.1f} {max(v):>9.1f}"
+        line = f"{name[:64]:<64} {len(us):>5} {fmt(us)}"
+        if last_k and len(us) >= last_k:
+            line += f" | {last_k:>4} {fmt(us[-last_k:])}"
+        print(line)
 
 
 def pmc(paths):
@@ -30,5 +57,7 @@ def pmc(paths):
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2])
+    elif sys.argv[1] == "trace":
+        trace(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else None)
     else:
         pmc(sys.argv[2:])
