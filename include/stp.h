@@ -85,7 +85,8 @@ typedef enum {
     STP_E_UNSUPPORTED = -2,   /* order / quantity count / physics / precision not supported          */
     STP_E_NOMEM = -3,         /* allocation failed, or a submitted batch exceeds the serving budget  */
     STP_E_DEVICE = -4,        /* a HIP runtime call or a kernel launch failed                        */
-    STP_E_BUSY = -5           /* serving queue full                                                  */
+    STP_E_BUSY = -5,          /* serving queue full                                                  */
+    STP_E_TIMEOUT = -6        /* serving: the ticket's deadline passed before its batch was launched */
 } stp_status;
 
 typedef enum { STP_ACOUSTIC = 0, STP_ELASTIC = 1, STP_GENERIC = 2, STP_ELASTIC_CURV = 3 } stp_physics;
@@ -274,15 +275,25 @@ stp_status stp_reserve(stp_plan_t plan, int64_t max_nelem);
 
 /* Serving: enqueue a batch for the plan's dispatcher thread. The batch descriptor is copied; its device
  * buffers must stay valid until stp_poll reports completion. The serving streams do not wait for any other
- * stream: work that produces the inputs (or touches the outputs) must be complete before stp_submit. Admission: the batch's output+scratch bytes
- * must fit serve_mem_budget (STP_E_NOMEM if it never can); batches wait while the in-flight total would
- * exceed it. Returns STP_E_BUSY when the queue holds 65536 pending tickets. */
+ * stream: work that produces the inputs (or touches the outputs) must be complete before stp_submit. With the
+ * environment variable STP_SERVE_SPLIT = k > 0 at plan creation, a batch of more than k elements is queued as
+ * parts of at most k consecutive elements, which run on different serving lanes (default: not split); the
+ * ticket completes when every part has. Admission: each part's output+scratch bytes must fit
+ * serve_mem_budget (STP_E_NOMEM if it never can); parts wait while the in-flight total would exceed it.
+ * Returns STP_E_BUSY when the queue would hold more than 65536 pending parts. */
 stp_status stp_submit(stp_plan_t plan, const stp_batch* batch, uint64_t* ticket);
+
+/* stp_submit with a deadline: every part of the batch must be launched within timeout_s seconds of the
+ * submission. Parts still queued when it passes are dropped (their elements' outputs are not written; parts
+ * already launched run to completion) and the ticket completes with STP_E_TIMEOUT. timeout_s = HUGE_VAL is
+ * stp_submit; STP_E_INVAL for a negative or NaN timeout. */
+stp_status stp_submit_deadline(stp_plan_t plan, const stp_batch* batch, double timeout_s, uint64_t* ticket);
 
 /* Query a ticket. Returns STP_PENDING while queued or running, STP_OK once complete (info filled, the
  * ticket retired), STP_E_INVAL for an unknown or already retired ticket, or for a completed batch with class
- * ids outside 0..nclass-1 (those elements' outputs were not written), STP_E_DEVICE if its launch failed.
- * info may be NULL. */
+ * ids outside 0..nclass-1 (those elements' outputs were not written), STP_E_TIMEOUT when its deadline passed
+ * before all of it was launched, STP_E_DEVICE if a launch failed. A failed ticket is retired too. info may be
+ * NULL; t_start is the launch of its first part, t_done the completion of its last. */
 stp_status stp_poll(stp_plan_t plan, uint64_t ticket, stp_ticket_info* info);
 
 /* Wait until every submitted ticket of the plan has completed (completion info stays pollable). */

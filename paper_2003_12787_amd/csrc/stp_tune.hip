@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "stp_plan.hpp"
+#include "tune_cache.hpp"
 
 namespace stp {
 
@@ -37,39 +38,15 @@ __global__ void fill_kernel(T* x, int64_t n, double lo, double span)
 }
 
 // --------------------------------------------------------------------------------------------- JSON cache
-// The cache is one JSON object: key -> object of numbers. Only that shape is written or read.
-using Entry = std::map<std::string, double>;
-using Cache = std::map<std::string, Entry>;
+// The cache is one JSON object: key -> object of numbers (tune_cache.cpp parses and formats it).
+using Entry = TuneEntry;
+using Cache = TuneCache;
 
 std::string cache_path()
 {
     if (const char* e = std::getenv("STP_TUNE_CACHE")) return e;
     const char* h = std::getenv("HOME");
     return std::string(h ? h : ".") + "/.cache/stp_tune.json";
-}
-
-void skip_ws(const std::string& s, size_t& i)
-{
-    while (i < s.size() && (s[i] == ' ' || s[i] == '\n' || s[i] == '\r' || s[i] == '\t')) ++i;
-}
-
-bool read_string(const std::string& s, size_t& i, std::string& out)
-{
-    skip_ws(s, i);
-    if (i >= s.size() || s[i] != '"') return false;
-    size_t j = s.find('"', i + 1);
-    if (j == std::string::npos) return false;
-    out = s.substr(i + 1, j - i - 1);
-    i = j + 1;
-    return true;
-}
-
-bool expect(const std::string& s, size_t& i, char c)
-{
-    skip_ws(s, i);
-    if (i >= s.size() || s[i] != c) return false;
-    ++i;
-    return true;
 }
 
 Cache load_cache()
@@ -82,39 +59,7 @@ Cache load_cache()
     size_t k;
     while ((k = std::fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, k);
     std::fclose(f);
-    size_t i = 0;
-    if (!expect(s, i, '{')) return Cache{};
-    skip_ws(s, i);
-    if (i < s.size() && s[i] == '}') return c;
-    for (;;) {
-        std::string key;
-        if (!read_string(s, i, key) || !expect(s, i, ':') || !expect(s, i, '{')) return Cache{};
-        Entry e;
-        skip_ws(s, i);
-        if (i < s.size() && s[i] == '}') {
-            ++i;
-        } else {
-            for (;;) {
-                std::string name;
-                if (!read_string(s, i, name) || !expect(s, i, ':')) return Cache{};
-                skip_ws(s, i);
-                char* end = nullptr;
-                const double v = std::strtod(s.c_str() + i, &end);
-                if (end == s.c_str() + i) return Cache{};
-                i = end - s.c_str();
-                e[name] = v;
-                skip_ws(s, i);
-                if (i < s.size() && s[i] == ',') { ++i; continue; }
-                if (!expect(s, i, '}')) return Cache{};
-                break;
-            }
-        }
-        c[key] = e;
-        skip_ws(s, i);
-        if (i < s.size() && s[i] == ',') { ++i; continue; }
-        if (!expect(s, i, '}')) return Cache{};
-        break;
-    }
+    (void)parse_tune_cache(s, c);  // a malformed cache reads as empty (only costs retuning)
     return c;
 }
 
@@ -130,15 +75,8 @@ void store_cache(const Cache& c)
     const std::string tmp = path + ".tmp";
     FILE* f = std::fopen(tmp.c_str(), "wb");
     if (!f) return;  // an unwritable cache only costs retuning
-    std::fprintf(f, "{\n");
-    size_t n = 0;
-    for (auto& kv : c) {
-        std::fprintf(f, " \"%s\": {", kv.first.c_str());
-        size_t m = 0;
-        for (auto& e : kv.second) std::fprintf(f, "%s\"%s\": %.9g", m++ ? ", " : "", e.first.c_str(), e.second);
-        std::fprintf(f, "}%s\n", ++n < c.size() ? "," : "");
-    }
-    std::fprintf(f, "}\n");
+    const std::string text = format_tune_cache(c);
+    std::fwrite(text.data(), 1, text.size(), f);
     std::fclose(f);
     (void)std::rename(tmp.c_str(), path.c_str());
 }

@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libstp.so")
 
 # stp_status
-OK, PENDING, E_INVAL, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_BUSY = 0, 1, -1, -2, -3, -4, -5
+OK, PENDING, E_INVAL, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_BUSY, E_TIMEOUT = 0, 1, -1, -2, -3, -4, -5, -6
 # stp_physics / stp_prec
 ACOUSTIC, ELASTIC, GENERIC, ELASTIC_CURV = 0, 1, 2, 3
 FP64, FP32, BF16X3 = 0, 1, 2
@@ -24,7 +24,7 @@ GAUSS_LEGENDRE, GAUSS_LOBATTO = 0, 1
 VARIANT_AUTO, VARIANT_PLAIN, VARIANT_FUSED, VARIANT_MFMA = 0, 1, 2, 3
 
 # Exported symbols declared in include/stp.h.
-SYMBOLS = ("stp_plan", "stp_plan_free", "stp_run", "stp_run_noalloc", "stp_sync", "stp_reserve", "stp_submit", "stp_poll", "stp_drain",
+SYMBOLS = ("stp_plan", "stp_plan_free", "stp_run", "stp_run_noalloc", "stp_sync", "stp_reserve", "stp_submit", "stp_submit_deadline", "stp_poll", "stp_drain",
            "stp_class_cost", "stp_correct", "stp_face_params", "stp_plan_describe", "stp_last_error")
 
 
@@ -85,6 +85,7 @@ def lib():
         L.stp_run_noalloc.argtypes = [C.c_void_p, C.POINTER(Batch), C.c_void_p]
         L.stp_sync.argtypes = [C.c_void_p, C.c_void_p]
         L.stp_submit.argtypes = [C.c_void_p, C.POINTER(Batch), C.POINTER(C.c_uint64)]
+        L.stp_submit_deadline.argtypes = [C.c_void_p, C.POINTER(Batch), C.c_double, C.POINTER(C.c_uint64)]
         L.stp_poll.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(TicketInfo)]
         L.stp_drain.argtypes = [C.c_void_p]
         L.stp_class_cost.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
@@ -94,7 +95,8 @@ def lib():
         L.stp_face_params.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
         L.stp_last_error.argtypes = []
         L.stp_last_error.restype = C.c_char_p
-        for f in ("stp_plan", "stp_run", "stp_run_noalloc", "stp_sync", "stp_reserve", "stp_submit", "stp_poll", "stp_drain", "stp_class_cost",
+        for f in ("stp_plan", "stp_run", "stp_run_noalloc", "stp_sync", "stp_reserve", "stp_submit", "stp_submit_deadline", "stp_poll",
+                  "stp_drain", "stp_class_cost",
                   "stp_plan_describe", "stp_correct"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -237,6 +239,12 @@ class Plan:
     def submit(self, batch):
         t = C.c_uint64()
         _check(lib().stp_submit(self.handle, C.byref(batch), C.byref(t)))
+        return t.value
+
+    def submit_deadline(self, batch, timeout_s):
+        """stp_submit_deadline: parts not launched within timeout_s seconds are dropped (ticket: E_TIMEOUT)."""
+        t = C.c_uint64()
+        _check(lib().stp_submit_deadline(self.handle, C.byref(batch), C.c_double(timeout_s), C.byref(t)))
         return t.value
 
     def poll(self, ticket):

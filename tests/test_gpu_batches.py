@@ -243,3 +243,83 @@ def test_serving_preset_batches_match_oracle():
                 assert v < TOL[stp.FP32], (phys, N, k, v)
     say(f"[serve-oracle]   every element of every ticket, worst max rel err {worst:.2e}")
     plan.close()
+
+
+def test_serving_splits_large_batches_across_lanes(monkeypatch):
+    """With STP_SERVE_SPLIT = 1024, batches above 1024 elements are queued as parts on different lanes; the
+    outputs equal stp_run's bit for bit: a uniform batch with contiguous storage and host scalars dt, h; the
+    same with per-element dt, h; and a heterogeneous batch with per-element offsets."""
+    import torch
+    monkeypatch.setenv("STP_SERVE_SPLIT", "1024")
+    from paper_2003_12787_amd import runner
+    from test_gpu_parity import mixed_batch
+    b = W.elastic_batch(2, 3000, 945)
+    rng = np.random.default_rng(946)
+    bv = W.elastic_batch(3, 2500, 947)
+    bv.h = rng.uniform(0.5, 2.0, bv.nelem)
+    bv.dt = bv.dt * bv.h * rng.uniform(0.2, 1.0, bv.nelem)
+    for label, ub in (("uniform, scalar dt/h", b), ("uniform, per-element dt/h", bv)):
+        plan = stp.Plan([runner.class_of(ub)], prec=stp.FP32, serve_mem_budget=512 << 20)
+        ref = runner.run(plan, ub)
+        db = runner.DeviceBatch(plan, ub)
+        db.clear_outputs(float("nan"))
+        torch.cuda.synchronize()
+        say(f"[split] {label}: E={ub.nelem}")
+        t = plan.submit(db.cbatch)
+        plan.drain()
+        st, info = plan.poll(t)
+        assert st == stp.OK and info.t_done >= info.t_start >= info.t_submit
+        out = db.outputs()
+        for k in ref:
+            assert np.array_equal(out[k], ref[k]), (label, k)
+        plan.close()
+    mb = mixed_batch(E_scale=12, seed=948)
+    assert len(mb.cls) > 1024
+    plan = stp.Plan(mb.classes, prec=stp.FP32, serve_mem_budget=512 << 20)
+    ref_d = Dev(mb)
+    plan.run(ref_d.batch(plan))
+    torch.cuda.synchronize()
+    ref = ref_d.host()
+    d = Dev(mb)
+    torch.cuda.synchronize()
+    say(f"[split] heterogeneous: E={len(mb.cls)}")
+    t = plan.submit(d.batch(plan))
+    plan.drain()
+    st, _ = plan.poll(t)
+    assert st == stp.OK
+    got = d.host()
+    for k in ref:  # fface is written only for the classes with A; both runs leave the rest at NaN
+        assert np.array_equal(got[k], ref[k], equal_nan=True), k
+    plan.close()
+
+
+def test_serving_deadline(monkeypatch):
+    """A ticket whose deadline has passed before its batch is launched fails with STP_E_TIMEOUT and writes
+    nothing; tickets without a deadline (or with a generous one) complete. Split into parts (STP_SERVE_SPLIT)."""
+    import torch
+    monkeypatch.setenv("STP_SERVE_SPLIT", "1024")
+    from paper_2003_12787_amd import runner
+    b = W.elastic_batch(3, 2100, 949)  # three parts
+    plan = stp.Plan([runner.class_of(b)], prec=stp.FP32, serve_mem_budget=512 << 20)
+    ref = runner.run(plan, b)
+    late, ok1, ok2 = (runner.DeviceBatch(plan, b) for _ in range(3))
+    for db in (late, ok1, ok2):
+        db.clear_outputs(float("nan"))
+    torch.cuda.synchronize()
+    t_late = plan.submit_deadline(late.cbatch, 0.0)  # the deadline is the submission time itself
+    t_ok1 = plan.submit_deadline(ok1.cbatch, 60.0)
+    t_ok2 = plan.submit(ok2.cbatch)
+    plan.drain()
+    st, _ = plan.poll(t_late)
+    assert st == stp.E_TIMEOUT and "deadline" in stp.last_error()
+    assert np.isnan(late.outputs()["qavg"]).all()
+    for t, db in ((t_ok1, ok1), (t_ok2, ok2)):
+        st, _ = plan.poll(t)
+        assert st == stp.OK
+        out = db.outputs()
+        for k in ref:
+            assert np.array_equal(out[k], ref[k]), k
+    with pytest.raises(stp.StpError) as ei:
+        plan.submit_deadline(ok1.cbatch, -1.0)
+    assert ei.value.status == stp.E_INVAL
+    plan.close()
