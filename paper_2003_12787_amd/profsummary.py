@@ -3,6 +3,13 @@
 usage: python -m paper_2003_12787_amd.profsummary stats <kernel_stats.csv>
        python -m paper_2003_12787_amd.profsummary trace <kernel_trace.csv> [last_k]
        python -m paper_2003_12787_amd.profsummary pmc <counter_collection.csv> [<counter_collection.csv> ...]
+       python -m paper_2003_12787_amd.profsummary issue <counter_collection.csv> [match]
+
+`issue` reads one pass holding SQ_WAVES, SQ_WAVE_CYCLES, SQ_ACTIVE_INST_VALU, SQ_INSTS_VALU, SQ_INSTS_LDS,
+SQ_WAIT_INST_LDS and SQ_WAIT_INST_ANY and gives, per kernel whose name contains `match`, the dispatch duration,
+the VALU and LDS instructions per wave, and three shares: resident waves per SIMD and VALU-busy share of the
+SIMDs (both from the quad-cycle counters over the dispatch's duration at 2.4 GHz on 1024 SIMDs: a lower clock
+under load makes both larger), and the share of a wave's cycles spent waiting on LDS and on anything.
 
 `trace` gives, per kernel, the dispatch count and the mean, median, min and max duration over all dispatches
 and over the last `last_k` of them (the launches a benchmark times after its warm-up ones).
@@ -54,9 +61,32 @@ def pmc(paths):
         print(f"{k:<72} {g:>9} {c:<24} {len(v):>3} {sum(v) / len(v):>18.6g}")
 
 
+def issue(path, match="", clock_ghz=2.4, simds=1024):
+    cnt = collections.defaultdict(lambda: collections.defaultdict(list))
+    dur = collections.defaultdict(dict)
+    for r in csv.DictReader(open(path)):
+        k = r["Kernel_Name"]
+        if match not in k:
+            continue
+        cnt[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        dur[k][r["Dispatch_Id"]] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    print(f"{'kernel':<60} {'waves':>7} {'us':>8} {'valu/w':>7} {'lds/w':>6} {'w/simd':>6} "
+          f"{'valu%':>6} {'ldsw%':>6} {'wait%':>6}")
+    for k, c in cnt.items():
+        m = {n: sum(v) / len(v) for n, v in c.items()}
+        d = sum(dur[k].values()) / len(dur[k])
+        cyc = d * clock_ghz * simds  # SIMD-cycles of the dispatch
+        wv, wc = m["SQ_WAVES"], m["SQ_WAVE_CYCLES"]
+        print(f"{k[:60]:<60} {wv:>7.0f} {d / 1e3:>8.1f} {m['SQ_INSTS_VALU'] / wv:>7.0f} "
+              f"{m['SQ_INSTS_LDS'] / wv:>6.0f} {4 * wc / cyc:>6.2f} {100 * 4 * m['SQ_ACTIVE_INST_VALU'] / cyc:>6.1f} "
+              f"{100 * m['SQ_WAIT_INST_LDS'] / wc:>6.1f} {100 * m['SQ_WAIT_INST_ANY'] / wc:>6.1f}")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2])
+    elif sys.argv[1] == "issue":
+        issue(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else "")
     elif sys.argv[1] == "trace":
         trace(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else None)
     else:
