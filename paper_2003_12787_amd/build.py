@@ -32,6 +32,7 @@ CFLAGS = [
 # more than the 128 registers that allow four waves per SIMD.
 EXTRA = {
     "stp_mfma_n7.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+    "stp_mfma_n89.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
 }
 
 

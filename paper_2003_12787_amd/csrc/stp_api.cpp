@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "basis.hpp"
+#include "mfma_tables.hpp"
 
 namespace stp {
 
@@ -202,33 +203,15 @@ stp_status build_class(stp_plan_s* p, ClassState& cs)
         }
     }
     if (needSplit) {
-        // A operand of v_mfma_f32_16x16x32_bf16 for the split contraction, one row per lane. D (the FP32
-        // matrix with zero row sums) is split exactly into three BF16 pieces D = D0 + D1 + D2. Lane l holds row
-        // i = l % 16 and the 8 K entries of lane group q = l / 16, which pair with the B entries of the lanes of
-        // that group: the pieces of their nodes 2q and 2q+1 as (hi, mid) of 2q, (hi, mid) of 2q+1, lo of 2q,
-        // lo of 2q+1, hi of 2q, hi of 2q+1. Row i belongs to output node 2 (i / 4) + i % 2, part (i / 2) % 2:
-        //   part a: D0 on hi, mid and lo, D1 on the second copy of hi;   part b: D2 on hi, D1 on mid.
-        // The two parts of a node land in the same lane and sum to D0 (hi + mid + lo) + D1 (hi + mid) + D2 hi.
+        // A operands of the MFMA kernels: D (the FP32 matrix with zero row sums) split exactly into three BF16
+        // pieces D = D0 + D1 + D2, placed as each kernel's products expect (mfma_tables.cpp)
         float Df[kMaxNodes * kMaxNodes];
         derivative_matrix_f32(n, D, Df);
         uint16_t P0[kMaxNodes * kMaxNodes], P1[kMaxNodes * kMaxNodes], P2[kMaxNodes * kMaxNodes];
         split3_bf16(n * n, Df, P0, P1, P2);
-        uint16_t tab[64][8];
-        for (int l = 0; l < 64; ++l)
-            for (int e = 0; e < 8; ++e) {
-                const int i = l % 16, q = l / 16;
-                const int out = 2 * (i / 4) + i % 2, part = (i / 2) % 2;
-                // entry e: node 2q + which, piece kind 0 hi, 1 mid, 2 lo, 3 second hi
-                const int which = e < 4 ? e / 2 : e % 2;
-                const int kind = e < 4 ? e % 2 : (e < 6 ? 2 : 3);
-                const int src = out * n + 2 * q + which;
-                uint16_t v = 0;
-                if (part == 0) v = kind == 3 ? P1[src] : P0[src];
-                else if (kind == 0) v = P2[src];
-                else if (kind == 1) v = P1[src];
-                tab[l][e] = v;
-            }
-        if ((st = upload(&tab[0][0], 64 * 8, &cs.dDsplit)) != STP_OK) return st;
+        const std::vector<uint16_t> tab = n == 8 ? mfma_table_n8(P0, P1, P2) : mfma_table_hi(n, P0, P1, P2);
+        if (tab.empty()) return fail(STP_E_DEVICE, "MFMA table for n=%d failed its consistency check", n);
+        if ((st = upload(tab.data(), tab.size(), &cs.dDsplit)) != STP_OK) return st;
     }
     (void)hasA;
     if ((st = set_kernel(p, cs, chosen)) != STP_OK) return st;

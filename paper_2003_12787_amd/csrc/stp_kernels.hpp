@@ -33,8 +33,10 @@ KernelInfo plain_kernel_f32acc64_rt16(int N);
 // Fused kernel (presets, FP32, N <= 7): lanes own x-lines, even/odd derivatives, LDS transposes.
 KernelInfo fused_kernel_f32(int N, int physics);
 
-// Split-BF16 MFMA kernel (presets, FP32 I/O, N = 7).
+// Split-BF16 MFMA kernels (FP32 I/O): presets and curvilinear elastic at N = 7, Cartesian presets at N = 8, 9.
 KernelInfo mfma_kernel_n7(int physics);
+KernelInfo mfma_kernel_n89(int N, int physics);
+inline KernelInfo mfma_kernel(int N, int physics) { return N == 7 ? mfma_kernel_n7(physics) : mfma_kernel_n89(N, physics); }
 
 // Heterogeneous persistent kernel of one physics bucket (FP32 I/O, orders 1..7, 512 threads per workgroup).
 struct HeteroKernel {

@@ -160,13 +160,15 @@ struct Eligibility {
 
 Eligibility eligible(const stp_plan_s* p, const ClassState& cs)
 {
-    // the fused kernel implements the Cartesian presets, the MFMA kernel also curvilinear elastic elements
+    // the fused kernel implements the Cartesian presets up to order 7; the MFMA kernels the Cartesian presets at
+    // orders 7 to 9 and curvilinear elastic elements at order 7
     const bool cart = cs.cls.physics == STP_ACOUSTIC || cs.cls.physics == STP_ELASTIC;
     const bool curv = cs.cls.physics == STP_ELASTIC_CURV;
     const bool f32io = p->prec != STP_FP64;
     const bool simple = f32io && !cs.acc64 && !(cs.cls.flags & STP_SRC_POINT);
-    return {simple && cart && cs.cls.order <= 7,
-            simple && (cart || curv) && cs.cls.order == 7 && p->prec == STP_BF16X3};
+    const int N = cs.cls.order;
+    return {simple && cart && N <= 7,
+            simple && p->prec == STP_BF16X3 && ((N == 7 && (cart || curv)) || ((N == 8 || N == 9) && cart))};
 }
 
 }  // namespace
@@ -178,7 +180,7 @@ std::vector<std::pair<int, KernelInfo>> kernel_candidates(stp_plan_s* p, const C
     v.push_back({STP_VARIANT_PLAIN,
                  plain_kernel(p->prec == STP_FP64, cs.acc64, cs.cls.order, cs.cls.physics, cs.cls.nquant)});
     if (el.fused) v.push_back({STP_VARIANT_FUSED, fused_kernel_f32(cs.cls.order, cs.cls.physics)});
-    if (el.mfma) v.push_back({STP_VARIANT_MFMA, mfma_kernel_n7(cs.cls.physics)});
+    if (el.mfma) v.push_back({STP_VARIANT_MFMA, mfma_kernel(cs.cls.order, cs.cls.physics)});
     return v;
 }
 
@@ -196,7 +198,7 @@ KernelInfo select_kernel(stp_plan_s* p, const ClassState& cs, int* variant)
     case STP_VARIANT_FUSED:
         return el.fused ? fused_kernel_f32(cs.cls.order, cs.cls.physics) : KernelInfo{};
     case STP_VARIANT_MFMA:
-        return el.mfma ? mfma_kernel_n7(cs.cls.physics) : KernelInfo{};
+        return el.mfma ? mfma_kernel(cs.cls.order, cs.cls.physics) : KernelInfo{};
     default:
         return KernelInfo{};
     }

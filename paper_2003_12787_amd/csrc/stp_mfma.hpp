@@ -81,6 +81,44 @@ __device__ inline void deriv_mfma(const bf16x8& A, const Split2& s, float (&out)
     out[1] = c[1] + c[3];
 }
 
+// r[.][t] += the pointwise term of a Cartesian preset (acoustic or elastic) for g, the derivative along
+// direction D of the quantity dq(D, K) of the direction's derivative set, at L nodes (1/h is folded into the
+// material coefficients).
+template <int PHYS, int D, int K, int L, int R>
+__device__ inline void ncp_cart(const Material<float, PHYS> (&mt)[L], const float (&g)[L], float (&r)[R][L])
+{
+    if constexpr (PHYS == kElastic) {
+        using P = PhysTraits<kElastic>;
+        if constexpr (K < 3) {
+            if constexpr (K == D) {
+#pragma unroll
+                for (int t = 0; t < L; ++t) {
+                    r[3 + D][t] = fma(mt[t].c[3], g[t], r[3 + D][t]);
+                    r[3 + (D + 1) % 3][t] = fma(mt[t].c[1], g[t], r[3 + (D + 1) % 3][t]);
+                    r[3 + (D + 2) % 3][t] = fma(mt[t].c[1], g[t], r[3 + (D + 2) % 3][t]);
+                }
+            } else {
+                constexpr int q = P::sig(D, K);
+#pragma unroll
+                for (int t = 0; t < L; ++t) r[q][t] = fma(mt[t].c[2], g[t], r[q][t]);
+            }
+        } else {
+            constexpr int i = K - 3;
+#pragma unroll
+            for (int t = 0; t < L; ++t) r[i][t] = fma(mt[t].c[0], g[t], r[i][t]);
+        }
+    } else {
+        static_assert(PHYS == kAcoustic, "Cartesian presets only");
+        if constexpr (K == 0) {
+#pragma unroll
+            for (int t = 0; t < L; ++t) r[1 + D][t] = fma(mt[t].c[1], g[t], r[1 + D][t]);
+        } else {
+#pragma unroll
+            for (int t = 0; t < L; ++t) r[0][t] = fma(mt[t].c[0], g[t], r[0][t]);
+        }
+    }
+}
+
 template <int PHYS>
 struct Mfma8 {
     static constexpr int N = 7, n = 8, n2 = 64, n3 = 512;
@@ -234,34 +272,8 @@ struct Mfma8 {
                     r[b][t] = fma(Gd[t][a], gr, r[b][t]);
                 }
             }
-        } else if constexpr (PHYS == kElastic) {
-            using P = PhysTraits<kElastic>;
-            if constexpr (K < 3) {
-                if constexpr (K == D) {
-#pragma unroll
-                    for (int t = 0; t < NL; ++t) {
-                        r[3 + D][t] = fma(mt[t].c[3], g[t], r[3 + D][t]);
-                        r[3 + (D + 1) % 3][t] = fma(mt[t].c[1], g[t], r[3 + (D + 1) % 3][t]);
-                        r[3 + (D + 2) % 3][t] = fma(mt[t].c[1], g[t], r[3 + (D + 2) % 3][t]);
-                    }
-                } else {
-                    constexpr int q = P::sig(D, K);
-#pragma unroll
-                    for (int t = 0; t < NL; ++t) r[q][t] = fma(mt[t].c[2], g[t], r[q][t]);
-                }
-            } else {
-                constexpr int i = K - 3;
-#pragma unroll
-                for (int t = 0; t < NL; ++t) r[i][t] = fma(mt[t].c[0], g[t], r[i][t]);
-            }
         } else {
-            if constexpr (K == 0) {
-#pragma unroll
-                for (int t = 0; t < NL; ++t) r[1 + D][t] = fma(mt[t].c[1], g[t], r[1 + D][t]);
-            } else {
-#pragma unroll
-                for (int t = 0; t < NL; ++t) r[0][t] = fma(mt[t].c[0], g[t], r[0][t]);
-            }
+            ncp_cart<PHYS, D, K>(mt, g, r);
         }
     }
 

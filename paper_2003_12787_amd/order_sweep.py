@@ -1,8 +1,8 @@
 """Per-order timing of the predictor's FP32 kernels: where the matrix cores could pay.
 
 For the acoustic and elastic presets at N = 1..9 (per-node material, Q ~ N(0, 1), inputs drawn on the device),
-every kernel variant that exists for the class in FP32 I/O (plain, fused; the split-BF16x3 MFMA kernel at
-N = 7) is timed with HIP events over a batch of about 2 GB of algorithmic traffic. The algorithmic bytes
+every kernel variant that exists for the class in FP32 I/O (plain, fused; the split-BF16x3 MFMA kernels at
+N = 7..9) is timed with HIP events over a batch of about 2 GB of algorithmic traffic. The algorithmic bytes
 (inputs read once, outputs written once) and flops come from stp_class_cost. A variant that moves its bytes
 near the measured device-copy rate is bound by HBM, and faster contractions cannot shorten it; a variant well
 below it is bound by its instruction issue, and that is where the matrix cores can pay.
@@ -67,7 +67,7 @@ def main():
             dt = 0.4 / ((2 * N + 1) * 2.0)
             variants = [stp.VARIANT_PLAIN] + ([stp.VARIANT_FUSED] if N <= 7 else [])
             precs = [(stp.FP32, v) for v in variants]
-            if N == 7:
+            if N >= 7:
                 precs.append((stp.BF16X3, stp.VARIANT_MFMA))
             for prec, var in precs:
                 plan = stp.Plan(cls, prec=prec, variant=var)

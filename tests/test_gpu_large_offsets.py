@@ -116,3 +116,9 @@ def test_heterogeneous_beyond_int32_offsets(gpu):
     """Persistent bucket launches (acoustic, elastic) and an own launch (order 8) in one stp_run."""
     parts = [W.elastic_batch(3, 5, 873), W.acoustic_batch(5, 5, 874), W.elastic_batch(8, 3, 875)]
     check(dict(prec=stp.FP32), parts, gpu, True)
+
+
+@pytest.mark.parametrize("N", [8, 9])
+def test_mfma_orders_8_9_beyond_int32_offsets(gpu, N):
+    """Order 8 blocks hold an odd number of values, so misaligned placements reach every copy-out alignment."""
+    check(dict(prec=stp.BF16X3, variant=stp.VARIANT_MFMA), [W.elastic_batch(N, 5, 876 + N)], gpu, True)

@@ -189,9 +189,56 @@ def test_bf16x3_full_size_sampled():
     check(b, stp.BF16X3, variant=stp.VARIANT_MFMA, sample=spread(b.nelem, 24, 11), label="bf16x3-C3-full")
 
 
-@pytest.mark.parametrize("N", [2, 5, 8])
+@pytest.mark.parametrize("N", [2, 5])
 def test_bf16x3_plan_other_orders_use_fp32_kernels(N):
     check(W.elastic_batch(N, 40, 980 + N), stp.BF16X3, label="bf16x3-fallback")
+
+
+# Orders 8 and 9: two chained 32x32x16 products per derivative, five nodes per lane, n = 9 with a stand-in pad
+# node, and more lanes than lines (repeated lines in the last wave).
+@pytest.mark.parametrize("variant", [stp.VARIANT_AUTO, stp.VARIANT_MFMA])
+@pytest.mark.parametrize("N", [8, 9])
+def test_bf16x3_mfma_elastic_orders_8_9(N, variant):
+    check(W.elastic_batch(N, 45, 990 + N), stp.BF16X3, variant=variant, label="bf16x3-elastic-hi")
+
+
+@pytest.mark.parametrize("N", [8, 9])
+def test_bf16x3_mfma_acoustic_orders_8_9_and_favg_sum(N):
+    b = W.acoustic_batch(N, 60, 992 + N)
+    check(b, stp.BF16X3, variant=stp.VARIANT_MFMA, label="bf16x3-acoustic-hi")
+    check(b, stp.BF16X3, variant=stp.VARIANT_MFMA, favg_sum=True, label="bf16x3-acoustic-hi-favg-sum")
+
+
+@pytest.mark.parametrize("N", [8, 9])
+def test_bf16x3_mfma_smooth_plane_waves_orders_8_9(N):
+    """Smooth fields at the orders where D's rows are largest (absolute row sums grow with n)."""
+    check(W.elastic_plane_wave_batch(N, 64, 994 + N), stp.BF16X3, variant=stp.VARIANT_MFMA,
+          label="bf16x3-elastic-plane-wave-hi")
+    check(W.acoustic_plane_wave_batch(N, 64, 996 + N), stp.BF16X3, variant=stp.VARIANT_MFMA, favg_sum=True,
+          label="bf16x3-acoustic-plane-wave-hi")
+
+
+@pytest.mark.parametrize("N", [8, 9])
+def test_bf16x3_mfma_orders_8_9_per_element_material_and_dt_h(N):
+    b = W.elastic_batch(N, 33, 998 + N, per_node=False)
+    rng = np.random.default_rng(N)
+    b.h = rng.uniform(0.5, 2.0, b.nelem)
+    b.dt = b.dt * b.h * rng.uniform(0.2, 1.0, b.nelem)
+    check(b, stp.BF16X3, variant=stp.VARIANT_MFMA, label="bf16x3-per-element-hi")
+
+
+def test_bf16x3_heterogeneous_with_orders_8_9():
+    """A split-BF16x3 heterogeneous plan: orders 8 and 9 take their own MFMA launches over element lists (on
+    the side streams), beside the persistent launch of the low orders."""
+    parts = [W.elastic_batch(9, 14, 1001), W.acoustic_batch(8, 20, 1002), W.elastic_batch(3, 40, 1003),
+             W.elastic_batch(8, 11, 1004, per_node=False), W.acoustic_batch(9, 17, 1005),
+             W.acoustic_batch(4, 30, 1006)]
+    from paper_2003_12787_amd import runner
+    mb = W.interleave(parts, [runner.class_of(p) for p in parts], 1007)
+    plan = stp.Plan(mb.classes, prec=stp.BF16X3)
+    got = run_mixed(plan, mb, stp.BF16X3)
+    say(f"[parity]   worst {check_mixed(mb, stp.BF16X3, got)}")
+    plan.close()
 
 
 def test_unsupported_variant_is_reported():
