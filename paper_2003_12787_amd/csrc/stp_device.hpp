@@ -136,6 +136,22 @@ struct Material {
             c[3] = (T)((lam + 2.0 * mu) * inv_h);
         }
     }
+    // The same coefficients from FP32 arithmetic (a reciprocal within 1 ulp for 1/rho): the matrix-core kernels,
+    // whose BF16 products are accurate to about FP32, spend no FP64 instructions on them.
+    __device__ inline void load_f32(const float* par, float ih)
+    {
+        if constexpr (PHYS == kAcoustic) {
+            c[0] = -par[1] * ih;
+            c[1] = -ih * __builtin_amdgcn_rcpf(par[0]);
+            c[2] = c[3] = 0.f;
+        } else if constexpr (PHYS == kElastic) {
+            const float lam = par[1], mu = par[2];
+            c[0] = ih * __builtin_amdgcn_rcpf(par[0]);
+            c[1] = lam * ih;
+            c[2] = mu * ih;
+            c[3] = fmaf(2.f, mu, lam) * ih;
+        }
+    }
 };
 
 // Curvilinear elastic: the elastic coefficients plus the metric terms G[d][j] = h dxi_d/dx_j of the node.
@@ -150,6 +166,16 @@ struct Material<T, kElasticCurv> {
         c[1] = (T)(lam * inv_h);
         c[2] = (T)(mu * inv_h);
         c[3] = (T)((lam + 2.0 * mu) * inv_h);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) G[k] = par[3 + k];
+    }
+    __device__ inline void load_f32(const T* par, float ih)
+    {
+        const float lam = par[1], mu = par[2];
+        c[0] = ih * __builtin_amdgcn_rcpf(par[0]);
+        c[1] = lam * ih;
+        c[2] = mu * ih;
+        c[3] = fmaf(2.f, mu, lam) * ih;
 #pragma unroll
         for (int k = 0; k < 9; ++k) G[k] = par[3 + k];
     }

@@ -607,10 +607,10 @@ struct Mfma8 {
             Material<float, PHYS> mt[NL];
             load2(static_cast<const float*>(a.Q) + er.q + node0 * M, (er.q & 1) == 0, p);
             {
-                const double inv_h = 1.0 / er.h;
+                const float ih = (float)(1.0 / er.h);
                 const float* par = static_cast<const float*>(a.params) + er.coef;
 #pragma unroll
-                for (int t = 0; t < NL; ++t) mt[t].load(per_elem ? par : par + (node0 + t) * NP, inv_h);
+                for (int t = 0; t < NL; ++t) mt[t].load_f32(per_elem ? par : par + (node0 + t) * NP, ih);
             }
             const float* gp = static_cast<const float*>(a.params) + er.coef + (per_elem ? 0 : node0 * NP);
             const int gs = per_elem ? 0 : NP;
@@ -653,8 +653,11 @@ struct Mfma8 {
                 for (int s = 0; s < M; ++s)
 #pragma unroll
                     for (int t = 0; t < NL; ++t) qb[s][t] = fma(w, p[s][t], qb[s][t]);
-                __syncthreads();
+                // No barrier here: the next step writes the tile after every lane has passed the barrier that
+                // precedes this step's last gather (the tile's last reads come before it), and the exchange
+                // buffer after the barrier that follows its own tile writes.
             }
+            __syncthreads();  // the last gather's reads of the exchange buffer, which stages the outputs
 
             // outputs. The output blocks are staged in the exchange buffer, so each staging round starts
             // after every lane's last read of the buffer (a barrier) and ends with one (inside store_block).

@@ -114,14 +114,31 @@ struct MfmaHi {
     // fourth node through every step. Only the stores and the face sums (zero face weights) leave it out. This
     // keeps the loop free of per-lane predication.
     __device__ static inline bool valid(const Lane& L, int t) { return !kPad || t < NL - 1 || L.v4; }
+    //
+    // A pass takes the byte addresses of the lane's five nodes in one pattern, from `region` on, as five separate
+    // registers made opaque to the compiler. Every access is then one of these plus a slot offset that fits the
+    // instruction's 16-bit offset field (each region plus its slots stays under 64 KB), and no two accesses share
+    // a register, so none is merged into a two-address instruction that would need a new base (a VALU add) for
+    // each slot.
     struct Pat {
-        unsigned b, b4;  // byte address of the lane's node 0 and of its fifth node (or its stand-in)
+        unsigned b[NL];
     };
-    __device__ static inline Pat pat(unsigned base, unsigned st, bool v4)
+    // Only the elastic tile of n = 10 (74 KB, 18 slots) pays for five address registers; the smaller tiles keep
+    // one opaque base per pass, whose few merged pairs cost fewer adds than the registers cost occupancy.
+    static constexpr bool kNodeRegs = PHYS == kElastic && n == 10;
+    __device__ static inline Pat pat(unsigned base, unsigned st, bool v4, unsigned region)
     {
-        return {base, base + (!kPad || v4 ? 4u * st : 3u * st)};
+        Pat P;
+        if constexpr (!kNodeRegs) base += (unsigned)opaque_zero();
+#pragma unroll
+        for (int t = 0; t < NL - 1; ++t) P.b[t] = base + region + st * t;
+        P.b[NL - 1] = base + region + (!kPad || v4 ? 4u * st : 3u * st);
+        if constexpr (kNodeRegs) asm volatile("" : "+v"(P.b[0]), "+v"(P.b[1]), "+v"(P.b[2]), "+v"(P.b[3]), "+v"(P.b[4]));
+        return P;
     }
-    __device__ static inline unsigned at(const Pat& P, unsigned st, int t) { return t < NL - 1 ? P.b + st * t : P.b4; }
+    static constexpr unsigned kTile = 4 * HM_OFF, kExch = 4 * G_OFF;  // region byte offsets
+    static_assert(4 * (LO_OFF + NLP * SLOT) <= 65536 && 4 * NG * SLOT <= 65536 && 4 * M * SLOT <= 65536,
+                  "slot offsets fit the 16-bit LDS offset field");
 
     __device__ static inline Lane lane_setup(const uint16_t* tab, int wv, int l)
     {
@@ -166,7 +183,7 @@ struct MfmaHi {
                 const Split5 sp = split5(v[Q], lo_bits);
 #pragma unroll
                 for (int t = 0; t < NL; ++t)
-                    lds<unsigned>(smem, at(P, SO, t) + 4 * (HM_OFF + s * SLOT)) = sp.hm[t];
+                    lds<unsigned>(smem, P.b[t] + 4 * (s * SLOT)) = sp.hm[t];
                 constexpr bool last = (lp & 1) == 1 || I + 1 >= M || K8::lo_pair(K8::qord(I + 1)) != lp + 1;
                 if constexpr (!last) {
 #pragma unroll
@@ -177,7 +194,7 @@ struct MfmaHi {
                         // (lo of the pair's first quantity | lo of the second), or the lone lo in the low half
                         const unsigned w = (lp & 1) ? __builtin_amdgcn_perm(lo_bits[t], pend[t], 0x07060302u)
                                                     : (lo_bits[t] >> 16);
-                        lds<unsigned>(smem, at(P, SO, t) + 4 * (LO_OFF + (lp >> 1) * SLOT)) = w;
+                        lds<unsigned>(smem, P.b[t] + 4 * (LO_OFF + (lp >> 1) * SLOT)) = w;
                     }
                 }
             }
@@ -205,15 +222,15 @@ struct MfmaHi {
     // The split of the lane's values of quantity q at its nodes along its line in the pattern (P, ST), read
     // from the tile. `lw` holds the lo words of q's pair, read unless `reuse` (the pair's other quantity was read
     // just before).
-    __device__ static inline Split5 read_split(unsigned char* smem, const Pat& P, unsigned ST, int q, bool reuse,
+    __device__ static inline Split5 read_split(unsigned char* smem, const Pat& P, int q, bool reuse,
                                                unsigned (&lw)[NL])
     {
         const int s = S::slot(q), lp = K8::lo_pair(q);
         Split5 sp;
 #pragma unroll
         for (int t = 0; t < NL; ++t) {
-            sp.hm[t] = lds<unsigned>(smem, at(P, ST, t) + 4 * (HM_OFF + s * SLOT));
-            if (!reuse) lw[t] = lds<unsigned>(smem, at(P, ST, t) + 4 * (LO_OFF + (lp >> 1) * SLOT));
+            sp.hm[t] = lds<unsigned>(smem, P.b[t] + 4 * (s * SLOT));
+            if (!reuse) lw[t] = lds<unsigned>(smem, P.b[t] + 4 * (LO_OFF + (lp >> 1) * SLOT));
         }
         // the quantity's half of the lo words, packed by node pairs
         const unsigned sel = (lp & 1) ? 0x07060302u : 0x05040100u;
@@ -230,7 +247,7 @@ struct MfmaHi {
                                              const Material<float, PHYS> (&mt)[NL], float (&r)[R][NL])
     {
         unsigned lw[NL] = {0u, 0u, 0u, 0u, 0u};
-        xpass_tile_q<0>(A, smem, pat(L.bo + (unsigned)opaque_zero(), SO, L.v4), mt, r, lw);
+        xpass_tile_q<0>(A, smem, pat(L.bo, SO, L.v4, kTile), mt, r, lw);
     }
     template <int I, int R>
     __device__ static inline void xpass_tile_q(const bf16x8 (&A)[2], unsigned char* smem, const Pat& P,
@@ -243,7 +260,7 @@ struct MfmaHi {
                 constexpr int lp = K8::lo_pair(q);
                 constexpr bool reuse = I > 0 && (lp & 1) == 1 && S::slot(S::dq(0, K8::kord(0, I - 1))) >= 0 &&
                                        K8::lo_pair(S::dq(0, K8::kord(0, I - 1))) == lp - 1;
-                const Split5 sp = read_split(smem, P, SO, q, reuse, lw);
+                const Split5 sp = read_split(smem, P, q, reuse, lw);
                 float g[NL];
                 deriv_mfma32(A, sp, g);
                 ncp_cart<PHYS, 0, K8::kord(0, I)>(mt, g, r);
@@ -260,7 +277,7 @@ struct MfmaHi {
                                               float (&r)[R][NL])
     {
         unsigned pend[NL] = {0u, 0u, 0u, 0u, 0u};
-        split_q<0>(smem, pat(L.bo + (unsigned)opaque_zero(), SO, L.v4), v, pend);
+        split_q<0>(smem, pat(L.bo, SO, L.v4, kTile), v, pend);
         xpass_reg<0>(A, mt, v, r);
         xpass_tile(A, smem, L, mt, r);
     }
@@ -272,19 +289,20 @@ struct MfmaHi {
     __device__ static inline void transposed(const bf16x8 (&A)[2], unsigned char* smem, const Lane& L)
     {
         constexpr unsigned ST = D == 1 ? SY : SZ;
-        const Pat P = pat((D == 1 ? L.by : L.bz) + (unsigned)opaque_zero(), ST, L.v4);
+        const unsigned base = D == 1 ? L.by : L.bz;
+        const Pat P = pat(base, ST, L.v4, kTile), PG = pat(base, ST, L.v4, kExch);
         unsigned lw[NL] = {0u, 0u, 0u, 0u, 0u};
 #pragma unroll
         for (int i = 0; i < NG; ++i) {
             const int q = S::dq(D, K8::kord(D, i));
             const int lp = K8::lo_pair(q);
             const bool reuse = i > 0 && (lp & 1) == 1 && K8::lo_pair(S::dq(D, K8::kord(D, i - 1))) == lp - 1;
-            const Split5 sp = read_split(smem, P, ST, q, reuse, lw);
+            const Split5 sp = read_split(smem, P, q, reuse, lw);
             float g[NL];
             deriv_mfma32(A, sp, g);
 #pragma unroll
             for (int t = 0; t < NL; ++t)
-                lds<float>(smem, at(P, ST, t) + 4 * (G_OFF + i * SLOT)) = g[t];
+                lds<float>(smem, PG.b[t] + 4 * (i * SLOT)) = g[t];
         }
     }
 
@@ -293,7 +311,7 @@ struct MfmaHi {
     __device__ static inline void gather(unsigned char* smem, const Lane& L, const Material<float, PHYS> (&mt)[NL],
                                          float (&r)[R][NL])
     {
-        gather_q<D, 0>(smem, pat(L.bo + (unsigned)opaque_zero(), SO, L.v4), mt, r);
+        gather_q<D, 0>(smem, pat(L.bo, SO, L.v4, kExch), mt, r);
     }
     template <int D, int I, int R>
     __device__ static inline void gather_q(unsigned char* smem, const Pat& P, const Material<float, PHYS> (&mt)[NL],
@@ -302,7 +320,7 @@ struct MfmaHi {
         if constexpr (I < NG) {
             float g[NL];
 #pragma unroll
-            for (int t = 0; t < NL; ++t) g[t] = lds<float>(smem, at(P, SO, t) + 4 * (G_OFF + I * SLOT));
+            for (int t = 0; t < NL; ++t) g[t] = lds<float>(smem, P.b[t] + 4 * (I * SLOT));
             ncp_cart<PHYS, D, K8::kord(D, I)>(mt, g, r);
             gather_q<D, I + 1>(smem, P, mt, r);
         }
@@ -395,14 +413,14 @@ struct MfmaHi {
             Material<float, PHYS> mt[NL];
             {
                 const float* q = static_cast<const float*>(a.Q) + er.q + node0 * M;
-                const double inv_h = 1.0 / er.h;
+                const float ih = (float)(1.0 / er.h);
                 const float* par = static_cast<const float*>(a.params) + er.coef;
 #pragma unroll
                 for (int t = 0; t < NL; ++t) {
                     const int x = t < NL - 1 || valid(L, t) ? t : t - 1;  // the pad loads the fourth node
 #pragma unroll
                     for (int s = 0; s < M; ++s) p[s][t] = q[x * M + s];
-                    mt[t].load(per_elem ? par : par + (node0 + x) * NP, inv_h);
+                    mt[t].load_f32(per_elem ? par : par + (node0 + x) * NP, ih);
                 }
             }
 #pragma unroll
@@ -488,11 +506,11 @@ struct MfmaHi {
                 e0[t] = valid(L, t) ? ld<float>(a.e0, NL * L.h + t) : 0.f;
                 e1[t] = valid(L, t) ? ld<float>(a.e1, NL * L.h + t) : 0.f;
             }
-            const Pat Po = pat(L.bo, SO, L.v4), Py = pat(L.by, SY, L.v4), Pz = pat(L.bz, SZ, L.v4);
+            const Pat Po = pat(L.bo, SO, L.v4, 0), Py = pat(L.by, SY, L.v4, 0), Pz = pat(L.bz, SZ, L.v4, 0);
 #pragma unroll
             for (int s = 0; s < M; ++s)
 #pragma unroll
-                for (int t = 0; t < NL; ++t) lds<float>(smem, at(Po, SO, t) + 4 * s * SLOT) = qb[s][t];
+                for (int t = 0; t < NL; ++t) lds<float>(smem, Po.b[t] + 4 * s * SLOT) = qb[s][t];
             faces_dir<0>(F, qb, e0, e1, L.lo, L.h, L.dup_o);
             __syncthreads();
             {
@@ -501,13 +519,13 @@ struct MfmaHi {
                 for (int s = 0; s < M; ++s)
 #pragma unroll
                     for (int t = 0; t < NL; ++t)
-                        u[s][t] = lds<float>(smem, at(Py, SY, t) + 4 * s * SLOT);
+                        u[s][t] = lds<float>(smem, Py.b[t] + 4 * s * SLOT);
                 faces_dir<1>(F, u, e0, e1, L.ly, L.h, L.dup_y);
 #pragma unroll
                 for (int s = 0; s < M; ++s)
 #pragma unroll
                     for (int t = 0; t < NL; ++t)
-                        u[s][t] = lds<float>(smem, at(Pz, SZ, t) + 4 * s * SLOT);
+                        u[s][t] = lds<float>(smem, Pz.b[t] + 4 * s * SLOT);
                 faces_dir<2>(F, u, e0, e1, L.lz, L.h, L.dup_z);
             }
             __syncthreads();
@@ -518,8 +536,10 @@ struct MfmaHi {
     }
 };
 
+// At least two waves per SIMD: two elastic workgroups share a CU (the LDS bound).
 template <int PHYS, int NORD>
-__global__ void __launch_bounds__(64 * mfma_hi::waves(NORD + 1)) stp_mfma_hi_kernel(StpArgs a)
+__global__ void __launch_bounds__(64 * mfma_hi::waves(NORD + 1)) __attribute__((amdgpu_waves_per_eu(2)))
+stp_mfma_hi_kernel(StpArgs a)
 {
     MfmaHi<PHYS, NORD>::run(a);
 }
