@@ -484,9 +484,10 @@ def test_heterogeneous_graph_capture_replays_with_side_streams():
 def test_uniform_graph_capture_replays():
     import torch
     from paper_2003_12787_amd import runner
-    b = W.c3_elastic_n7(2048)
-    for prec, variant in ((stp.FP32, stp.VARIANT_FUSED), (stp.BF16X3, stp.VARIANT_MFMA)):
-        say(f"[graph] C3-shaped E=2048 prec={prec} variant={variant}")
+    for b, prec, variant in ((W.c3_elastic_n7(2048), stp.FP32, stp.VARIANT_FUSED),
+                             (W.c3_elastic_n7(2048), stp.BF16X3, stp.VARIANT_MFMA),
+                             (W.elastic_batch(9, 300, 1010), stp.BF16X3, stp.VARIANT_MFMA)):
+        say(f"[graph] N={b.N} E={b.nelem} prec={prec} variant={variant}")
         plan = stp.Plan([runner.class_of(b)], prec=prec, variant=variant)
         db = runner.DeviceBatch(plan, b)
         plan.run(db.cbatch)
