@@ -128,10 +128,11 @@ struct Mfma8 {
     static constexpr int NP = PhysTraits<PHYS>::np;
     using S = fused::Sets<PHYS>;
     static constexpr int NPS = S::NPS, NG = S::NG;
-    // Exchange-buffer slots: the derivatives of one direction come back in chunks of NGX quantities (all of
-    // them at once for the Cartesian presets; 5 + 4 for curvilinear elements, which differentiate all 9
-    // quantities in every direction) so that four elements per CU fit in LDS.
-    static constexpr int NGX = NG <= 6 ? NG : 5;
+    // Exchange-buffer slots: the derivatives of one direction come back in chunks of NGX quantities. All of
+    // them come back at once: curvilinear elements differentiate all 9 quantities in every direction, and their
+    // 143 registers hold three elements per CU, whose 47 KB of LDS each fit (two chunks would save LDS that
+    // cannot host a fourth element, at two more barriers per direction). The chunked path stays for NGX < NG.
+    static constexpr int NGX = NG;
     static constexpr int C1 = NGX;  // end of the first chunk
     static constexpr int SLOT = n3;  // one quantity's tile, swizzled (at())
     // Quantity pairs of the tile's lo words: each 32-bit word holds the lo pieces of two quantities at one node,
