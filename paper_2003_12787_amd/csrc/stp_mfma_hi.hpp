@@ -114,17 +114,16 @@ struct MfmaHi {
     // fourth node through every step. Only the stores and the face sums (zero face weights) leave it out. This
     // keeps the loop free of per-lane predication.
     __device__ static inline bool valid(const Lane& L, int t) { return !kPad || t < NL - 1 || L.v4; }
-    //
-    // A pass takes the byte addresses of the lane's five nodes in one pattern, from `region` on, as five separate
-    // registers made opaque to the compiler. Every access is then one of these plus a slot offset that fits the
-    // instruction's 16-bit offset field (each region plus its slots stays under 64 KB), and no two accesses share
-    // a register, so none is merged into a two-address instruction that would need a new base (a VALU add) for
-    // each slot.
+
+    // A pass takes the byte addresses of the lane's five nodes in one pattern, from `region` on. Every access is
+    // one of these plus a slot offset that fits the instruction's 16-bit offset field (each region plus its
+    // slots stays under 64 KB). For the elastic tile of n = 10 (74 KB, 18 slots) the five addresses are separate
+    // registers made opaque to the compiler, so no two accesses share a register and none is merged into a
+    // two-address instruction that would need a new base (a VALU add) for each slot. The smaller tiles keep one
+    // opaque base per pass, whose few merged pairs cost fewer adds than five registers cost occupancy.
     struct Pat {
         unsigned b[NL];
     };
-    // Only the elastic tile of n = 10 (74 KB, 18 slots) pays for five address registers; the smaller tiles keep
-    // one opaque base per pass, whose few merged pairs cost fewer adds than the registers cost occupancy.
     static constexpr bool kNodeRegs = PHYS == kElastic && n == 10;
     __device__ static inline Pat pat(unsigned base, unsigned st, bool v4, unsigned region)
     {
@@ -498,7 +497,6 @@ struct MfmaHi {
             // faces: the x-faces from the registers, the y- and z-faces from an FP32 q-bar tile; staged in LDS
             // in the output layout [f][a][b][s] and copied out with 16-byte stores
             float* qf = static_cast<float*>(a.qface) + er.face;
-            float* PF = smf;
             float* F = smf + FACE_OFF + (int)(((uintptr_t)qf >> 2) & 3u);
             float e0[NL], e1[NL];
 #pragma unroll
@@ -531,7 +529,6 @@ struct MfmaHi {
             __syncthreads();
             copy_out(F, qf, 6 * n2 * M, tid);
             __syncthreads();
-            (void)PF;
         }
     }
 };
