@@ -563,6 +563,7 @@ def main():
         "fp32_plain": (stp.FP32, stp.VARIANT_PLAIN),
         "fp32_fused": (stp.FP32, stp.VARIANT_FUSED),
         "bf16x3_mfma": (stp.BF16X3, stp.VARIANT_MFMA),
+        "fp32_mfma": (stp.FP32, stp.VARIANT_MFMA),
     }
     for name in variants:
         prec, var = specs[name]

@@ -33,6 +33,7 @@ CFLAGS = [
 EXTRA = {
     "stp_mfma_n7.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
     "stp_mfma_n89.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+    "stp_mfma_f32_n7.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
 }
 
 

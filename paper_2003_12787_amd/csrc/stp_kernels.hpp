@@ -37,6 +37,8 @@ KernelInfo fused_kernel_f32(int N, int physics);
 KernelInfo mfma_kernel_n7(int physics);
 KernelInfo mfma_kernel_n89(int N, int physics);
 inline KernelInfo mfma_kernel(int N, int physics) { return N == 7 ? mfma_kernel_n7(physics) : mfma_kernel_n89(N, physics); }
+// FP32 MFMA kernel (FP32 I/O and arithmetic): Cartesian presets at N = 7.
+KernelInfo mfma32_kernel_n7(int physics);
 
 // Heterogeneous persistent kernel of one physics bucket (FP32 I/O, orders 1..7, 512 threads per workgroup).
 struct HeteroKernel {

@@ -168,7 +168,14 @@ Eligibility eligible(const stp_plan_s* p, const ClassState& cs)
     const bool simple = f32io && !cs.acc64 && !(cs.cls.flags & STP_SRC_POINT);
     const int N = cs.cls.order;
     return {simple && cart && N <= 7,
-            simple && p->prec == STP_BF16X3 && ((N == 7 && (cart || curv)) || ((N == 8 || N == 9) && cart))};
+            simple && ((p->prec == STP_BF16X3 && ((N == 7 && (cart || curv)) || ((N == 8 || N == 9) && cart))) ||
+                       (p->prec == STP_FP32 && N == 7 && cart))};
+}
+
+// the matrix-core kernel of the plan's precision: FP32 products, or split-BF16 products with FP32 accumulation
+KernelInfo mfma_for(const stp_plan_s* p, const ClassState& cs)
+{
+    return p->prec == STP_FP32 ? mfma32_kernel_n7(cs.cls.physics) : mfma_kernel(cs.cls.order, cs.cls.physics);
 }
 
 }  // namespace
@@ -180,7 +187,7 @@ std::vector<std::pair<int, KernelInfo>> kernel_candidates(stp_plan_s* p, const C
     v.push_back({STP_VARIANT_PLAIN,
                  plain_kernel(p->prec == STP_FP64, cs.acc64, cs.cls.order, cs.cls.physics, cs.cls.nquant)});
     if (el.fused) v.push_back({STP_VARIANT_FUSED, fused_kernel_f32(cs.cls.order, cs.cls.physics)});
-    if (el.mfma) v.push_back({STP_VARIANT_MFMA, mfma_kernel(cs.cls.order, cs.cls.physics)});
+    if (el.mfma) v.push_back({STP_VARIANT_MFMA, mfma_for(p, cs)});
     return v;
 }
 
@@ -189,8 +196,8 @@ KernelInfo select_kernel(stp_plan_s* p, const ClassState& cs, int* variant)
     const Eligibility el = eligible(p, cs);
     const KernelInfo plain = plain_kernel(p->prec == STP_FP64, cs.acc64, cs.cls.order, cs.cls.physics, cs.cls.nquant);
     int v = p->variant;
-    if (v == STP_VARIANT_AUTO)  // built-in rule: matrix cores where a kernel exists, else fused, else plain
-        v = el.mfma ? STP_VARIANT_MFMA : (el.fused ? STP_VARIANT_FUSED : STP_VARIANT_PLAIN);
+    if (v == STP_VARIANT_AUTO)  // built-in rule: split-BF16 matrix cores where a kernel exists, else fused, else plain
+        v = el.mfma && p->prec == STP_BF16X3 ? STP_VARIANT_MFMA : (el.fused ? STP_VARIANT_FUSED : STP_VARIANT_PLAIN);
     if (variant) *variant = v;
     switch (v) {
     case STP_VARIANT_PLAIN:
@@ -198,7 +205,7 @@ KernelInfo select_kernel(stp_plan_s* p, const ClassState& cs, int* variant)
     case STP_VARIANT_FUSED:
         return el.fused ? fused_kernel_f32(cs.cls.order, cs.cls.physics) : KernelInfo{};
     case STP_VARIANT_MFMA:
-        return el.mfma ? mfma_kernel(cs.cls.order, cs.cls.physics) : KernelInfo{};
+        return el.mfma ? mfma_for(p, cs) : KernelInfo{};
     default:
         return KernelInfo{};
     }

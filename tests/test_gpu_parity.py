@@ -189,6 +189,40 @@ def test_bf16x3_full_size_sampled():
     check(b, stp.BF16X3, variant=stp.VARIANT_MFMA, sample=spread(b.nelem, 24, 11), label="bf16x3-C3-full")
 
 
+# FP32 matrix-core kernel (order 7, Cartesian presets): FP32 products and accumulation, FP32 tolerance
+def test_fp32_mfma_elastic_n7():
+    check(W.c3_elastic_n7(nelem=300), stp.FP32, variant=stp.VARIANT_MFMA, label="fp32-mfma-C3-small")
+
+
+def test_fp32_mfma_acoustic_n7_and_favg_sum():
+    check(W.acoustic_batch(7, 150, 975), stp.FP32, variant=stp.VARIANT_MFMA, label="fp32-mfma-acoustic")
+    check(W.acoustic_batch(7, 150, 975), stp.FP32, variant=stp.VARIANT_MFMA, favg_sum=True,
+          label="fp32-mfma-acoustic-favg-sum")
+    check(W.elastic_batch(7, 60, 976), stp.FP32, variant=stp.VARIANT_MFMA, favg_sum=True,
+          label="fp32-mfma-elastic-favg-sum")
+
+
+def test_fp32_mfma_smooth_plane_waves():
+    """Smooth fields, where favg is a derivative of a nearly constant q-bar: per-direction and summed favg."""
+    check(W.acoustic_plane_wave_batch(7, 125, 977), stp.FP32, variant=stp.VARIANT_MFMA, favg_sum=True,
+          label="fp32-mfma-acoustic-plane-wave")
+    check(W.elastic_plane_wave_batch(7, 216, 978), stp.FP32, variant=stp.VARIANT_MFMA,
+          label="fp32-mfma-elastic-plane-wave")
+
+
+def test_fp32_mfma_per_element_material_and_dt_h():
+    b = W.elastic_batch(7, 77, 979, per_node=False)
+    rng = np.random.default_rng(12)
+    b.h = rng.uniform(0.5, 2.0, b.nelem)
+    b.dt = b.dt * b.h * rng.uniform(0.2, 1.0, b.nelem)
+    check(b, stp.FP32, variant=stp.VARIANT_MFMA, label="fp32-mfma-per-element")
+
+
+def test_fp32_mfma_full_size_sampled():
+    b = W.c3_elastic_n7()
+    check(b, stp.FP32, variant=stp.VARIANT_MFMA, sample=spread(b.nelem, 24, 13), label="fp32-mfma-C3-full")
+
+
 @pytest.mark.parametrize("N", [2, 5])
 def test_bf16x3_plan_other_orders_use_fp32_kernels(N):
     check(W.elastic_batch(N, 40, 980 + N), stp.BF16X3, label="bf16x3-fallback")
