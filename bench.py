@@ -27,6 +27,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 # FP32 without packed instructions runs at the FP64 rate (packed FP32 is not used by this build).
 ALU_PEAK_TFS = {"f64": 78.6, "f32": 78.6}
 MFMA_BF16_PEAK_TFS = 2500.0    # dense BF16 matrix-core peak
+MFMA_F32_PEAK_TFS = 157.3      # dense FP32 matrix-core peak
 
 
 def log(*a):
@@ -44,7 +45,7 @@ def parse():
     ap.add_argument("--copy-gib", type=float, default=1.0,
                     help="size of the device-to-device copy timed as the measured HBM reference (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--variants", default="fp64_plain,fp32_plain,fp32_fused,bf16x3_mfma")
+    ap.add_argument("--variants", default="fp64_plain,fp32_plain,fp32_fused,bf16x3_mfma,fp32_mfma")
     ap.add_argument("--no-hetero", action="store_true", help="skip the heterogeneous 16384-element batch")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop latency measurement")
     ap.add_argument("--serve-batches", type=int, default=10000, help="measured batches per arrival rate")
@@ -187,12 +188,13 @@ def cpu_description(threads):
 
 def bench_lobatto(args, torch, stp, runner, b, ids):
     """The benchmark workload on Gauss-Lobatto nodes (the other node family of Sec. II-A): the split-BF16x3
-    MFMA and FP32 fused kernels with the plan's Lobatto tables. Returns timings and sampled outputs of the
-    elements `ids` for the CPU leg."""
+    MFMA, FP32 MFMA and FP32 fused kernels with the plan's Lobatto tables. Returns timings and sampled outputs of
+    the elements `ids` for the CPU leg."""
     E = b.nelem
     res = {"workload": "elastic N=7 benchmark workload on Gauss-Lobatto nodes (same inputs)"}
     tid = torch.from_numpy(ids).cuda()
-    for name, prec, var in (("bf16x3_mfma", stp.BF16X3, stp.VARIANT_MFMA), ("fp32_fused", stp.FP32, stp.VARIANT_FUSED)):
+    for name, prec, var in (("bf16x3_mfma", stp.BF16X3, stp.VARIANT_MFMA), ("fp32_mfma", stp.FP32, stp.VARIANT_MFMA),
+                            ("fp32_fused", stp.FP32, stp.VARIANT_FUSED)):
         plan = stp.Plan([runner.class_of(b)], prec=prec, variant=var, nodes=stp.GAUSS_LOBATTO)
         db = runner.DeviceBatch(plan, b)
         ms = float(np.median(time_launches(lambda st: plan.run(db.cbatch, st), args.steps, args.warmup,
@@ -594,13 +596,16 @@ def main():
     # by the elastic B_d), N+1 applications; on the split-BF16x3 variant they run on the matrix cores: one
     # 16x16x32 BF16 product per 16 lines of 8 nodes, 8 times the contraction's multiply-adds (the six split
     # products, two output rows per node, the other line group's zero blocks), at the dense BF16 peak; the
-    # rest of its flops run on the VALU.
+    # rest of its flops run on the VALU. The FP32 MFMA variant forms exactly the contraction's products on the
+    # matrix cores (4x4 blocks of the lanes' own lines, nothing wasted) at the dense FP32 matrix peak.
     valu = "f64" if h["dtype"] == "f64" else "f32"  # the VALU type of the non-contraction work
     n = b.N + 1
     contr = (b.N + 1) * 3 * 2 * n * n ** 3 * 6
     t_hbm = h["bytes_per_element"] / (HBM_PEAK_GBS * 1e9)
     if head == "bf16x3_mfma":
         t_cmp = 8 * contr / (MFMA_BF16_PEAK_TFS * 1e12) + (h["flops_per_element"] - contr) / (ALU_PEAK_TFS["f32"] * 1e12)
+    elif head == "fp32_mfma":
+        t_cmp = contr / (MFMA_F32_PEAK_TFS * 1e12) + (h["flops_per_element"] - contr) / (ALU_PEAK_TFS["f32"] * 1e12)
     else:
         t_cmp = h["flops_per_element"] / (ALU_PEAK_TFS[valu] * 1e12)
     if t_hbm >= t_cmp:
@@ -663,7 +668,7 @@ def main():
         if lobatto is not None:  # sampled parity on Gauss-Lobatto nodes
             ref = oracle.stp(b.N, b.physics, b.Q[lob_ids], b.dt[lob_ids], b.h[lob_ids], params=b.params[lob_ids],
                              nthreads=threads, nodes=1)
-            for name in ("bf16x3_mfma", "fp32_fused"):
+            for name in ("bf16x3_mfma", "fp32_mfma", "fp32_fused"):
                 got = lobatto[name]["sampled"]
                 errs = {}
                 for key in ("qavg", "favg", "qface"):

@@ -47,11 +47,12 @@
  *                 matrices and G[d][j] = h dxi_d/dx_j the metric terms (the inverse Jacobian of the map
  *                 scaled by the element size h; an undeformed cube of side h has G = I).
  *
- * Precision: STP_FP64 computes and stores in double. STP_FP32 and STP_BF16X3 read and write float; their
- * derivative contractions run in FP32 (VALU) or on the matrix cores with the operands split into three BF16
- * pieces each (D = D0 + D1 + D2 and u = hi + mid + lo; at N = 7 the six products of order up to 2^-16 are
- * formed, at N = 8, 9 all nine) and FP32 accumulation (MFMA; about FP32 accuracy). An STP_BF16X3 class without
- * an MFMA kernel (orders below 7, FP64 accumulation, point sources, generic physics) runs the FP32 kernels.
+ * Precision: STP_FP64 computes and stores in double. STP_FP32 and STP_BF16X3 read and write float. STP_FP32
+ * forms its derivative contractions in FP32, on the VALU or (acoustic and elastic presets at N = 7) as FP32
+ * matrix-core products. STP_BF16X3 forms them on the matrix cores with the operands split into three BF16 pieces
+ * each (D = D0 + D1 + D2 and u = hi + mid + lo; at N = 7 the six products of order up to 2^-16 are formed, at
+ * N = 8, 9 all nine) and FP32 accumulation (about FP32 accuracy). An STP_BF16X3 class without such a kernel
+ * (orders below 7, FP64 accumulation, point sources, generic physics) runs the FP32 kernels.
  * Classes whose order is >= acc64_min_order (when > 0) accumulate qavg and the face extrapolation in FP64.
  *
  * Ownership: the caller owns every buffer and passes raw pointers; device pointers must be device memory
@@ -139,9 +140,11 @@ enum {
     STP_VARIANT_PLAIN = 1,   /* one element per workgroup, one thread per node, LDS-staged             */
     STP_VARIANT_FUSED = 2,   /* register-blocked lines, LDS transposes (acoustic and elastic presets,
                                 FP32 I/O without FP64 accumulation or point source, N <= 7)            */
-    STP_VARIANT_MFMA = 3     /* split-BF16x3 MFMA contractions with FP32 accumulation (STP_BF16X3,
-                                without FP64 accumulation or point source: acoustic, elastic and
-                                curvilinear elastic presets at N = 7; acoustic and elastic at N = 8, 9) */
+    STP_VARIANT_MFMA = 3     /* matrix-core contractions, without FP64 accumulation or point source:
+                                STP_FP32 FP32 products (acoustic and elastic presets at N = 7);
+                                STP_BF16X3 split-BF16x3 products with FP32 accumulation (acoustic,
+                                elastic and curvilinear elastic presets at N = 7; acoustic and elastic
+                                at N = 8, 9). The library's choice where such a kernel exists.         */
 };
 
 typedef struct {

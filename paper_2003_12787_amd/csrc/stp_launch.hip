@@ -160,8 +160,9 @@ struct Eligibility {
 
 Eligibility eligible(const stp_plan_s* p, const ClassState& cs)
 {
-    // the fused kernel implements the Cartesian presets up to order 7; the MFMA kernels the Cartesian presets at
-    // orders 7 to 9 and curvilinear elastic elements at order 7
+    // the fused kernel implements the Cartesian presets up to order 7; the split-BF16 MFMA kernels the Cartesian
+    // presets at orders 7 to 9 and curvilinear elastic elements at order 7; the FP32 MFMA kernel the Cartesian
+    // presets at order 7
     const bool cart = cs.cls.physics == STP_ACOUSTIC || cs.cls.physics == STP_ELASTIC;
     const bool curv = cs.cls.physics == STP_ELASTIC_CURV;
     const bool f32io = p->prec != STP_FP64;
@@ -196,8 +197,8 @@ KernelInfo select_kernel(stp_plan_s* p, const ClassState& cs, int* variant)
     const Eligibility el = eligible(p, cs);
     const KernelInfo plain = plain_kernel(p->prec == STP_FP64, cs.acc64, cs.cls.order, cs.cls.physics, cs.cls.nquant);
     int v = p->variant;
-    if (v == STP_VARIANT_AUTO)  // built-in rule: split-BF16 matrix cores where a kernel exists, else fused, else plain
-        v = el.mfma && p->prec == STP_BF16X3 ? STP_VARIANT_MFMA : (el.fused ? STP_VARIANT_FUSED : STP_VARIANT_PLAIN);
+    if (v == STP_VARIANT_AUTO)  // built-in rule: matrix cores where a kernel exists, else fused, else plain
+        v = el.mfma ? STP_VARIANT_MFMA : (el.fused ? STP_VARIANT_FUSED : STP_VARIANT_PLAIN);
     if (variant) *variant = v;
     switch (v) {
     case STP_VARIANT_PLAIN:

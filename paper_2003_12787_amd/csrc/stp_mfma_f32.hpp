@@ -46,6 +46,15 @@ __device__ inline float mirror(float v)
                                                                  false));
 }
 
+// Orders a wave's LDS accesses before and after this point against each other (the LDS executes a wave's
+// accesses in order; this keeps the compiler from moving them across).
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // D u at the lane's four nodes 4h .. 4h + 3 of its line, from u at the same nodes (A as above).
 __device__ inline void deriv4(const float (&A)[2][4], const float (&u)[4], float (&out)[4])
 {
@@ -70,22 +79,50 @@ struct MfmaF {
     using S = fused::Sets<PHYS>;
     static constexpr int NPS = S::NPS, NG = S::NG;
     static constexpr int SLOT = n3;  // one quantity's tile, swizzled (at())
-    // LDS (floats): the tile of the quantities differentiated along y or z, then the exchange buffers of the y-
-    // and of the z-derivatives (both directions are differentiated in one phase between two barriers). Outputs
-    // are staged over them (one output block: 64 lines padded by 4 floats), and the face pass holds an FP32 q-bar
-    // tile of all quantities followed by the face values. The elastic kernel's 40 KB hold four elements per CU,
-    // as many as its registers allow.
-    static constexpr int P_OFF = 0, GY_OFF = NPS * SLOT, GZ_OFF = GY_OFF + NG * SLOT;
-    static constexpr int ELDS = GZ_OFF + NG * SLOT;
-    static constexpr int g_off(int D) { return D == 1 ? GY_OFF : GZ_OFF; }
+    // The y- and z-derivatives are formed in one phase between two barriers. A quantity that only one of the two
+    // directions differentiates gets its derivative written over its own tile values: the lanes of a wave read
+    // those nodes before they write them, and no other wave reads them in that phase (the y-role lines of wave w
+    // have z2 = w, its z-role lines y2 = w). The quantities both directions differentiate (shared) need exchange
+    // slots, one set per direction.
+    static constexpr bool shared(int q)
+    {
+        bool y = false, z = false;
+        for (int k = 0; k < NG; ++k) {
+            y = y || S::dq(1, k) == q;
+            z = z || S::dq(2, k) == q;
+        }
+        return y && z;
+    }
+    static constexpr int NGS = [] {
+        int c = 0;
+        for (int q = 0; q < M; ++q) c += shared(q) ? 1 : 0;
+        return c;
+    }();
+    // exchange slot of a shared quantity (its rank among the shared ones), -1 for the others
+    static constexpr int gslot(int q)
+    {
+        if (!shared(q)) return -1;
+        int c = 0;
+        for (int i = 0; i < q; ++i) c += shared(i) ? 1 : 0;
+        return c;
+    }
+    // LDS (floats): the tile of the quantities differentiated along y or z, then the exchange slots of the y- and
+    // of the z-derivatives. Outputs are staged over them (each wave's half of an output block, its lines padded by
+    // 4 floats), and the face pass holds an FP32 q-bar tile of all quantities followed by the face values. The
+    // elastic kernel's 32 KB leave room for the four elements per CU that its registers allow.
+    static constexpr int P_OFF = 0, GY_OFF = NPS * SLOT, GZ_OFF = GY_OFF + NGS * SLOT;
+    static constexpr int ELDS = GZ_OFF + NGS * SLOT;
+    // tile word offset of the direction-D derivative of quantity q (exchange slot or in place)
+    static constexpr int dslot(int D, int q)
+    {
+        return gslot(q) >= 0 ? (D == 1 ? GY_OFF : GZ_OFF) + gslot(q) * SLOT : P_OFF + S::slot(q) * SLOT;
+    }
     static constexpr int LINE = n * M;        // floats of one line of an output block
     static constexpr int SLINE = LINE + 4;    // staged line (16-byte aligned)
-    static constexpr int STAGE_END = n2 * SLINE;  // one round of 64 lines from the start of the LDS
+    static constexpr int WSTAGE = 32 * SLINE; // one wave's staging area (its 32 owner lines)
     static constexpr int FACE_OFF = M * SLOT;
     static constexpr int max3(int x, int y, int z) { return x > y ? (x > z ? x : z) : (y > z ? y : z); }
-    static constexpr int LDS_FLOATS = max3(ELDS, FACE_OFF + 6 * n2 * M, STAGE_END);
-    // two rounds of 32 lines staged in the tile, which leaves the exchange buffers intact
-    static_assert((n2 / 2) * SLINE <= GY_OFF, "half-block staging fits in the tile");
+    static constexpr int LDS_FLOATS = max3(ELDS, FACE_OFF + 6 * n2 * M, 2 * WSTAGE);
 
     // x-derivative index of quantity q (k with dq(0, k) == q), or -1
     static constexpr int kx(int q)
@@ -266,8 +303,8 @@ struct MfmaF {
         }
     }
 
-    // y- or z-role: the derivatives along D of the quantities dq(D, k) on the role lines, into the slots k of the
-    // direction's exchange buffer. B[abid][m] = D[4h + l % 4][4 abid + m].
+    // y- or z-role: the derivatives along D of the quantities dq(D, k) on the role lines, into their exchange
+    // slots or in place (dslot). B[abid][m] = D[4h + l % 4][4 abid + m].
     template <int D>
     __device__ static inline void transposed(const float (&B)[2][4], unsigned char* smem, const Offs& f)
     {
@@ -285,10 +322,7 @@ struct MfmaF {
 #pragma unroll
             for (int m = 0; m < 4; ++m) c = __builtin_amdgcn_mfma_f32_4x4x1f32(u[m], B[1][m], c, 1, 1, 0);
 #pragma unroll
-            for (int t = 0; t < NL; ++t) lds(smem, wr[t] + 4 * (g_off(D) + k * SLOT)) = c[t];
-            // two quantities at a time: four independent product chains hide the products' latency, and the
-            // accumulators of the others are not all live at once
-            if (k % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+            for (int t = 0; t < NL; ++t) lds(smem, wr[t] + 4 * dslot(D, S::dq(D, k))) = c[t];
         }
     }
 
@@ -299,7 +333,7 @@ struct MfmaF {
         if constexpr (K < NG) {
             float g[NL];
 #pragma unroll
-            for (int t = 0; t < NL; ++t) g[t] = lds(smem, ow[t] + 4 * (g_off(D) + K * SLOT));
+            for (int t = 0; t < NL; ++t) g[t] = lds(smem, ow[t] + 4 * dslot(D, S::dq(D, K)));
             mfma::ncp_cart<PHYS, D, K>(mt, g, r);
             gather<D, K + 1>(smem, ow, mt, r);
         }
@@ -309,16 +343,22 @@ struct MfmaF {
     // and z-derivatives through the tile and the exchange buffers. Ends after the gathers; the caller may rewrite
     // the tile at once (its last reads came before the barrier that precedes the gathers), and the exchange
     // buffers after its next barrier.
+    //
+    // The y-pass is local to each wave: wave w's owner lines have z2 = w, and so have its y-role lines, which read
+    // only tile nodes its own x-pass wrote and write only nodes its own owners gather (the LDS executes a wave's
+    // accesses in order). So the y-role pass follows the x-pass without a barrier, and the y-gather shares the
+    // phase of the z-role pass (which reads both waves' tile writes: after the first barrier); the z-gather
+    // follows the second barrier. Each phase mixes matrix-core and VALU work.
     __device__ static inline void volume(const float (&A)[2][4], const float (&B)[2][4], unsigned char* smem,
                                          const Offs& f, const Material<float, PHYS> (&mt)[NL],
                                          const float (&v)[M][NL], float (&r)[M][NL])
     {
         xpass<0>(A, smem, f.o, mt, v, r);
-        __syncthreads();
         transposed<1>(B, smem, f);
-        transposed<2>(B, smem, f);
         __syncthreads();
         gather<1>(smem, f.o, mt, r);
+        transposed<2>(B, smem, f);
+        __syncthreads();
         gather<2>(smem, f.o, mt, r);
     }
 
@@ -342,44 +382,39 @@ struct MfmaF {
         }
     }
 
-    // Store one output block of the element (64 lines x 8 nodes x M contiguous floats at `dst`) through the
-    // staging area S, ROUNDS rounds of 64 / ROUNDS lines (the lines of one wave per round when ROUNDS = 2), lines
-    // padded to SLINE floats, so that each 16-byte store instruction of a wave covers 1 KB of consecutive
-    // addresses. Falls back to per-lane stores when misaligned. Ends with a workgroup barrier either way
-    // (`aligned` is uniform over the workgroup); the caller has passed a barrier after the last read of S.
-    template <int ROUNDS>
-    __device__ static inline void store_block(float* Sg, float* dst, const float (&v)[M][NL], int tid, int wv,
-                                              int line, int h, bool aligned)
+    // Store one output block (64 lines x 8 nodes x M contiguous floats at `dst`) through per-wave staging areas:
+    // wave w's owner lines 32w .. 32w + 31 are 32 x LINE contiguous floats of the block, which the wave stages in its
+    // own area (lines padded to SLINE floats) and copies out with 16-byte stores, each store instruction covering
+    // 1 KB of consecutive addresses. The LDS executes a wave's accesses in order, so neither the copy nor the wave's
+    // next use of its area waits for the other wave; the caller orders the areas against the other wave's use of
+    // the same words. Falls back to per-lane stores when misaligned (`aligned` is uniform over the workgroup).
+    __device__ static inline void store_wave(float* area, float* dst, const float (&v)[M][NL], int wv, int l,
+                                             int line, int h, bool aligned)
     {
         if (!aligned) {
             float* d = dst + (line * n + 4 * h) * M;
 #pragma unroll
             for (int w = 0; w < NL * M; ++w) d[w] = v[w % M][w / M];
-            __syncthreads();
             return;
         }
-        constexpr int LPR = n2 / ROUNDS;  // lines per round
-        constexpr int L4 = LINE / 4;      // float4 per line
+        float* my = area + wv * WSTAGE;
+        float4* s4 = reinterpret_cast<float4*>(my + (line - 32 * wv) * SLINE + 4 * h * M);
 #pragma unroll
-        for (int rnd = 0; rnd < ROUNDS; ++rnd) {
-            if (ROUNDS == 1 || wv == rnd) {
-                float4* s4 = reinterpret_cast<float4*>(Sg + (line - rnd * LPR) * SLINE + 4 * h * M);
-#pragma unroll
-                for (int i = 0; i < M; ++i) {
-                    const int w = 4 * i;
-                    s4[i] = make_float4(v[(w + 0) % M][(w + 0) / M], v[(w + 1) % M][(w + 1) / M],
-                                        v[(w + 2) % M][(w + 2) / M], v[(w + 3) % M][(w + 3) / M]);
-                }
-            }
-            __syncthreads();
-            float4* d4 = reinterpret_cast<float4*>(dst + rnd * LPR * LINE);
-#pragma unroll
-            for (int j = tid; j < LPR * L4; j += WG) {
-                const int ln = j / L4, k = j - ln * L4;
-                d4[j] = *reinterpret_cast<const float4*>(Sg + ln * SLINE + 4 * k);
-            }
-            __syncthreads();
+        for (int i = 0; i < M; ++i) {
+            const int w = 4 * i;
+            s4[i] = make_float4(v[(w + 0) % M][(w + 0) / M], v[(w + 1) % M][(w + 1) / M],
+                                v[(w + 2) % M][(w + 2) / M], v[(w + 3) % M][(w + 3) / M]);
         }
+        wave_sync();
+        constexpr int L4 = LINE / 4;  // float4 per line
+        static_assert((32 * L4) % 64 == 0, "a wave's lines are a whole number of float4 per lane");
+        float4* d4 = reinterpret_cast<float4*>(dst + (int64_t)wv * 32 * LINE);
+#pragma unroll
+        for (int i = 0; i < 32 * L4 / 64; ++i) {
+            const int j = l + 64 * i, ln = j / L4, k = j - ln * L4;
+            d4[j] = *reinterpret_cast<const float4*>(my + ln * SLINE + 4 * k);
+        }
+        wave_sync();
     }
 
     // The faces of direction D (0 x, 1 y, 2 z) from the q-bar values u[s][t] at the lane's nodes along its line in
@@ -471,30 +506,30 @@ struct MfmaF {
                 // precedes this step's gathers (the tile's last reads come before it), and the exchange buffers
                 // after the barrier that follows its own tile writes.
             }
-            __syncthreads();  // the last gather's reads of the exchange buffer, which stages the outputs
+            __syncthreads();  // the last gathers' reads of the tile and exchange slots, which stage the outputs
 
-            // outputs. Each staging round starts after every lane's last read of the staging area (a barrier)
-            // and ends with one (inside store_block).
+            // outputs: q-bar, the faces, favg
             const bool fsum = (a.flags & kFavgSum) != 0;
-            store_block<1>(Sg, static_cast<float*>(a.qavg) + er.q, qb, tid, wv, line, h, al);
+            store_wave(Sg, static_cast<float*>(a.qavg) + er.q, qb, wv, l, line, h, al);
+            __syncthreads();  // both waves' copies out of their staging areas, which the face tile overwrites
             // faces (before favg, so that q-bar is no longer live once the favg x-pass has stored it in the tile):
             // the x-faces from the registers, the y- and z-faces from an FP32 q-bar tile. The face values are staged
             // in LDS in the output layout [f][a][b][s] and written with coalesced stores.
             float* PF = Sg;
             float* F = PF + FACE_OFF;
-            float eo[NL], ep[NL];  // face vectors l_j(h), l_j(1 - h) at the lane's 4 nodes along a line
-#pragma unroll
-            for (int t = 0; t < NL; ++t) {
-                eo[t] = ld<float>(h ? a.e1 : a.e0, 4 * h + t);
-                ep[t] = ld<float>(h ? a.e0 : a.e1, 4 * h + t);
-            }
-#pragma unroll
-            for (int s = 0; s < M; ++s)
-#pragma unroll
-                for (int t = 0; t < NL; ++t) lds(smem, off.o[t] + 4 * s * SLOT) = qb[s][t];
-            faces_dir<0>(F, qb, eo, ep, line, h);
-            __syncthreads();
             {
+                float eo[NL], ep[NL];  // face vectors l_j(h), l_j(1 - h) at the lane's 4 nodes along a line
+#pragma unroll
+                for (int t = 0; t < NL; ++t) {
+                    eo[t] = ld<float>(h ? a.e1 : a.e0, 4 * h + t);
+                    ep[t] = ld<float>(h ? a.e0 : a.e1, 4 * h + t);
+                }
+#pragma unroll
+                for (int s = 0; s < M; ++s)
+#pragma unroll
+                    for (int t = 0; t < NL; ++t) lds(smem, off.o[t] + 4 * s * SLOT) = qb[s][t];
+                faces_dir<0>(F, qb, eo, ep, line, h);
+                __syncthreads();
                 // the y- and z-faces of the lines (z, x) resp. (y, x) = (la, lb) in the owner's lane layout, whose
                 // line partners are DPP mirrors
                 const int ca = la(wv, l), cb = lb(l);
@@ -520,16 +555,15 @@ struct MfmaF {
             } else {
                 for (int i = tid; i < 6 * n2 * M; i += WG) qf[i] = F[i];
             }
-            __syncthreads();  // the face copy's reads of the staging area, which the favg pass reuses
             {
-                // favg = V_d(q-bar): the x-pass (which stores q-bar in the tile), both transposed passes, then the
-                // three directions' contributions, each block staged in the tile once the transposed passes have
-                // read it (two rounds, leaving the exchange buffers intact), or their sum.
-                float fx[M][NL];
+                // favg = V_d(q-bar): the x-pass (its tile writes miss the face values still being copied out),
+                // then, after a barrier, both transposed passes (which overwrite the face values) and the gathers.
+                // The three direction blocks are held in registers and staged once the gathers have read the tile.
+                float fx[M][NL], fy[M][NL], fz[M][NL];
 #pragma unroll
                 for (int s = 0; s < M; ++s)
 #pragma unroll
-                    for (int t = 0; t < NL; ++t) fx[s][t] = 0.f;
+                    for (int t = 0; t < NL; ++t) fx[s][t] = fy[s][t] = fz[s][t] = 0.f;
                 xpass<0>(A, smem, off.o, mt, qb, fx);
                 __syncthreads();
                 transposed<1>(B, smem, off);
@@ -537,27 +571,20 @@ struct MfmaF {
                 __syncthreads();
                 float* fav = static_cast<float*>(a.favg) + (fsum ? er.q : 3 * er.q);
                 if (!fsum) {
-                    store_block<2>(Sg, fav, fx, tid, wv, line, h, al);
-#pragma unroll
-                    for (int s = 0; s < M; ++s)
-#pragma unroll
-                        for (int t = 0; t < NL; ++t) fx[s][t] = 0.f;
-                    gather<1>(smem, off.o, mt, fx);
-                    store_block<2>(Sg, fav + (int64_t)n3 * M, fx, tid, wv, line, h, al);
-#pragma unroll
-                    for (int s = 0; s < M; ++s)
-#pragma unroll
-                        for (int t = 0; t < NL; ++t) fx[s][t] = 0.f;
-                    gather<2>(smem, off.o, mt, fx);
-                    // one round over the tile and the y-buffer (read before the last barrier), not the z-buffer
-                    store_block<1>(Sg, fav + 2 * (int64_t)n3 * M, fx, tid, wv, line, h, al);  // ends with a barrier
+                    gather<1>(smem, off.o, mt, fy);
+                    gather<2>(smem, off.o, mt, fz);
+                    __syncthreads();  // the gathers' reads, before the staging overwrites the tile
+                    store_wave(Sg, fav, fx, wv, l, line, h, al);
+                    store_wave(Sg, fav + (int64_t)n3 * M, fy, wv, l, line, h, al);
+                    store_wave(Sg, fav + 2 * (int64_t)n3 * M, fz, wv, l, line, h, al);
                 } else {
                     gather<1>(smem, off.o, mt, fx);
                     gather<2>(smem, off.o, mt, fx);
-                    __syncthreads();  // the gathers' reads of the exchange buffers, which the staging overwrites
-                    store_block<1>(Sg, fav, fx, tid, wv, line, h, al);  // ends with a barrier
+                    __syncthreads();  // the gathers' reads, before the staging overwrites the tile
+                    store_wave(Sg, fav, fx, wv, l, line, h, al);
                 }
             }
+            __syncthreads();  // both waves' staging copies, before the next element's x-pass writes the tile
         }
     }
 };

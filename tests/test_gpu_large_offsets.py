@@ -104,6 +104,13 @@ def test_mfma_beyond_int32_offsets(gpu, misalign):
     check(dict(prec=stp.BF16X3, variant=stp.VARIANT_MFMA), [W.elastic_batch(7, 6, 870)], gpu, misalign)
 
 
+@pytest.mark.parametrize("misalign", [False, True])
+@pytest.mark.parametrize("physics", ["elastic", "acoustic"])
+def test_fp32_mfma_beyond_int32_offsets(gpu, physics, misalign):
+    part = W.elastic_batch(7, 6, 869) if physics == "elastic" else W.acoustic_batch(7, 6, 868)
+    check(dict(prec=stp.FP32, variant=stp.VARIANT_MFMA), [part], gpu, misalign)
+
+
 def test_fused_beyond_int32_offsets(gpu):
     check(dict(prec=stp.FP32, variant=stp.VARIANT_FUSED), [W.elastic_batch(3, 6, 871)], gpu, True)
 

@@ -42,7 +42,8 @@ def check(b, prec, variant=stp.VARIANT_AUTO):
 
 
 @pytest.mark.parametrize("N,prec,variant", [(3, stp.FP64, stp.VARIANT_PLAIN), (3, stp.FP32, stp.VARIANT_FUSED),
-                                            (7, stp.FP32, stp.VARIANT_FUSED), (7, stp.BF16X3, stp.VARIANT_MFMA),
+                                            (7, stp.FP32, stp.VARIANT_FUSED), (7, stp.FP32, stp.VARIANT_MFMA),
+                                            (7, stp.BF16X3, stp.VARIANT_MFMA),
                                             (9, stp.FP32, stp.VARIANT_PLAIN)])
 def test_elastic_lobatto_variants(N, prec, variant):
     check(W.elastic_batch(N, 40, 700 + N), prec, variant)

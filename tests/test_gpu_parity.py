@@ -519,6 +519,7 @@ def test_uniform_graph_capture_replays():
     import torch
     from paper_2003_12787_amd import runner
     for b, prec, variant in ((W.c3_elastic_n7(2048), stp.FP32, stp.VARIANT_FUSED),
+                             (W.c3_elastic_n7(2048), stp.FP32, stp.VARIANT_MFMA),
                              (W.c3_elastic_n7(2048), stp.BF16X3, stp.VARIANT_MFMA),
                              (W.elastic_batch(9, 300, 1010), stp.BF16X3, stp.VARIANT_MFMA)):
         say(f"[graph] N={b.N} E={b.nelem} prec={prec} variant={variant}")
