@@ -1,8 +1,8 @@
 """Per-order timing of the predictor's FP32 kernels: where the matrix cores could pay.
 
 For the acoustic and elastic presets at N = 1..9 (per-node material, Q ~ N(0, 1), inputs drawn on the device),
-every kernel variant that exists for the class in FP32 I/O (plain, fused; the split-BF16x3 MFMA kernels at
-N = 7..9) is timed with HIP events over a batch of about 2 GB of algorithmic traffic. The algorithmic bytes
+every kernel variant that exists for the class in FP32 I/O (plain, fused; the FP32 MFMA kernel at N = 7 and
+the split-BF16x3 MFMA kernels at N = 7..9) is timed with HIP events over a batch of about 2 GB of algorithmic traffic. The algorithmic bytes
 (inputs read once, outputs written once) and flops come from stp_class_cost. A variant that moves its bytes
 near the measured device-copy rate is bound by HBM, and faster contractions cannot shorten it; a variant well
 below it is bound by its instruction issue, and that is where the matrix cores can pay.
@@ -48,7 +48,8 @@ def main():
     torch.cuda.empty_cache()
     out = {"copy_gbs": copy_gbs, "rows": []}
     print(f"copy {copy_gbs:.0f} GB/s", file=sys.stderr)
-    names = {stp.VARIANT_PLAIN: "plain", stp.VARIANT_FUSED: "fused", stp.VARIANT_MFMA: "mfma"}
+    names = {(stp.FP32, stp.VARIANT_PLAIN): "plain", (stp.FP32, stp.VARIANT_FUSED): "fused",
+             (stp.FP32, stp.VARIANT_MFMA): "mfma32", (stp.BF16X3, stp.VARIANT_MFMA): "mfma"}
     g = torch.Generator(device="cuda")
     for phys, m, npar, pname in ((stp.ACOUSTIC, 4, 2, "acoustic"), (stp.ELASTIC, 9, 3, "elastic")):
         for N in range(lo, hi + 1):
@@ -67,6 +68,8 @@ def main():
             dt = 0.4 / ((2 * N + 1) * 2.0)
             variants = [stp.VARIANT_PLAIN] + ([stp.VARIANT_FUSED] if N <= 7 else [])
             precs = [(stp.FP32, v) for v in variants]
+            if N == 7:
+                precs.append((stp.FP32, stp.VARIANT_MFMA))
             if N >= 7:
                 precs.append((stp.BF16X3, stp.VARIANT_MFMA))
             for prec, var in precs:
@@ -84,12 +87,12 @@ def main():
                 torch.cuda.synchronize()
                 ms = float(np.median([a0.elapsed_time(a1) for a0, a1 in ev]))
                 gbs = bytes_el * E / (ms * 1e-3) / 1e9
-                row = {"physics": pname, "N": N, "variant": names[var], "nelem": E, "ms": ms,
+                row = {"physics": pname, "N": N, "variant": names[(prec, var)], "nelem": E, "ms": ms,
                        "elements_per_s": E / (ms * 1e-3), "hbm_gbs": gbs, "frac_of_copy": gbs / copy_gbs,
                        "frac_of_8tbs": gbs / 8000.0, "tflops": flops_el * E / (ms * 1e-3) / 1e12,
                        "bytes_per_element": bytes_el, "flops_per_element": flops_el}
                 out["rows"].append(row)
-                print(f"{pname:9s} N={N} {names[var]:6s} E={E:7d} {ms:8.3f} ms  {gbs:6.0f} GB/s "
+                print(f"{pname:9s} N={N} {names[(prec, var)]:6s} E={E:7d} {ms:8.3f} ms  {gbs:6.0f} GB/s "
                       f"({gbs / copy_gbs:5.1%} of copy)  {row['tflops']:5.1f} TFLOP/s", file=sys.stderr)
                 plan.close()
             del Q, par, qavg, favg, qface
