@@ -198,7 +198,8 @@ struct Mfma8 {
 
     // Row D of the metric terms at the lane's 2 nodes (curvilinear elements): re-read from the parameter array
     // for each direction (the laundered offset keeps the loads inside the Taylor loop; L2 holds the element's
-    // parameters) instead of being held in registers for the whole kernel.
+    // parameters) instead of being held in registers for the whole kernel. Each row is loaded one phase before
+    // the phase that uses it, so at most two rows are live at a time.
     using GRow = float[NL][3];
     template <int D>
     __device__ static inline void load_grow(const float* gp, int stride, GRow& Gd)
@@ -464,15 +465,13 @@ struct Mfma8 {
     }
 
     // r += the y- or z-contributions, once every lane has written the first chunk of direction D (transposed
-    // <D, 0, C1>) and passed a barrier; the other chunk, if any, goes through the exchange buffer here. gp, gs:
-    // the lane's first node's parameters and the per-node stride (0 for per-element parameters).
+    // <D, 0, C1>) and passed a barrier; the other chunk, if any, goes through the exchange buffer here. Gd: the
+    // direction's metric row at the lane's nodes (curvilinear elements; loaded by the caller a phase ahead).
     template <int D, int R>
     __device__ static inline void finish_dir(const bf16x8& A, unsigned char* smem, const Offs& f,
-                                             const Material<float, PHYS> (&mt)[NL], const float* gp, int gs,
+                                             const Material<float, PHYS> (&mt)[NL], const GRow& Gd,
                                              float (&r)[R][NL])
     {
-        GRow Gd;
-        load_grow<D>(gp, gs, Gd);
         gather<D, 0, C1>(smem, addr(f.o), mt, Gd, r);
         if constexpr (NG > NGX) {
             __syncthreads();
@@ -621,6 +620,10 @@ struct Mfma8 {
                 for (int t = 0; t < NL; ++t) qb[s][t] = p[s][t];
             float w = 1.f;
             const float dt = (float)er.dt;
+            // curvilinear elements: each direction's metric row is loaded one phase ahead of its use (row 0 of the
+            // next application during this step's z-gather), so the L2 latency overlaps the previous phase's work
+            GRow G0;
+            load_grow<0>(gp, gs, G0);
 #pragma unroll 1
             for (int o = 1; o <= N; ++o) {
                 float r[TR][NL];
@@ -628,19 +631,20 @@ struct Mfma8 {
                 for (int s = 0; s < TR; ++s)
 #pragma unroll
                     for (int t = 0; t < NL; ++t) r[s][t] = 0.f;
-                {
-                    GRow G0;
-                    load_grow<0>(gp, gs, G0);
-                    split_xpass(A, smem, off, mt, G0, p, r);
-                }
+                GRow G1;
+                load_grow<1>(gp, gs, G1);
+                split_xpass(A, smem, off, mt, G0, p, r);
                 __syncthreads();
                 transposed<1, 0, C1>(A, smem, off);
                 __syncthreads();
-                finish_dir<1>(A, smem, off, mt, gp, gs, r);
+                GRow G2;
+                load_grow<2>(gp, gs, G2);
+                finish_dir<1>(A, smem, off, mt, G1, r);
                 __syncthreads();
                 transposed<2, 0, C1>(A, smem, off);
                 __syncthreads();
-                finish_dir<2>(A, smem, off, mt, gp, gs, r);
+                load_grow<0>(gp, gs, G0);
+                finish_dir<2>(A, smem, off, mt, G2, r);
                 w = w * dt * __builtin_amdgcn_rcpf((float)(o + 1));
                 if constexpr (TR == kGradRows) {
                     grad_finish(mt, r, p);
@@ -670,11 +674,9 @@ struct Mfma8 {
                 for (int s = 0; s < M; ++s)
 #pragma unroll
                     for (int t = 0; t < NL; ++t) fx[s][t] = 0.f;
-                {
-                    GRow G0;
-                    load_grow<0>(gp, gs, G0);
-                    split_xpass(A, smem, off, mt, G0, qb, fx);
-                }
+                GRow G1;
+                load_grow<1>(gp, gs, G1);
+                split_xpass(A, smem, off, mt, G0, qb, fx);  // G0: loaded during the last step's z-gather
                 float* fav = static_cast<float*>(a.favg) + (fsum ? er.q : 3 * er.q);
                 if (!fsum) {
                     store_block(G, fav, fx, tid, wv, c, q, al);  // ends with a barrier: the tile is complete
@@ -687,7 +689,9 @@ struct Mfma8 {
                 }
                 transposed<1, 0, C1>(A, smem, off);
                 __syncthreads();
-                finish_dir<1>(A, smem, off, mt, gp, gs, fx);
+                GRow G2;
+                load_grow<2>(gp, gs, G2);
+                finish_dir<1>(A, smem, off, mt, G1, fx);
                 __syncthreads();
                 if (!fsum) {
                     store_block(G, fav + (int64_t)n3 * M, fx, tid, wv, c, q, al);
@@ -698,7 +702,7 @@ struct Mfma8 {
                 }
                 transposed<2, 0, C1>(A, smem, off);
                 __syncthreads();
-                finish_dir<2>(A, smem, off, mt, gp, gs, fx);
+                finish_dir<2>(A, smem, off, mt, G2, fx);
                 __syncthreads();
                 store_block(G, fsum ? fav : fav + 2 * (int64_t)n3 * M, fx, tid, wv, c, q, al);
             }
