@@ -356,12 +356,14 @@ stp_status stp_plan_describe(stp_plan_t p, char* buf, size_t len)
     char tmp[256];
     for (size_t c = 0; c < p->classes.size(); ++c) {
         const ClassState& cs = p->classes[c];
+        const KernelInfo onchip = resident_kernel_f32(cs.cls.order, cs.cls.nquant);
         std::snprintf(tmp, sizeof tmp,
                       "%s{\"order\": %d, \"nquant\": %d, \"physics\": %d, \"variant\": \"%s\", \"tiled\": %s, "
-                      "\"elements_per_tile\": %d, \"acc64\": %s}",
+                      "\"elements_per_tile\": %d, \"acc64\": %s, \"on_chip_B\": %s}",
                       c ? ", " : "", cs.cls.order, cs.cls.nquant, cs.cls.physics,
                       names[cs.variant >= 0 && cs.variant <= 3 ? cs.variant : 0], cs.tiled ? "true" : "false",
-                      cs.tiled ? cs.slots : 1, cs.acc64 ? "true" : "false");
+                      cs.tiled ? cs.slots : 1, cs.acc64 ? "true" : "false",
+                      onchip.fn && onchip.fn == cs.kernel.fn ? "true" : "false");
         out += tmp;
     }
     std::snprintf(tmp, sizeof tmp,

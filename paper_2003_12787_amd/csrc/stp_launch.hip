@@ -173,6 +173,22 @@ Eligibility eligible(const stp_plan_s* p, const ClassState& cs)
                        (p->prec == STP_FP32 && N == 7 && cart))};
 }
 
+// Generic classes with dense per-node B_d and no other terms (no A, no point source), FP32 arithmetic and
+// accumulation: the kernel that keeps B_d on chip through the Taylor loop, where one exists for the order and m.
+KernelInfo resident_for(const stp_plan_s* p, const ClassState& cs)
+{
+    const unsigned other = STP_A_PRESENT | STP_SRC_POINT | STP_COEF_PER_ELEMENT;
+    if (p->prec == STP_FP64 || cs.acc64 || cs.cls.physics != STP_GENERIC || (cs.cls.flags & other)) return {};
+    return resident_kernel_f32(cs.cls.order, cs.cls.nquant);
+}
+
+// the plain variant: the on-chip B_d kernel where it applies, else the plain kernel
+KernelInfo plain_for(const stp_plan_s* p, const ClassState& cs)
+{
+    const KernelInfo r = resident_for(p, cs);
+    return r.fn ? r : plain_kernel(p->prec == STP_FP64, cs.acc64, cs.cls.order, cs.cls.physics, cs.cls.nquant);
+}
+
 // the matrix-core kernel of the plan's precision: FP32 products, or split-BF16 products with FP32 accumulation
 KernelInfo mfma_for(const stp_plan_s* p, const ClassState& cs)
 {
@@ -185,8 +201,7 @@ std::vector<std::pair<int, KernelInfo>> kernel_candidates(stp_plan_s* p, const C
 {
     const Eligibility el = eligible(p, cs);
     std::vector<std::pair<int, KernelInfo>> v;
-    v.push_back({STP_VARIANT_PLAIN,
-                 plain_kernel(p->prec == STP_FP64, cs.acc64, cs.cls.order, cs.cls.physics, cs.cls.nquant)});
+    v.push_back({STP_VARIANT_PLAIN, plain_for(p, cs)});
     if (el.fused) v.push_back({STP_VARIANT_FUSED, fused_kernel_f32(cs.cls.order, cs.cls.physics)});
     if (el.mfma) v.push_back({STP_VARIANT_MFMA, mfma_for(p, cs)});
     return v;
@@ -195,7 +210,7 @@ std::vector<std::pair<int, KernelInfo>> kernel_candidates(stp_plan_s* p, const C
 KernelInfo select_kernel(stp_plan_s* p, const ClassState& cs, int* variant)
 {
     const Eligibility el = eligible(p, cs);
-    const KernelInfo plain = plain_kernel(p->prec == STP_FP64, cs.acc64, cs.cls.order, cs.cls.physics, cs.cls.nquant);
+    const KernelInfo plain = plain_for(p, cs);
     int v = p->variant;
     if (v == STP_VARIANT_AUTO)  // built-in rule: matrix cores where a kernel exists, else fused, else plain
         v = el.mfma ? STP_VARIANT_MFMA : (el.fused ? STP_VARIANT_FUSED : STP_VARIANT_PLAIN);
@@ -342,7 +357,9 @@ stp_status hetero_prepare(stp_plan_s* p)
         const int N = cs.cls.order, nn = (N + 1) * (N + 1) * (N + 1);
         const bool hasA = cs.cls.physics == STP_GENERIC && (cs.cls.flags & STP_A_PRESENT);
         cs.tiled = false;
-        if (f32io && !cs.acc64 && N <= hetero::kMaxOrder) {
+        // tiles of the persistent launch; classes of the on-chip B_d kernel keep their own launch (a tile slot
+        // has one thread per node and the LDS of a few elements, too little to hold B_d)
+        if (f32io && !cs.acc64 && N <= hetero::kMaxOrder && !resident_for(p, cs).fn) {
             const int bk = hetero::bucket_of(cs.cls.physics, cs.cls.nquant);
             const HeteroKernel k = hetero_kernel_f32(bk);
             const size_t sl = k.fn ? k.slot_lds(N, cs.cls.nquant, hasA) : 0;

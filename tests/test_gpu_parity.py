@@ -291,6 +291,38 @@ def test_generic_dense_B_per_node(N, m, prec):
     check(W.generic_batch(N, m, 67, 700 + N * 20 + m), prec, label="generic")
 
 
+@pytest.mark.parametrize("N,m", [(7, 9), (8, 9), (9, 9), (7, 4), (8, 4), (9, 4)])
+def test_generic_on_chip_B(N, m):
+    """Generic classes with dense per-node B_d and no other terms take the kernel that holds B_d on chip
+    (registers and LDS, the rest streamed): FP32 parity at every order and m it covers, odd element counts."""
+    from paper_2003_12787_amd import runner
+    b = W.generic_batch(N, m, 37, 760 + N * 20 + m)
+    plan = stp.Plan([runner.class_of(b)], prec=stp.FP32)
+    assert plan.describe()["classes"][0]["on_chip_B"]
+    plan.close()
+    check(b, stp.FP32, label="generic-on-chip-B")
+
+
+def test_generic_on_chip_B_favg_sum_and_routing():
+    """The summed-flux output of the on-chip B_d kernel; classes with A, a point source, per-element coefficients,
+    FP64 accumulation or FP64 I/O, and orders below 7, keep the plain kernel."""
+    from paper_2003_12787_amd import runner
+    check(W.generic_batch(7, 9, 23, 777), stp.FP32, favg_sum=True, label="generic-on-chip-B-favg-sum")
+    for cls, prec, acc64 in [((7, 9, W.GENERIC, stp.A_PRESENT), stp.FP32, 0),
+                             ((7, 9, W.GENERIC, stp.SRC_POINT), stp.FP32, 0),
+                             ((7, 9, W.GENERIC, stp.COEF_PER_ELEMENT), stp.FP32, 0),
+                             ((8, 9, W.GENERIC, 0), stp.FP32, 8),
+                             ((7, 9, W.GENERIC, 0), stp.FP64, 0),
+                             ((6, 9, W.GENERIC, 0), stp.FP32, 0),
+                             ((6, 4, W.GENERIC, 0), stp.FP32, 0)]:
+        plan = stp.Plan([cls], prec=prec, acc64_min_order=acc64)
+        assert not plan.describe()["classes"][0]["on_chip_B"], cls
+        plan.close()
+    plan = stp.Plan([(7, 9, W.GENERIC, 0)], prec=stp.BF16X3)
+    assert plan.describe()["classes"][0]["on_chip_B"]
+    plan.close()
+
+
 @pytest.mark.parametrize("prec", [stp.FP64, stp.FP32])
 def test_generic_high_orders_with_A_source_and_per_element(prec):
     """Orders 8 and 9 form B_d (D x_d u) column by column: with A_d and a point source (per node), and with
