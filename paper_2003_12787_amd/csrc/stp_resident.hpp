@@ -10,7 +10,9 @@
 // beyond KR + KL are streamed at each application. Word e of a node's B_d is the entry (s, q) of B_d with
 // e = d m^2 + q m + s: the Taylor step forms one derivative (D x_d u)_q at a time and adds column q of B_d
 // times it to the node's m accumulators (the column form of the plain kernel at orders 8 and 9, whose
-// arithmetic this kernel repeats operation for operation).
+// arithmetic this kernel repeats operation for operation). With G = 4 the derivatives of four quantities are
+// formed together from 16-byte LDS reads of a tile padded to a multiple of four words per node; the sums keep
+// their order, so the results are the same bits.
 //
 // Per element (Sec. II-A, Eq. (4); Sec. II-B outputs):
 //   p_0 = Q;  for o = 1..N:  p_o = V(p_{o-1});  qavg += dt^o/(o+1)! p_o
@@ -24,20 +26,25 @@
 namespace stp {
 namespace resident {
 
-template <int N, int MB, int NT, int K, int KR, int KL>
+template <int N, int MB, int NT, int K, int KR, int KL, int G>
 struct Res {
     static constexpr int n = N + 1;
     static constexpr int n2 = n * n;
     static constexpr int nn = n * n2;
     static constexpr int m = MB;
     static constexpr int NE = 3 * m * m;  // words of B_d per node
+    // G = 4: the tile's node stride is padded to a multiple of 4 words, so that the four quantities q0..q0 + 3 of
+    // a line node come in one 16-byte LDS read and four derivatives are formed together (G = 1: one at a time)
+    static_assert(G == 1 || G == 4, "derivative group");
+    static constexpr int MP = G == 4 ? (m + 3) / 4 * 4 : m;
     static_assert(NT % 64 == 0 && NT * K >= nn && NT * (K - 1) < nn, "the K nodes per thread tile the element");
     static_assert(KR >= 0 && KL >= 0 && KR + KL <= NE, "resident words within a node's B_d");
 
-    // LDS: D [n][n], l(0) [n], l(1) [n]; the Taylor term [nn][m]; the LDS-resident words [KL][nn]
+    // LDS: D [n][n], l(0) [n], l(1) [n]; the Taylor term [nn][MP] (padding words zero); the LDS-resident words
+    // [KL][nn]
     static constexpr size_t al16(size_t b) { return (b + 15) & ~size_t(15); }
     static constexpr size_t kP = al16(sizeof(float) * (n * n + 2 * n));
-    static constexpr size_t kB = al16(kP + sizeof(float) * nn * m);
+    static constexpr size_t kB = al16(kP + sizeof(float) * nn * MP);
     static constexpr size_t kLds = kB + sizeof(float) * (size_t)KL * nn;
     static_assert(kLds <= 160 * 1024, "LDS of one workgroup");
 
@@ -47,7 +54,7 @@ struct Res {
         return (int64_t)(e / (m * m)) * m * m * nn + (int64_t)((e % m) * m + (e / m) % m) * nn;
     }
 
-    // (D x_d u)_s at a node with coordinates (z, y, x); u is the LDS tile [node][m]
+    // (D x_d u)_s at a node with coordinates (z, y, x); u is the LDS tile [node][MP]
     template <int D>
     __device__ static inline float dline(const float* Ds, const float* u, int node, int z, int y, int x, int s)
     {
@@ -56,8 +63,28 @@ struct Res {
         constexpr int stride = D == 0 ? 1 : (D == 1 ? n : n2);
         float acc = 0;
 #pragma unroll
-        for (int j = 0; j < n; ++j) acc = fmaf(Ds[kd * n + j], u[(base + j * stride) * m + s], acc);
+        for (int j = 0; j < n; ++j) acc = fmaf(Ds[kd * n + j], u[(base + j * stride) * MP + s], acc);
         return acc;
+    }
+
+    // (D x_d u)_{q0..q0+3} with the sums in the order of dline (bit-identical per quantity)
+    template <int D>
+    __device__ static inline void dline4(const float* Ds, const float* u, int node, int z, int y, int x, int q0,
+                                         float (&g)[4])
+    {
+        const int kd = D == 0 ? x : (D == 1 ? y : z);
+        const int base = D == 0 ? node - x : (D == 1 ? node - y * n : node - z * n2);
+        constexpr int stride = D == 0 ? 1 : (D == 1 ? n : n2);
+        g[0] = g[1] = g[2] = g[3] = 0;
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+            const float dj = Ds[kd * n + j];
+            const float4 v = *reinterpret_cast<const float4*>(u + (base + j * stride) * MP + q0);
+            g[0] = fmaf(dj, v.x, g[0]);
+            g[1] = fmaf(dj, v.y, g[1]);
+            g[2] = fmaf(dj, v.z, g[2]);
+            g[3] = fmaf(dj, v.w, g[3]);
+        }
     }
 
     struct Nodes {
@@ -67,42 +94,71 @@ struct Res {
 
     // r[k] += V_D(u) at the thread's nodes: -(1/h) sum_q B_D[:, q] (D x_D u)_q, column by column. bg[k] points
     // at word 0 of node k's B_d in memory (streamed words), bres at the LDS-resident words.
+    // Word e of the thread's node k: registers, LDS or memory
+    __device__ static inline float word(int e, int k, const float (&breg)[K][KR > 0 ? KR : 1], const float* bres,
+                                        const float* const (&bg)[K], const Nodes& nd)
+    {
+        if (e < KR) return breg[k][e < KR ? e : 0];
+        if (e < KR + KL) return bres[(e - KR) * nn + nd.node[k]];
+        return bg[k][goff(e)];
+    }
+
+    // r[k] += V_D(u) at the thread's nodes: -(1/h) sum_q B_D[:, q] (D x_D u)_q, column by column. bg[k] points
+    // at word 0 of node k's B_d in memory (streamed words), bres at the LDS-resident words.
     template <int D>
     __device__ static inline void apply(const float* Ds, const float* u, const float (&breg)[K][KR > 0 ? KR : 1],
                                         const float* bres, const float* const (&bg)[K], const Nodes& nd,
                                         float ninv_h, float (&r)[K][MB])
     {
-#pragma unroll
-        for (int q = 0; q < m; ++q) {
-            float b[K][MB];
-#pragma unroll
-            for (int s = 0; s < m; ++s) {
-                const int e = D * m * m + q * m + s;
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    if (e < KR)
-                        b[k][s] = breg[k][e < KR ? e : 0];
-                    else if (e < KR + KL)
-                        b[k][s] = bres[(e - KR) * nn + nd.node[k]];
-                    else
-                        b[k][s] = bg[k][goff(e)];
-                }
-            }
-            float g[K];
-#pragma unroll
-            for (int k = 0; k < K; ++k) g[k] = ninv_h * dline<D>(Ds, u, nd.node[k], nd.z[k], nd.y[k], nd.x[k], q);
+        // column q: r[k][s] += B_D[s][q] (-(1/h) g_q) in the order s = 0..m-1, then the accumulators are pinned:
+        // they are stored only for owned nodes, and without the pin the compiler sinks the column's arithmetic
+        // into that conditional store, past the step's barrier, and keeps every loaded word of the step live
+        auto column = [&](int q, const float (&b)[K][MB], const float (&gq)[K]) {
 #pragma unroll
             for (int s = 0; s < m; ++s)
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    r[k][s] = fmaf(b[k][s], g[k], r[k][s]);
-                    // the accumulators are stored only for owned nodes; without this pin the compiler sinks the
-                    // column's arithmetic into that conditional store, past the step's barrier, and keeps every
-                    // loaded word of the step live until then
+                    r[k][s] = fmaf(b[k][s], gq[k], r[k][s]);
                     asm volatile("" : "+v"(r[k][s]));
                 }
-            // one column's loads and derivative at a time: bounds the registers they hold
-            __builtin_amdgcn_sched_barrier(0);
+        };
+        if constexpr (G == 1) {
+#pragma unroll
+            for (int q = 0; q < m; ++q) {
+                float b[K][MB];
+#pragma unroll
+                for (int s = 0; s < m; ++s)
+#pragma unroll
+                    for (int k = 0; k < K; ++k) b[k][s] = word(D * m * m + q * m + s, k, breg, bres, bg, nd);
+                float g[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    g[k] = ninv_h * dline<D>(Ds, u, nd.node[k], nd.z[k], nd.y[k], nd.x[k], q);
+                column(q, b, g);
+                // one column's loads and derivative at a time: bounds the registers they hold
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+#pragma unroll
+            for (int q0 = 0; q0 < m; q0 += 4) {
+                float g4[K][4];
+#pragma unroll
+                for (int k = 0; k < K; ++k) dline4<D>(Ds, u, nd.node[k], nd.z[k], nd.y[k], nd.x[k], q0, g4[k]);
+#pragma unroll
+                for (int qq = 0; qq < 4; ++qq) {
+                    const int q = q0 + qq;
+                    if (q >= m) break;
+                    float b[K][MB], g[K];
+#pragma unroll
+                    for (int s = 0; s < m; ++s)
+#pragma unroll
+                        for (int k = 0; k < K; ++k) b[k][s] = word(D * m * m + q * m + s, k, breg, bres, bg, nd);
+#pragma unroll
+                    for (int k = 0; k < K; ++k) g[k] = ninv_h * g4[k][qq];
+                    column(q, b, g);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
     }
 
@@ -134,7 +190,10 @@ struct Res {
             e1s[i] = ld<float>(a.e1, i);
         }
         const float* Q = static_cast<const float*>(a.Q) + er.q;
-        for (int i = tid; i < nn * m; i += NT) pbuf[i] = Q[i];
+        for (int i = tid; i < nn * MP; i += NT) {
+            const int node = i / MP, s = i - node * MP;
+            pbuf[i] = s < m ? Q[node * m + s] : 0.f;
+        }
         // LDS-resident words: word KR + j of node t at bres[j nn + t] (consecutive lanes, consecutive banks)
         for (int i = tid; i < KL * nn; i += NT) {
             const int j = i / nn, t = i - j * nn;
@@ -152,7 +211,7 @@ struct Res {
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
-            for (int s = 0; s < m; ++s) qb[k][s] = pbuf[nd.node[k] * m + s];
+            for (int s = 0; s < m; ++s) qb[k][s] = pbuf[nd.node[k] * MP + s];
         float w = 1;
         const float dt = (float)er.dt;
         for (int o = 1; o <= N; ++o) {
@@ -175,7 +234,7 @@ struct Res {
                 if (!nd.own[k]) continue;
 #pragma unroll
                 for (int s = 0; s < m; ++s) {
-                    pbuf[nd.node[k] * m + s] = r[k][s];
+                    pbuf[nd.node[k] * MP + s] = r[k][s];
                     qb[k][s] = fmaf(w, r[k][s], qb[k][s]);
                 }
             }
@@ -187,11 +246,11 @@ struct Res {
         for (int k = 0; k < K; ++k) {
             if (!nd.own[k]) continue;
 #pragma unroll
-            for (int s = 0; s < m; ++s) pbuf[nd.node[k] * m + s] = qb[k][s];
+            for (int s = 0; s < m; ++s) pbuf[nd.node[k] * MP + s] = qb[k][s];
         }
         __syncthreads();
         float* qavg = static_cast<float*>(a.qavg) + er.q;
-        for (int i = tid; i < nn * m; i += NT) qavg[i] = pbuf[i];
+        for (int i = tid; i < nn * m; i += NT) qavg[i] = pbuf[(i / m) * MP + i % m];
 
         // faces of q-bar: [f][a][b][s], f = 2 axis + side
         float* qface = static_cast<float*>(a.qface) + er.face;
@@ -204,7 +263,7 @@ struct Res {
             for (int j = 0; j < n; ++j) {
                 const int node = axis == 0 ? (aa * n + bb) * n + j
                                            : (axis == 1 ? (aa * n + j) * n + bb : (j * n + aa) * n + bb);
-                acc = fmaf(ev[j], pbuf[node * m + s], acc);
+                acc = fmaf(ev[j], pbuf[node * MP + s], acc);
             }
             qface[i] = acc;
         }
@@ -242,25 +301,25 @@ struct Res {
     }
 };
 
-template <int N, int MB, int NT, int K, int KR, int KL>
+template <int N, int MB, int NT, int K, int KR, int KL, int G>
 __global__ void __launch_bounds__(NT) stp_resident_kernel(StpArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     for (int64_t it = blockIdx.x;; it += gridDim.x) {
         ElemRef er;
         if (!elem_ref(a, it, er)) break;
-        Res<N, MB, NT, K, KR, KL>::element(a, er, smem, threadIdx.x);
+        Res<N, MB, NT, K, KR, KL, G>::element(a, er, smem, threadIdx.x);
     }
 }
 
-template <int N, int MB, int NT, int K, int KR, int KL>
+template <int N, int MB, int NT, int K, int KR, int KL, int G = 1>
 KernelInfo resident_info()
 {
     KernelInfo ki;
-    ki.fn = reinterpret_cast<const void*>(&stp_resident_kernel<N, MB, NT, K, KR, KL>);
+    ki.fn = reinterpret_cast<const void*>(&stp_resident_kernel<N, MB, NT, K, KR, KL, G>);
     ki.block = NT;
     ki.mb = MB;
-    ki.lds = [](int, bool) -> size_t { return Res<N, MB, NT, K, KR, KL>::kLds; };
+    ki.lds = [](int, bool) -> size_t { return Res<N, MB, NT, K, KR, KL, G>::kLds; };
     return ki;
 }
 
