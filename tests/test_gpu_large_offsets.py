@@ -1,5 +1,5 @@
 """GPU: elements placed beyond 2^31 values in every input and output buffer (64-bit per-element offsets in
-stp_batch), for the MFMA, fused and plain kernels and the heterogeneous persistent launch. The outputs at
+stp_batch), for the MFMA, fused, plain and on-chip B_d kernels and the heterogeneous persistent launch. The outputs at
 those offsets must equal, bit for bit, those of the same elements run from small contiguous buffers on the
 same plan, and match the oracle. About 60 GB of device memory per case (FP32), most of it never touched."""
 import sys
@@ -39,13 +39,22 @@ def offsets(sizes, misalign):
     return np.array(off, dtype=np.int64), cur
 
 
+def coef_block(p, j):
+    """Element j's coefficient block in the library layout: preset parameters, or a generic class's B_d."""
+    if p.params is not None:
+        return p.params[j].ravel()
+    return W.coef_abi(p.B[j:j + 1], p.coef_per_element)[0].ravel()
+
+
 def run_far(plan, parts, torch, misalign, classes_of=None):
-    """Run the elements of `parts` (uniform host batches, FP32-rounded) placed at 64-bit offsets; returns the
-    outputs per element as host arrays."""
+    """Run the elements of `parts` (uniform host batches, FP32-rounded; all presets, or all generic without A)
+    placed at 64-bit offsets; returns the outputs per element as host arrays."""
     elems = [(c, p, j) for c, p in enumerate(parts) for j in range(p.nelem)]
+    generic = parts[0].params is None
+    assert all((p.params is None) == generic and p.A is None for p in parts)
     sq = [p.Q[0].size for c, p, j in elems]
     sf = [6 * (p.N + 1) ** 2 * p.m for c, p, j in elems]
-    sp = [p.params[0].size for c, p, j in elems]
+    sp = [coef_block(p, j).size for c, p, j in elems]
     oq, endq = offsets(sq, misalign)
     of, endf = offsets(sf, misalign)
     oc, endc = offsets(sp, misalign)
@@ -55,14 +64,15 @@ def run_far(plan, parts, torch, misalign, classes_of=None):
     qface, par = torch.empty(endf, **f32), torch.empty(endc, **f32)
     for k, (c, p, j) in enumerate(elems):
         Q[oq[k]:oq[k] + sq[k]] = torch.from_numpy(p.Q[j].ravel()).to(**f32)
-        par[oc[k]:oc[k] + sp[k]] = torch.from_numpy(p.params[j].ravel()).to(**f32)
+        par[oc[k]:oc[k] + sp[k]] = torch.from_numpy(coef_block(p, j)).to(**f32)
     i64 = lambda a: torch.from_numpy(a).to("cuda", torch.int64)
     kw = dict(off_q=i64(oq), off_coef=i64(oc), off_face=i64(of))
     if len(parts) > 1:
         kw["cls"] = torch.from_numpy(np.array([c for c, p, j in elems], dtype=np.int32)).cuda()
     dt = torch.from_numpy(np.array([p.dt[j] for c, p, j in elems])).to("cuda", torch.float64)
     h = torch.from_numpy(np.array([p.h[j] for c, p, j in elems])).to("cuda", torch.float64)
-    plan.run(plan.batch(len(elems), Q, qavg, favg, qface, dt, h, params=par, **kw))
+    coef = {"B": par} if generic else {"params": par}
+    plan.run(plan.batch(len(elems), Q, qavg, favg, qface, dt, h, **coef, **kw))
     torch.cuda.synchronize()
     out = []
     for k, (c, p, j) in enumerate(elems):
@@ -84,7 +94,7 @@ def check(plan_args, parts, torch, misalign):
         for j in range(parts[0].nelem):
             near[(0, j)] = {k: v[j].ravel() for k, v in got.items()}
     for c, p in enumerate(parts):
-        ref = oracle.stp(p.N, p.physics, p.Q, p.dt, p.h, params=p.params, coef_per_element=p.coef_per_element)
+        ref = oracle.stp(p.N, p.physics, p.Q, p.dt, p.h, params=p.params, B=p.B, coef_per_element=p.coef_per_element)
         ks = [k for k, (cc, pp, j) in enumerate(elems) if cc == c]
         g = {key: np.stack([far[k][key].astype(np.float64).reshape(ref[key][0].shape) for k in ks])
              for key in ("qavg", "favg", "qface")}
@@ -129,3 +139,13 @@ def test_heterogeneous_beyond_int32_offsets(gpu):
 def test_mfma_orders_8_9_beyond_int32_offsets(gpu, N):
     """Order 8 blocks hold an odd number of values, so misaligned placements reach every copy-out alignment."""
     check(dict(prec=stp.BF16X3, variant=stp.VARIANT_MFMA), [W.elastic_batch(N, 5, 876 + N)], gpu, True)
+
+
+@pytest.mark.parametrize("N,m", [(7, 9), (9, 4)])
+def test_on_chip_B_beyond_int32_offsets(gpu, N, m):
+    """The generic kernel that holds B_d on chip: B_d blocks, like every other array, past 2^31 values."""
+    part = W.generic_batch(N, m, 5, 880 + N + m)
+    plan = stp.Plan([runner.class_of(part)], prec=stp.FP32)
+    assert plan.describe()["classes"][0]["on_chip_B"]
+    plan.close()
+    check(dict(prec=stp.FP32), [part], gpu, True)
