@@ -41,7 +41,7 @@ inline KernelInfo mfma_kernel(int N, int physics) { return N == 7 ? mfma_kernel_
 KernelInfo mfma32_kernel_n7(int physics);
 
 // Generic classes with dense per-node B_d, no A and no point source (FP32 I/O and arithmetic), with B_d held
-// on chip through the Taylor loop: m = 4 or 9 at orders 7..9; fn == nullptr elsewhere.
+// on chip through the Taylor loop: m = 4 at orders 4..9, m = 9 at orders 7..9; fn == nullptr elsewhere.
 KernelInfo resident_kernel_f32(int N, int m);
 
 // Heterogeneous persistent kernel of one physics bucket (FP32 I/O, orders 1..7, 512 threads per workgroup).

@@ -291,7 +291,7 @@ def test_generic_dense_B_per_node(N, m, prec):
     check(W.generic_batch(N, m, 67, 700 + N * 20 + m), prec, label="generic")
 
 
-@pytest.mark.parametrize("N,m", [(7, 9), (8, 9), (9, 9), (7, 4), (8, 4), (9, 4)])
+@pytest.mark.parametrize("N,m", [(7, 9), (8, 9), (9, 9), (4, 4), (5, 4), (6, 4), (7, 4), (8, 4), (9, 4)])
 def test_generic_on_chip_B(N, m):
     """Generic classes with dense per-node B_d and no other terms take the kernel that holds B_d on chip
     (registers and LDS, the rest streamed): FP32 parity at every order and m it covers, odd element counts."""
@@ -305,7 +305,7 @@ def test_generic_on_chip_B(N, m):
 
 def test_generic_on_chip_B_favg_sum_and_routing():
     """The summed-flux output of the on-chip B_d kernel; classes with A, a point source, per-element coefficients,
-    FP64 accumulation or FP64 I/O, and orders below 7, keep the plain kernel."""
+    FP64 accumulation or FP64 I/O, m = 9 below order 7, m = 4 below order 4 and other m keep the plain kernel."""
     from paper_2003_12787_amd import runner
     check(W.generic_batch(7, 9, 23, 777), stp.FP32, favg_sum=True, label="generic-on-chip-B-favg-sum")
     for cls, prec, acc64 in [((7, 9, W.GENERIC, stp.A_PRESENT), stp.FP32, 0),
@@ -314,7 +314,8 @@ def test_generic_on_chip_B_favg_sum_and_routing():
                              ((8, 9, W.GENERIC, 0), stp.FP32, 8),
                              ((7, 9, W.GENERIC, 0), stp.FP64, 0),
                              ((6, 9, W.GENERIC, 0), stp.FP32, 0),
-                             ((6, 4, W.GENERIC, 0), stp.FP32, 0)]:
+                             ((3, 4, W.GENERIC, 0), stp.FP32, 0),
+                             ((8, 5, W.GENERIC, 0), stp.FP32, 0)]:
         plan = stp.Plan([cls], prec=prec, acc64_min_order=acc64)
         assert not plan.describe()["classes"][0]["on_chip_B"], cls
         plan.close()
@@ -424,7 +425,8 @@ def test_c4_heterogeneous_full_size_sampled():
 
 
 def mixed_batch(E_scale=1, seed=905):
-    """Every physics bucket of the persistent launch plus a high-order class that runs on its own."""
+    """Every physics bucket of the persistent launch, classes with their own launch (high orders, run-time m, and
+    generic m = 4 with B_d on chip) in one batch."""
     G = W.GENERIC
     parts = [
         W.elastic_batch(3, 40 * E_scale, seed + 1),
@@ -436,6 +438,7 @@ def mixed_batch(E_scale=1, seed=905):
         W.generic_batch(3, 12, 15 * E_scale, seed + 7),
         W.generic_batch(8, 4, 6 * E_scale, seed + 8),
         W.generic_batch(6, 4, 10 * E_scale, seed + 9),
+        W.generic_batch(3, 4, 12 * E_scale, seed + 11),
     ]
     parts[5].src = W.point_source(parts[5], seed + 10)
     from paper_2003_12787_amd import runner
@@ -646,8 +649,9 @@ def test_autotune_heterogeneous_grid_and_tiles(tmp_path, monkeypatch):
     assert d["hetero_grid_per_cu"] in (2, 4, 8)
     assert d["hetero_lds_budget"] in (48 * 1024, 80 * 1024, 128 * 1024)
     for c, (N, m, phys, flags) in zip(d["classes"], mb.classes):
-        # tiled: order <= 7, preset physics or a generic class with m = 4 or 9
-        assert c["tiled"] == (N <= 7 and (phys != stp.GENERIC or m in (4, 9))), c
+        # tiled: order <= 7, preset physics or a generic class with m = 4 or 9, unless B_d is kept on chip
+        assert c["tiled"] == (N <= 7 and (phys != stp.GENERIC or m in (4, 9)) and not c["on_chip_B"]), c
+        assert c["on_chip_B"] == (phys == stp.GENERIC and not flags and ((m == 4 and N >= 4) or (m == 9 and N >= 7)))
         if c["tiled"]:
             assert 1 <= c["elements_per_tile"] <= 512 // (N + 1) ** 3
     cache = json.load(open(tmp_path / "tune.json"))
