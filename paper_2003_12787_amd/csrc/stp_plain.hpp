@@ -336,6 +336,34 @@ struct Plain {
             }
 
             // time-averaged fluxes favg[d] = V_d(q-bar)
+            if constexpr (sizeof(T) == 8) {
+                // FP64: one direction at a time, stored from the registers (each thread its node's m words,
+                // consecutive threads consecutive nodes), so that the three directions' fluxes (3 m doubles) are
+                // never live together
+                const bool fsum = (a.flags & kFavgSum) != 0;
+                T* favg = static_cast<T*>(a.favg) + (fsum ? er.q : 3 * er.q);
+                T fv[MB];
+#pragma unroll
+                for (int s = 0; s < MB; ++s) fv[s] = 0;
+                auto put = [&](T* dst) {
+                    if (own) {
+#pragma unroll
+                        for (int s = 0; s < MB; ++s) {
+                            if (s >= m) break;
+                            dst[tid * m + s] = fv[s];
+                            fv[s] = 0;
+                        }
+                    }
+                };
+                accum_Vd<0>(a, er, Ds, pbuf, fbuf, coefs, mt, m, inv_h, tid, z, y, x, own, hasA, fv);
+                if (!fsum) put(favg);
+                accum_Vd<1>(a, er, Ds, pbuf, fbuf, coefs, mt, m, inv_h, tid, z, y, x, own, hasA, fv);
+                if (!fsum) put(favg + nn * m);
+                accum_Vd<2>(a, er, Ds, pbuf, fbuf, coefs, mt, m, inv_h, tid, z, y, x, own, hasA, fv);
+                put(fsum ? favg : favg + 2 * nn * m);
+                __syncthreads();  // the next element overwrites the tiles
+                return;
+            }
             T fv[3][MB];
 #pragma unroll
             for (int s = 0; s < MB; ++s) fv[0][s] = fv[1][s] = fv[2][s] = 0;
@@ -374,8 +402,17 @@ struct Plain {
     }
 };
 
+// Waves per SIMD the compiler must allow (registers <= 512 / waves). The FP64 elastic kernel at order 7 needs 189
+// registers unbounded, one 512-thread workgroup per CU; bounded to 128 (two workgroups) it spills 108 bytes per
+// lane and runs 30% faster. Elsewhere the compiler's choice.
+template <typename T, int N, int PHYS>
+struct PlainWaves {
+    static constexpr int v = (sizeof(T) == 8 && N == 7 && PHYS == kElastic) ? 4 : 1;
+};
+
 template <typename T, typename ACC, int N, int PHYS, int MB, bool EX>
-__global__ void __launch_bounds__(((N + 1) * (N + 1) * (N + 1) + 63) / 64 * 64) stp_plain_kernel(StpArgs a)
+__global__ void __launch_bounds__(((N + 1) * (N + 1) * (N + 1) + 63) / 64 * 64)
+    __attribute__((amdgpu_waves_per_eu(PlainWaves<T, N, PHYS>::v))) stp_plain_kernel(StpArgs a)
 {
     Plain<T, ACC, N, PHYS, MB, EX>::run(a);
 }
