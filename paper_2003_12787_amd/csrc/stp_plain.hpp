@@ -404,10 +404,11 @@ struct Plain {
 
 // Waves per SIMD the compiler must allow (registers <= 512 / waves). The FP64 elastic kernel at order 7 needs 189
 // registers unbounded, one 512-thread workgroup per CU; bounded to 128 (two workgroups) it spills 108 bytes per
-// lane and runs 30% faster. Elsewhere the compiler's choice.
+// lane and runs 30% faster (the curvilinear one, 231 registers unbounded, spills 272 bytes and runs 4% faster).
+// Elsewhere the compiler's choice.
 template <typename T, int N, int PHYS>
 struct PlainWaves {
-    static constexpr int v = (sizeof(T) == 8 && N == 7 && PHYS == kElastic) ? 4 : 1;
+    static constexpr int v = (sizeof(T) == 8 && N == 7 && (PHYS == kElastic || PHYS == kElasticCurv)) ? 4 : 1;
 };
 
 template <typename T, typename ACC, int N, int PHYS, int MB, bool EX>
