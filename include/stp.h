@@ -137,7 +137,11 @@ typedef struct {
 /* Kernel variants selectable through stp_plan_desc.variant (0 = library choice). */
 enum {
     STP_VARIANT_AUTO = 0,
-    STP_VARIANT_PLAIN = 1,   /* one element per workgroup, one thread per node, LDS-staged             */
+    STP_VARIANT_PLAIN = 1,   /* one element per workgroup, one thread per node, LDS-staged; generic
+                                classes with dense per-node B_d and neither A nor a point source, FP32
+                                arithmetic (m = 4 at N = 4..9, m = 9 at N = 7..9): the same algorithm
+                                with part or all of each node's B_d held in registers and LDS through
+                                the Taylor loop (Sec. IV-A's footprint argument on a CU)               */
     STP_VARIANT_FUSED = 2,   /* register-blocked lines, LDS transposes (acoustic and elastic presets,
                                 FP32 I/O without FP64 accumulation or point source, N <= 7)            */
     STP_VARIANT_MFMA = 3     /* matrix-core contractions, without FP64 accumulation or point source:
@@ -266,8 +270,9 @@ stp_status stp_correct(stp_plan_t plan, const stp_step* step, void* hip_stream);
 stp_status stp_face_params(stp_plan_t plan, int64_t nelem, const void* params, void* fparams, void* hip_stream);
 
 /* Describe the plan's choices as a JSON object into buf (NUL-terminated): per class the kernel variant,
- * whether it is tiled in the persistent heterogeneous launch and its elements per tile, FP64 accumulation;
- * the persistent grid per CU and the tile LDS budget. STP_E_INVAL for a NULL plan or buffer, or when len
+ * whether it is tiled in the persistent heterogeneous launch and its elements per tile, FP64 accumulation,
+ * and whether its kernel keeps B_d on chip ("on_chip_B"); the persistent grid per CU and the tile LDS
+ * budget. STP_E_INVAL for a NULL plan or buffer, or when len
  * is too small (the message states the size needed). */
 stp_status stp_plan_describe(stp_plan_t plan, char* buf, size_t len);
 
