@@ -111,6 +111,14 @@ def test_elastic_per_element_material_and_favg_sum():
     check(b, stp.FP64, favg_sum=True, label="elastic-favg-sum")
 
 
+def test_fp64_order7_register_bound_favg_sum():
+    """The FP64 elastic order-7 kernel runs under a 128-register bound with favg stored one direction at a time:
+    per-node material, separate and summed fluxes, an element count that is not a multiple of the grid."""
+    b = W.elastic_batch(7, 45, 23)
+    check(b, stp.FP64, label="fp64-n7")
+    check(b, stp.FP64, favg_sum=True, label="fp64-n7-favg-sum")
+
+
 def test_c3_full_size_sampled():
     b = W.c3_elastic_n7()
     check(b, stp.FP32, sample=spread(b.nelem, 40), label="C3-full")
