@@ -92,8 +92,6 @@ struct Res {
         bool own[K];
     };
 
-    // r[k] += V_D(u) at the thread's nodes: -(1/h) sum_q B_D[:, q] (D x_D u)_q, column by column. bg[k] points
-    // at word 0 of node k's B_d in memory (streamed words), bres at the LDS-resident words.
     // Word e of the thread's node k: registers, LDS or memory
     __device__ static inline float word(int e, int k, const float (&breg)[K][KR > 0 ? KR : 1], const float* bres,
                                         const float* const (&bg)[K], const Nodes& nd)
@@ -113,7 +111,7 @@ struct Res {
         // column q: r[k][s] += B_D[s][q] (-(1/h) g_q) in the order s = 0..m-1, then the accumulators are pinned:
         // they are stored only for owned nodes, and without the pin the compiler sinks the column's arithmetic
         // into that conditional store, past the step's barrier, and keeps every loaded word of the step live
-        auto column = [&](int q, const float (&b)[K][MB], const float (&gq)[K]) {
+        auto column = [&](const float (&b)[K][MB], const float (&gq)[K]) {
 #pragma unroll
             for (int s = 0; s < m; ++s)
 #pragma unroll
@@ -134,7 +132,7 @@ struct Res {
 #pragma unroll
                 for (int k = 0; k < K; ++k)
                     g[k] = ninv_h * dline<D>(Ds, u, nd.node[k], nd.z[k], nd.y[k], nd.x[k], q);
-                column(q, b, g);
+                column(b, g);
                 // one column's loads and derivative at a time: bounds the registers they hold
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -155,7 +153,7 @@ struct Res {
                         for (int k = 0; k < K; ++k) b[k][s] = word(D * m * m + q * m + s, k, breg, bres, bg, nd);
 #pragma unroll
                     for (int k = 0; k < K; ++k) g[k] = ninv_h * g4[k][qq];
-                    column(q, b, g);
+                    column(b, g);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
