@@ -38,6 +38,17 @@ struct Plain {
     // B_d loads after each direction's LDS work; the column form runs their classes about twice as fast. At
     // orders 7 and below the row form is as fast or faster.
     static constexpr bool kColumnNcp = !kPreset && N >= 8;
+    // Presets at orders 8 and 9 (FP32 I/O): the tile's node stride is padded to a multiple of four words, so the
+    // quantities a direction reads come in 16-byte LDS reads (the sums keep their order: the same bits)
+    static constexpr bool kGroupLds = kPreset && N >= 8 && sizeof(T) == 4;
+    static constexpr int MPS = kGroupLds ? (MB + 3) / 4 * 4 : 1;
+    __host__ __device__ static constexpr int mp(int m) { return kGroupLds ? MPS : m; }
+    __host__ __device__ static constexpr bool group_needed(int D, int g)
+    {
+        for (int s = 4 * g; s < 4 * g + 4 && s < MB; ++s)
+            if (PhysTraits<PHYS == kGeneric ? kElastic : PHYS>::needs(D, s)) return true;
+        return false;
+    }
 
     // Byte offsets of the LDS regions, each 16-byte aligned; `total` is the dynamic LDS size.
     struct Layout {
@@ -49,7 +60,7 @@ struct Plain {
         Layout L{};
         L.coefs = al16(sizeof(T) * (n * n + 2 * n));
         L.pbuf = al16(L.coefs + (kPreset ? 0 : sizeof(T) * 6 * MB * MB));
-        L.fbuf = al16(L.pbuf + sizeof(T) * nn * m);
+        L.fbuf = al16(L.pbuf + sizeof(T) * nn * mp(m));
         L.qacc = al16(L.fbuf + (hasA ? sizeof(T) * nn * m : 0));
         L.total = L.qacc + (std::is_same<ACC, T>::value ? 0 : sizeof(ACC) * nn * m);
         return L;
@@ -138,9 +149,34 @@ struct Plain {
             return;
         }
         T g[MB];
+        if constexpr (kGroupLds) {
+            // every quantity B_d reads, from 16-byte reads of the line's nodes (sums in dline's order)
+            const int kd = D == 0 ? x : (D == 1 ? y : z);
+            const int base = D == 0 ? tid - x : (D == 1 ? tid - y * n : tid - z * n2);
+            constexpr int stride = D == 0 ? 1 : (D == 1 ? n : n2);
+#pragma unroll
+            for (int s = 0; s < MB; ++s) g[s] = 0;
+#pragma unroll
+            for (int j = 0; j < n; ++j) {
+                const T dj = Ds[kd * n + j];
+#pragma unroll
+                for (int gr = 0; gr < MPS / 4; ++gr) {
+                    if (!group_needed(D, gr)) continue;
+                    const float4 v = *reinterpret_cast<const float4*>(u + (base + j * stride) * MPS + 4 * gr);
+                    const T vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int s = 4 * gr + t;
+                        if (s < MB && PhysTraits<PHYS>::needs(D, s)) g[s] = fma(dj, vv[t], g[s]);
+                    }
+                }
+            }
+        }
 #pragma unroll
         for (int s = 0; s < MB; ++s) {
-            if constexpr (kPreset) {
+            if constexpr (kGroupLds) {
+                break;
+            } else if constexpr (kPreset) {
                 g[s] = PhysTraits<PHYS>::needs(D, s) ? dline<D>(Ds, u, MB, tid, z, y, x, s) : T(0);
             } else {
                 g[s] = s < m ? dline<D>(Ds, u, m, tid, z, y, x, s) : T(0);
@@ -214,7 +250,7 @@ struct Plain {
             const T inv_h = (T)(1.0 / er.h);
             const T* Q = static_cast<const T*>(a.Q) + er.q;
             if (valid)
-                for (int i = tid; i < nn * m; i += NT) pbuf[i] = Q[i];
+                for (int i = tid; i < nn * m; i += NT) pbuf[(i / m) * mp(m) + i % m] = Q[i];
             Material<T, PHYS> mt;
             if constexpr (kPreset) {
                 constexpr int np = PhysTraits<PHYS>::np;
@@ -242,7 +278,7 @@ struct Plain {
             ACC qb[MB];
             T r[MB];
 #pragma unroll
-            for (int s = 0; s < MB; ++s) qb[s] = (own && s < m) ? (ACC)pbuf[tid * m + s] : ACC(0);
+            for (int s = 0; s < MB; ++s) qb[s] = (own && s < m) ? (ACC)pbuf[tid * mp(m) + s] : ACC(0);
             ACC w = 1;
             const ACC dt = (ACC)er.dt;
             for (int o = 1; o <= N; ++o) {
@@ -262,7 +298,7 @@ struct Plain {
 #pragma unroll
                     for (int s = 0; s < MB; ++s) {
                         if (s >= m) break;
-                        pbuf[tid * m + s] = r[s];
+                        pbuf[tid * mp(m) + s] = r[s];
                         qb[s] = fma(w, (ACC)r[s], qb[s]);
                     }
                 }
@@ -274,14 +310,14 @@ struct Plain {
 #pragma unroll
                 for (int s = 0; s < MB; ++s) {
                     if (s >= m) break;
-                    pbuf[tid * m + s] = (T)qb[s];
+                    pbuf[tid * mp(m) + s] = (T)qb[s];
                     if constexpr (!std::is_same<ACC, T>::value) qacc[tid * m + s] = qb[s];
                 }
             }
             __syncthreads();
             T* qavg = static_cast<T*>(a.qavg) + er.q;
             if (valid)
-                for (int i = tid; i < nn * m; i += NT) qavg[i] = pbuf[i];
+                for (int i = tid; i < nn * m; i += NT) qavg[i] = pbuf[(i / m) * mp(m) + i % m];
 
             // faces of q-bar, in the accumulator precision
             T* qface = static_cast<T*>(a.qface) + er.face;
@@ -295,7 +331,7 @@ struct Plain {
                     const int node = axis == 0 ? (aa * n + b) * n + j
                                                : (axis == 1 ? (aa * n + j) * n + b : (j * n + aa) * n + b);
                     if constexpr (std::is_same<ACC, T>::value)
-                        acc = fma((ACC)ev[j], pbuf[node * m + s], acc);
+                        acc = fma((ACC)ev[j], pbuf[node * mp(m) + s], acc);
                     else
                         acc = fma((ACC)ev[j], qacc[node * m + s], acc);
                 }
@@ -380,12 +416,12 @@ struct Plain {
 #pragma unroll
                     for (int s = 0; s < MB; ++s) {
                         if (s >= m) break;
-                        pbuf[tid * m + s] = fsum ? fv[0][s] + fv[1][s] + fv[2][s] : fv[d][s];
+                        pbuf[tid * mp(m) + s] = fsum ? fv[0][s] + fv[1][s] + fv[2][s] : fv[d][s];
                     }
                 }
                 __syncthreads();
                 if (valid)
-                    for (int i = tid; i < nn * m; i += NT) favg[d * nn * m + i] = pbuf[i];
+                    for (int i = tid; i < nn * m; i += NT) favg[d * nn * m + i] = pbuf[(i / m) * mp(m) + i % m];
                 __syncthreads();
             }
         }
