@@ -38,9 +38,13 @@ struct Plain {
     // B_d loads after each direction's LDS work; the column form runs their classes about twice as fast. At
     // orders 7 and below the row form is as fast or faster.
     static constexpr bool kColumnNcp = !kPreset && N >= 8;
-    // Presets at orders 8 and 9 (FP32 I/O): the tile's node stride is padded to a multiple of four words, so the
-    // quantities a direction reads come in 16-byte LDS reads (the sums keep their order: the same bits)
-    static constexpr bool kGroupLds = kPreset && N >= 8 && sizeof(T) == 4;
+    // Presets with FP32 I/O: the tile's node stride is padded to a multiple of four words, so the quantities a
+    // direction reads come in 16-byte LDS reads (the sums keep their order: the same bits). Taken where it
+    // measured faster: acoustic (one group, 0.20 -> 0.16 ms for 4096 elements at order 7), curvilinear elastic
+    // (every quantity is read, 3 groups for 9), and Cartesian elastic at orders 8 and 9 (10-20%; one workgroup
+    // per CU, latency-bound). Below order 8 the elastic kernel reads 12 words for the 6 it needs at more waves
+    // per CU, and order 7 measured 13% slower.
+    static constexpr bool kGroupLds = kPreset && sizeof(T) == 4 && (PHYS != kElastic || N >= 8);
     static constexpr int MPS = kGroupLds ? (MB + 3) / 4 * 4 : 1;
     __host__ __device__ static constexpr int mp(int m) { return kGroupLds ? MPS : m; }
     __host__ __device__ static constexpr bool group_needed(int D, int g)
