@@ -38,18 +38,21 @@ struct Plain {
     // B_d loads after each direction's LDS work; the column form runs their classes about twice as fast. At
     // orders 7 and below the row form is as fast or faster.
     static constexpr bool kColumnNcp = !kPreset && N >= 8;
-    // Presets with FP32 I/O: the tile's node stride is padded to a multiple of four words, so the quantities a
-    // direction reads come in 16-byte LDS reads (the sums keep their order: the same bits). Taken where it
-    // measured faster: acoustic (one group, 0.20 -> 0.16 ms for 4096 elements at order 7), curvilinear elastic
-    // (every quantity is read, 3 groups for 9), and Cartesian elastic at orders 8 and 9 (10-20%; one workgroup
-    // per CU, latency-bound). Below order 8 the elastic kernel reads 12 words for the 6 it needs at more waves
-    // per CU, and order 7 measured 13% slower.
-    static constexpr bool kGroupLds = kPreset && sizeof(T) == 4 && (PHYS != kElastic || N >= 8);
-    static constexpr int MPS = kGroupLds ? (MB + 3) / 4 * 4 : 1;
+    // Presets: the tile's node stride is padded to a multiple of 16 bytes, so the quantities a direction reads
+    // come in 16-byte LDS reads (four floats or two doubles; the sums keep their order: the same bits). Taken
+    // where it measured faster. FP32: acoustic (one group, 0.20 -> 0.16 ms for 4096 elements at order 7),
+    // curvilinear elastic (every quantity is read, 3 groups for 9) and Cartesian elastic at orders 8 and 9
+    // (10-20%; one workgroup per CU, latency-bound); below order 8 the elastic kernel reads 12 words for the 6 it
+    // needs at more waves per CU, and order 7 measured 13% slower. FP64: curvilinear elastic (order 7 10.99 ->
+    // 10.50 ms); the Cartesian elastic kernel at order 7 measured 6.49 -> 8.15 ms, acoustic at order 5 the same.
+    static constexpr bool kGroupLds =
+        kPreset && (sizeof(T) == 4 ? (PHYS != kElastic || N >= 8) : PHYS == kElasticCurv);
+    static constexpr int GS = 16 / (int)sizeof(T);  // values per 16-byte read
+    static constexpr int MPS = kGroupLds ? (MB + GS - 1) / GS * GS : 1;
     __host__ __device__ static constexpr int mp(int m) { return kGroupLds ? MPS : m; }
     __host__ __device__ static constexpr bool group_needed(int D, int g)
     {
-        for (int s = 4 * g; s < 4 * g + 4 && s < MB; ++s)
+        for (int s = GS * g; s < GS * g + GS && s < MB; ++s)
             if (PhysTraits<PHYS == kGeneric ? kElastic : PHYS>::needs(D, s)) return true;
         return false;
     }
@@ -164,13 +167,19 @@ struct Plain {
             for (int j = 0; j < n; ++j) {
                 const T dj = Ds[kd * n + j];
 #pragma unroll
-                for (int gr = 0; gr < MPS / 4; ++gr) {
+                for (int gr = 0; gr < MPS / GS; ++gr) {
                     if (!group_needed(D, gr)) continue;
-                    const float4 v = *reinterpret_cast<const float4*>(u + (base + j * stride) * MPS + 4 * gr);
-                    const T vv[4] = {v.x, v.y, v.z, v.w};
+                    T vv[GS];
+                    if constexpr (GS == 4) {
+                        const float4 v = *reinterpret_cast<const float4*>(u + (base + j * stride) * MPS + 4 * gr);
+                        vv[0] = v.x; vv[1] = v.y; vv[2] = v.z; vv[3] = v.w;
+                    } else {
+                        const double2 v = *reinterpret_cast<const double2*>(u + (base + j * stride) * MPS + 2 * gr);
+                        vv[0] = v.x; vv[1] = v.y;
+                    }
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const int s = 4 * gr + t;
+                    for (int t = 0; t < GS; ++t) {
+                        const int s = GS * gr + t;
                         if (s < MB && PhysTraits<PHYS>::needs(D, s)) g[s] = fma(dj, vv[t], g[s]);
                     }
                 }
