@@ -8,7 +8,8 @@
 // from the queue with an atomic counter, so the expensive orders start first and cheap ones fill in behind;
 // every tile dispatches on its order to the element routine of the plain kernel. Everything is launched on
 // the caller's stream without host synchronisation or memsets, so a batch can be captured into a HIP graph.
-// Covers orders 1..7 (n^3 <= 512); higher orders run as per-class launches of the plain kernel.
+// Covers orders 1..7 (n^3 <= 512); higher orders, and the generic classes whose kernel keeps B_d on chip, run as
+// per-class launches of their own kernel.
 #pragma once
 #include <type_traits>
 
