@@ -481,8 +481,20 @@ struct Fused {
     }
 };
 
+// Waves per SIMD the register allocation must allow. The elastic kernel at N = 5, 6 needs 282 and 315
+// registers (VGPRs plus AGPRs), one wave per SIMD; bounded to two waves it spills 92 resp. 128 bytes per lane
+// and runs 22% faster, with the same results. Acoustic N = 6 (179 registers) bounded to three waves spills
+// 44 bytes and gains 3%. Tighter bounds elsewhere measured slower (elastic N = 7 at two waves: 536 bytes of
+// spills, 1.7x the time; elastic N = 3, 4 and acoustic N = 7 at three waves: 1.2-1.5x), so those keep the
+// compiler's choice.
 template <typename T, int N, int PHYS>
-__global__ void __launch_bounds__(wg_size(N + 1)) stp_fused_kernel(StpArgs a)
+struct FusedWaves {
+    static constexpr int v = PHYS == kElastic ? ((N == 5 || N == 6) ? 2 : 1) : (PHYS == kAcoustic && N == 6) ? 3 : 1;
+};
+
+template <typename T, int N, int PHYS>
+__global__ void __launch_bounds__(wg_size(N + 1)) __attribute__((amdgpu_waves_per_eu(FusedWaves<T, N, PHYS>::v)))
+stp_fused_kernel(StpArgs a)
 {
     Fused<T, N, PHYS>::run(a);
 }
