@@ -451,18 +451,33 @@ struct Plain {
     }
 };
 
-// Waves per SIMD the compiler must allow (registers <= 512 / waves). The FP64 elastic kernel at order 7 needs 189
-// registers unbounded, one 512-thread workgroup per CU; bounded to 128 (two workgroups) it spills 108 bytes per
-// lane and runs 30% faster (the curvilinear one, 231 registers unbounded, spills 272 bytes and runs 4% faster).
-// Elsewhere the compiler's choice.
-template <typename T, int N, int PHYS>
+// Waves per SIMD the compiler must allow (registers <= 512 / waves), so that one more workgroup fits a CU. Each
+// bound below measured faster with the same bits (batches of about 2 GB of traffic):
+//   - FP64 elastic, order 7: 189 registers, one 512-thread workgroup per CU; at 128 (two) it spills 108 bytes per
+//     lane and runs 30% faster. Curvilinear: 231 registers, 272 bytes of spills, 4% faster.
+//   - FP32 elastic, order 8: 114 registers, one 729-thread workgroup; at 80 (two) 28 bytes of spills, 22% faster.
+//   - FP32 acoustic, order 9: 89 registers, one 1000-thread workgroup; at 64 (two) 52 bytes, 21% faster.
+//   - FP32 I/O with FP64 accumulation, elastic order 6: at 96 registers (three 343-thread workgroups instead of
+//     two) 16% faster.
+// The same bound made FP32 elastic order 7 4% slower and, with FP64 accumulation, elastic orders 7 and 8 and
+// curvilinear order 7 10-50% slower. With FP64 accumulation, acoustic orders 8 and 9 ran 20-27% faster bounded
+// to two workgroups per CU on whole-GPU batches, but the serving path's mixed batches launch these classes with
+// a few dozen elements, where the longer workgroups cost 4% of its batch rate; they, and the rest, keep the
+// compiler's choice.
+template <typename T, typename ACC, int N, int PHYS>
 struct PlainWaves {
-    static constexpr int v = (sizeof(T) == 8 && N == 7 && (PHYS == kElastic || PHYS == kElasticCurv)) ? 4 : 1;
+    static constexpr bool f32 = sizeof(T) == 4 && sizeof(ACC) == 4;  // FP32 I/O and accumulation
+    static constexpr bool a64 = sizeof(T) == 4 && sizeof(ACC) == 8;  // FP32 I/O, FP64 accumulation
+    static constexpr int v = (sizeof(T) == 8 && N == 7 && (PHYS == kElastic || PHYS == kElasticCurv)) ? 4
+                             : (f32 && PHYS == kElastic && N == 8) ? 6
+                             : (f32 && PHYS == kAcoustic && N == 9) ? 8
+                             : (a64 && PHYS == kElastic && N == 6) ? 5
+                                                                    : 1;
 };
 
 template <typename T, typename ACC, int N, int PHYS, int MB, bool EX>
 __global__ void __launch_bounds__(((N + 1) * (N + 1) * (N + 1) + 63) / 64 * 64)
-    __attribute__((amdgpu_waves_per_eu(PlainWaves<T, N, PHYS>::v))) stp_plain_kernel(StpArgs a)
+    __attribute__((amdgpu_waves_per_eu(PlainWaves<T, ACC, N, PHYS>::v))) stp_plain_kernel(StpArgs a)
 {
     Plain<T, ACC, N, PHYS, MB, EX>::run(a);
 }
