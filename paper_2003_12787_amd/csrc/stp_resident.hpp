@@ -26,7 +26,7 @@
 namespace stp {
 namespace resident {
 
-template <int N, int MB, int NT, int K, int KR, int KL, int G>
+template <int N, int MB, int NT, int K, int KR, int KL, int G, bool PF>
 struct Res {
     static constexpr int n = N + 1;
     static constexpr int n2 = n * n;
@@ -120,7 +120,38 @@ struct Res {
                     asm volatile("" : "+v"(r[k][s]));
                 }
         };
-        if constexpr (G == 1) {
+        if constexpr (G == 1 && PF) {
+            // PF: column q + 1's words are loaded before column q's derivative and FMAs, so that two columns of
+            // streamed loads are in flight
+            float b[K][MB];
+#pragma unroll
+            for (int s = 0; s < m; ++s)
+#pragma unroll
+                for (int k = 0; k < K; ++k) b[k][s] = word(D * m * m + s, k, breg, bres, bg, nd);
+#pragma unroll
+            for (int q = 0; q < m; ++q) {
+                float bn[K][MB];
+                if (q + 1 < m) {
+#pragma unroll
+                    for (int s = 0; s < m; ++s)
+#pragma unroll
+                        for (int k = 0; k < K; ++k)
+                            bn[k][s] = word(D * m * m + (q + 1) * m + s, k, breg, bres, bg, nd);
+                }
+                float g[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    g[k] = ninv_h * dline<D>(Ds, u, nd.node[k], nd.z[k], nd.y[k], nd.x[k], q);
+                column(b, g);
+                __builtin_amdgcn_sched_barrier(0);
+                if (q + 1 < m) {
+#pragma unroll
+                    for (int s = 0; s < m; ++s)
+#pragma unroll
+                        for (int k = 0; k < K; ++k) b[k][s] = bn[k][s];
+                }
+            }
+        } else if constexpr (G == 1) {
 #pragma unroll
             for (int q = 0; q < m; ++q) {
                 float b[K][MB];
@@ -299,25 +330,25 @@ struct Res {
     }
 };
 
-template <int N, int MB, int NT, int K, int KR, int KL, int G>
+template <int N, int MB, int NT, int K, int KR, int KL, int G, bool PF>
 __global__ void __launch_bounds__(NT) stp_resident_kernel(StpArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     for (int64_t it = blockIdx.x;; it += gridDim.x) {
         ElemRef er;
         if (!elem_ref(a, it, er)) break;
-        Res<N, MB, NT, K, KR, KL, G>::element(a, er, smem, threadIdx.x);
+        Res<N, MB, NT, K, KR, KL, G, PF>::element(a, er, smem, threadIdx.x);
     }
 }
 
-template <int N, int MB, int NT, int K, int KR, int KL, int G = 1>
+template <int N, int MB, int NT, int K, int KR, int KL, int G = 1, bool PF = false>
 KernelInfo resident_info()
 {
     KernelInfo ki;
-    ki.fn = reinterpret_cast<const void*>(&stp_resident_kernel<N, MB, NT, K, KR, KL, G>);
+    ki.fn = reinterpret_cast<const void*>(&stp_resident_kernel<N, MB, NT, K, KR, KL, G, PF>);
     ki.block = NT;
     ki.mb = MB;
-    ki.lds = [](int, bool) -> size_t { return Res<N, MB, NT, K, KR, KL, G>::kLds; };
+    ki.lds = [](int, bool) -> size_t { return Res<N, MB, NT, K, KR, KL, G, PF>::kLds; };
     return ki;
 }
 
