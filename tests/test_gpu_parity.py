@@ -105,6 +105,16 @@ def test_acoustic_orders_per_node(N):
     check(W.acoustic_batch(N, 65, 600 + N), stp.FP64, label="acoustic-per-node")
 
 
+@pytest.mark.parametrize("phys,N,acc64", [("elastic", 8, 0), ("acoustic", 9, 0), ("elastic", 6, 6)])
+def test_plain_register_bounded_instances(phys, N, acc64):
+    """The plain instances compiled under a waves-per-SIMD bound (FP32 elastic N = 8, FP32 acoustic N = 9, FP32
+    I/O with FP64 accumulation at elastic N = 6), with per-node and per-element material and favg summed."""
+    gen = W.elastic_batch if phys == "elastic" else W.acoustic_batch
+    check(gen(N, 45, 640 + N), stp.FP32, variant=stp.VARIANT_PLAIN, acc64=acc64, label=f"plain-bounded-{phys}")
+    check(gen(N, 30, 650 + N, per_node=False), stp.FP32, variant=stp.VARIANT_PLAIN, acc64=acc64, favg_sum=True,
+          label=f"plain-bounded-{phys}-fsum")
+
+
 def test_elastic_per_element_material_and_favg_sum():
     b = W.elastic_batch(5, 130, 21, per_node=False)
     check(b, stp.FP32, label="elastic-per-element")
